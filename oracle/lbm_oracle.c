@@ -1,0 +1,799 @@
+/*
+ * Plain CPU reference ("oracle") for the LBM hot path of arXiv 2512.12213.
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU
+ * baseline of the benchmark; never by the product library.
+ *
+ * Straightforward two-array push scheme in double precision (or double complex
+ * for complex-step derivatives), one node at a time, in the order of the
+ * paper's Section 2:
+ *   moments -> model velocities -> (Smagorinsky tau) -> equilibrium (Eq. 1 /
+ *   Eq. 10) -> force term (Section 2 / Eq. 3) -> relaxation (Eq. 2) ->
+ *   propagation with halfway bounce-back -> momentum exchange (Eq. 25).
+ * Distributions are held as deviations d = f - w*rho0 (a change of variable
+ * only; it keeps FP64 round-off small when f is close to w*rho0).
+ *
+ * Every function is a direct transcription of the formula it cites; there is
+ * no blocking, fusion or reordering beyond per-row partial sums that make the
+ * reductions independent of the thread count.
+ *
+ * Parity status: pinned by the closed-form and invariant tests in the test
+ * suite (moment identities, model equivalences, exact-bounce-back channel
+ * profiles, the 1D class-sum recurrence, momentum and mass balances, Maxwell
+ * per-link sums, Hartmann channel, Smagorinsky fixed point, finite differences
+ * for the complex-step build).
+ */
+#include "lbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifdef ORC_COMPLEX
+#include <complex.h>
+typedef double complex real;
+#define RSQRT(x) csqrt(x)
+#define RE(x) creal(x)
+#define IM(x) cimag(x)
+#define MK(re, im) ((re) + (im) * I)
+#else
+typedef double real;
+#define RSQRT(x) sqrt(x)
+#define RE(x) (x)
+#define IM(x) (0.0 * (x))
+#define MK(re, im) (re)
+#endif
+
+#define MAXG 16
+#define NREC 24
+
+struct orc {
+  int lat, D, Q;
+  int nx, ny, nz;
+  long N;
+  double tau, dx, dt, c;
+  int model;
+  double rho0;
+  int e[19][3]; /* unit lattice vectors; the lattice velocity is c * e */
+  double w[19];
+  int opp[19];
+  int wall[3][2];       /* group of the plane wall at the low / high end of an axis; -1 periodic */
+  unsigned char* solid; /* per node: 0 fluid, 1 + group for a solid node */
+  int G;                /* number of link groups in use */
+  real uw[MAXG][3];
+  real a[3];
+  real* afield; /* [3][N] or NULL */
+  double cs;
+  int artefact;
+  int mhd;
+  double B0[3], mu, tau_m;
+  real *g, *gn; /* induction distributions [7][3][N] */
+  real *d, *dn; /* [Q][N] deviations */
+  /* records of the last executed step */
+  real wf[MAXG][3][3]; /* per group: raw, momentum-flux correction, Maxwell correction */
+  real M_t, P_t[3], rho_a[3];
+  long step;
+  int have_step;
+};
+
+/* ---------------------------------------------------------------------------
+ * Lattices (Section 2; velocity sets and weights of Qian, d'Humieres and
+ * Lallemand 1992).  Direction order is the documented state-exchange order.
+ * ------------------------------------------------------------------------- */
+static void set_lattice(orc* o) {
+  static const int e9[9][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
+  static const int e19[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                                 {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                                 {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                                 {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  memset(o->e, 0, sizeof(o->e));
+  if (o->lat == 0) {
+    o->D = 2;
+    o->Q = 9;
+    for (int q = 0; q < 9; ++q) {
+      o->e[q][0] = e9[q][0];
+      o->e[q][1] = e9[q][1];
+      int s = abs(e9[q][0]) + abs(e9[q][1]);
+      o->w[q] = s == 0 ? 4.0 / 9.0 : (s == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+    }
+  } else {
+    o->D = 3;
+    o->Q = 19;
+    for (int q = 0; q < 19; ++q) {
+      int s = 0;
+      for (int k = 0; k < 3; ++k) {
+        o->e[q][k] = e19[q][k];
+        s += abs(e19[q][k]);
+      }
+      o->w[q] = s == 0 ? 1.0 / 3.0 : (s == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+    }
+  }
+  for (int q = 0; q < o->Q; ++q)
+    for (int p = 0; p < o->Q; ++p)
+      if (o->e[p][0] == -o->e[q][0] && o->e[p][1] == -o->e[q][1] && o->e[p][2] == -o->e[q][2]) o->opp[q] = p;
+}
+
+/* D3Q7 lattice of the induction solver: weights 1/4 (rest) and 1/8, so that
+ * sum_k W_k e_k e_k = theta c^2 I with theta = 1/4. */
+static const int e7[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+static const int opp7[7] = {0, 2, 1, 4, 3, 6, 5};
+static double w7(int k) { return k == 0 ? 0.25 : 0.125; }
+#define THETA7 0.25
+
+orc* orc_create(int lattice, int nx, int ny, int nz, double tau, double dx, double dt, int model) {
+  if (lattice != 0 && lattice != 1) return NULL;
+  if (nx < 1 || ny < 1 || nz < 1) return NULL;
+  if (lattice == 0 && nz != 1) return NULL;
+  if (!(tau > 0.5) || !(dx > 0) || !(dt > 0)) return NULL;
+  if (model < 0 || model > 6) return NULL;
+  orc* o = (orc*)calloc(1, sizeof(orc));
+  o->lat = lattice;
+  set_lattice(o);
+  o->nx = nx;
+  o->ny = ny;
+  o->nz = nz;
+  o->N = (long)nx * ny * nz;
+  o->tau = tau;
+  o->dx = dx;
+  o->dt = dt;
+  o->c = dx / dt;
+  o->model = model;
+  o->rho0 = 1.0;
+  for (int k = 0; k < 3; ++k) o->wall[k][0] = o->wall[k][1] = -1;
+  o->G = 1;
+  o->solid = (unsigned char*)calloc(o->N, 1);
+  o->d = (real*)calloc((size_t)o->Q * o->N, sizeof(real));
+  o->dn = (real*)calloc((size_t)o->Q * o->N, sizeof(real));
+  return o;
+}
+
+void orc_destroy(orc* o) {
+  if (!o) return;
+  free(o->solid);
+  free(o->d);
+  free(o->dn);
+  free(o->afield);
+  free(o->g);
+  free(o->gn);
+  free(o);
+}
+
+int orc_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
+int orc_set_rho0(orc* o, double rho0) {
+  if (!(rho0 > 0)) return -1;
+  o->rho0 = rho0;
+  return 0;
+}
+
+static void note_group(orc* o, int g) {
+  if (g + 1 > o->G) o->G = g + 1;
+}
+
+int orc_set_walls(orc* o, int axis, int glo, int ghi) {
+  if (axis < 0 || axis >= o->D) return -1;
+  if (glo >= MAXG || ghi >= MAXG || glo < -1 || ghi < -1) return -1;
+  o->wall[axis][0] = glo;
+  o->wall[axis][1] = ghi;
+  if (glo >= 0) note_group(o, glo);
+  if (ghi >= 0) note_group(o, ghi);
+  return 0;
+}
+
+int orc_set_solid(orc* o, const unsigned char* mask, int group) {
+  if (group < 0 || group >= MAXG) return -1;
+  for (long i = 0; i < o->N; ++i)
+    if (mask[i]) o->solid[i] = (unsigned char)(1 + group);
+  note_group(o, group);
+  return 0;
+}
+
+int orc_set_wall_velocity(orc* o, int group, const double* u, const double* u_im) {
+  if (group < 0 || group >= MAXG) return -1;
+  for (int k = 0; k < 3; ++k) o->uw[group][k] = MK(u[k], u_im ? u_im[k] : 0.0);
+  note_group(o, group);
+  return 0;
+}
+
+int orc_set_body_force(orc* o, const double* a, const double* a_im) {
+  for (int k = 0; k < 3; ++k) o->a[k] = MK(a[k], a_im ? a_im[k] : 0.0);
+  return 0;
+}
+
+int orc_set_body_force_field(orc* o, const double* a, const double* a_im) {
+  free(o->afield);
+  o->afield = NULL;
+  if (!a) return 0;
+  o->afield = (real*)malloc(sizeof(real) * 3 * o->N);
+  for (long i = 0; i < 3 * o->N; ++i) o->afield[i] = MK(a[i], a_im ? a_im[i] : 0.0);
+  return 0;
+}
+
+int orc_set_les(orc* o, double cs) {
+  if (cs < 0) return -1;
+  o->cs = cs;
+  return 0;
+}
+
+int orc_set_artefact(orc* o, int on) {
+  o->artefact = on ? 1 : 0;
+  return 0;
+}
+
+int orc_set_mhd(orc* o, double B0x, double B0y, double B0z, double mu, double tau_m) {
+  if (o->lat != 1 || !(mu > 0) || !(tau_m > 0.5)) return -1;
+  o->mhd = 1;
+  o->B0[0] = B0x;
+  o->B0[1] = B0y;
+  o->B0[2] = B0z;
+  o->mu = mu;
+  o->tau_m = tau_m;
+  free(o->g);
+  free(o->gn);
+  o->g = (real*)calloc((size_t)21 * o->N, sizeof(real));
+  o->gn = (real*)calloc((size_t)21 * o->N, sizeof(real));
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Local formulas
+ * ------------------------------------------------------------------------- */
+static real edot(const orc* o, int q, const real* v) {
+  real s = 0;
+  for (int k = 0; k < o->D; ++k) s += (real)(o->c * o->e[q][k]) * v[k];
+  return s;
+}
+
+/* Equilibrium of Eq. (1), as a deviation from w*rho0. */
+static real feq_dev(const orc* o, int q, real rho, const real* u) {
+  const double c2 = o->c * o->c;
+  real eu = edot(o, q, u);
+  real uu = 0;
+  for (int k = 0; k < o->D; ++k) uu += u[k] * u[k];
+  return o->w[q] * ((rho - o->rho0) + rho * (3.0 * eu / c2 + 4.5 * eu * eu / (c2 * c2) - 1.5 * uu / c2));
+}
+
+/* Magnetic part of the MHD equilibrium, Eq. (10) (three-dimensional form). */
+static real phi_mhd(const orc* o, int q, const real* B) {
+  const double c2 = o->c * o->c;
+  real ee = 0, eB = 0, B2 = 0;
+  for (int k = 0; k < 3; ++k) {
+    ee += (real)(c2 * o->e[q][k] * o->e[q][k]);
+    eB += (real)(o->c * o->e[q][k]) * B[k];
+    B2 += B[k] * B[k];
+  }
+  return 9.0 * o->w[q] / (2.0 * c2 * c2 * o->mu) * (0.5 * B2 * ee - eB * eB - c2 * B2 / 6.0);
+}
+
+/* Maxwell stress L_ij = (B^2 delta_ij / 2 - B_i B_j) / mu (after Eq. 11). */
+static real maxwell(const orc* o, int i, int j, const real* B) {
+  real B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+  return ((i == j ? 0.5 * B2 : 0.0) - B[i] * B[j]) / o->mu;
+}
+
+static real body_force(const orc* o, long idx, int k) {
+  if (o->afield) return o->afield[(long)k * o->N + idx];
+  return o->a[k];
+}
+
+/* Per-node state needed by the collision and by the diagnostics. */
+typedef struct {
+  real rho, u[3], v[3], a[3], ueq[3], uF[3], B[3];
+  real C;      /* force-term coefficient */
+  real tau;    /* relaxation time in use (Smagorinsky or molecular) */
+  real Pi[3][3]; /* non-equilibrium second moment, Pi^neq */
+  real F[19];  /* force term per direction */
+  real E[3][3];  /* artefact term E_ij of Eq. (9) */
+} node_t;
+
+/* Moments, model velocities, Pi^neq, Smagorinsky tau, force term. */
+static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, node_t* s) {
+  const int D = o->D, Q = o->Q;
+  const double c = o->c, c2 = c * c, dt = o->dt;
+  memset(s, 0, sizeof(*s));
+  /* rho = sum f, rho u = sum e f (Section 2) */
+  real rho = o->rho0, j[3] = {0, 0, 0};
+  for (int q = 0; q < Q; ++q) {
+    rho += dl[q];
+    for (int k = 0; k < D; ++k) j[k] += (real)(c * o->e[q][k]) * dl[q];
+  }
+  s->rho = rho;
+  for (int k = 0; k < 3; ++k) {
+    s->u[k] = k < D ? j[k] / rho : 0;
+    s->a[k] = k < D ? body_force(o, idx, k) : 0;
+    s->v[k] = s->u[k] + 0.5 * dt * s->a[k]; /* v = u + dt a / 2 for all models */
+    s->B[k] = Bn ? Bn[k] : 0;
+  }
+  /* u^eq per model (Section 2): [e] uses v, the original Shan-Chen form uses
+   * u + tau dt a, all others use u. */
+  for (int k = 0; k < 3; ++k) {
+    if (o->model == 4)
+      s->ueq[k] = s->v[k];
+    else if (o->model == 5)
+      s->ueq[k] = s->u[k] + o->tau * dt * s->a[k];
+    else
+      s->ueq[k] = s->u[k];
+  }
+  /* Pi^neq = sum e e f - (p delta + rho u^eq u^eq + L) (cheap form after
+   * Eq. 9, with the Maxwell stress that Eq. 11 puts in M^eq_ij). */
+  for (int i = 0; i < D; ++i)
+    for (int k = 0; k < D; ++k) {
+      real m = 0;
+      for (int q = 0; q < Q; ++q) m += (real)(c2 * o->e[q][i] * o->e[q][k]) * dl[q];
+      real eqm = (i == k ? (rho - o->rho0) * c2 / 3.0 : 0.0) + rho * s->ueq[i] * s->ueq[k];
+      if (o->mhd) eqm += maxwell(o, i, k, s->B);
+      s->Pi[i][k] = m - eqm;
+    }
+  /* Smagorinsky closure (C_s > 0): nu_eff = nu0 + (C_s dx)^2 |S| with
+   * |S| = sqrt(2 S:S) and S from Eq. (9) at the same tau_eff; with
+   * nu = dt c^2 (tau - 1/2) / 3 this is the quadratic
+   *   tau^2 - tau0 tau - 9 sqrt(2) (C_s dx)^2 Q / (2 rho c^4 dt^2) = 0,
+   * Q = sqrt(Pi:Pi), whose positive root is taken. */
+  s->tau = o->tau;
+  if (o->cs > 0) {
+    real PP = 0;
+    for (int i = 0; i < D; ++i)
+      for (int k = 0; k < D; ++k) PP += s->Pi[i][k] * s->Pi[i][k];
+    real Qn = RSQRT(PP);
+    double l2 = (o->cs * o->dx) * (o->cs * o->dx);
+    s->tau = 0.5 * (o->tau + RSQRT(o->tau * o->tau + 18.0 * sqrt(2.0) * l2 * Qn / (rho * c2 * c2 * dt * dt)));
+  }
+  /* u^F and C per model (Section 2) */
+  s->C = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    switch (o->model) {
+      case 1: s->uF[k] = s->u[k]; break;                                   /* [b] */
+      case 2: s->uF[k] = s->u[k] + 0.5 * s->tau * dt * s->a[k]; break;   /* [c] */
+      case 3: s->uF[k] = s->v[k]; break;                                   /* [d] */
+      case 4: s->uF[k] = s->v[k]; break;                                   /* [e] */
+      default: s->uF[k] = 0; break;
+    }
+  }
+  if (o->model == 4) s->C = 1.0 - 1.0 / (2.0 * s->tau);
+  /* force term */
+  for (int q = 0; q < Q; ++q) {
+    real ea = edot(o, q, s->a);
+    if (o->model == 0) {
+      /* [a] He et al.: F = rho w 3 e.a dt / c^2 */
+      s->F[q] = rho * o->w[q] * 3.0 * ea * dt / c2;
+    } else if (o->model >= 1 && o->model <= 4) {
+      /* Eq. (3): F = C rho w [3 (e - u^F)/c^2 + 9 (e.u^F) e / c^4] . a dt */
+      real uFa = 0;
+      for (int k = 0; k < D; ++k) uFa += s->uF[k] * s->a[k];
+      real euF = edot(o, q, s->uF);
+      s->F[q] = s->C * rho * o->w[q] * (3.0 * (ea - uFa) / c2 + 9.0 * euF * ea / (c2 * c2)) * dt;
+    } else if (o->model == 6) {
+      /* original exact-difference form: F = feq(rho, u + dt a) - feq(rho, u) */
+      real us[3];
+      for (int k = 0; k < 3; ++k) us[k] = s->u[k] + dt * s->a[k];
+      s->F[q] = feq_dev(o, q, rho, us) - feq_dev(o, q, rho, s->u);
+    } else {
+      s->F[q] = 0; /* original Shan-Chen: no force term */
+    }
+  }
+  /* artefact term of Eq. (9): E = tau dt (u^eq_i rho a_j + u^eq_j rho a_i) - tau Theta_ij,
+   * Theta_ij = sum e_i e_j F (Eq. 4) */
+  for (int i = 0; i < D; ++i)
+    for (int k = 0; k < D; ++k) {
+      real th = 0;
+      for (int q = 0; q < Q; ++q) th += (real)(c2 * o->e[q][i] * o->e[q][k]) * s->F[q];
+      s->E[i][k] = s->tau * dt * (s->ueq[i] * rho * s->a[k] + s->ueq[k] * rho * s->a[i]) - s->tau * th;
+    }
+}
+
+/* Where does the link from node (x,y,z) along direction e end?
+ * Returns 0 and the target index for a fluid target (periodic wrap), or 1 and
+ * the link group for a link that ends in a wall or solid node.  A link that
+ * crosses plane walls of two axes (a corner) belongs to the lowest such axis. */
+static int link_target(const orc* o, int x, int y, int z, const int* e, long* tidx, int* grp) {
+  int p[3] = {x + e[0], y + e[1], z + e[2]};
+  int n[3] = {o->nx, o->ny, o->nz};
+  for (int k = 0; k < 3; ++k) {
+    if (p[k] < 0 || p[k] >= n[k]) {
+      int side = p[k] < 0 ? 0 : 1;
+      if (o->wall[k][side] >= 0) {
+        *grp = o->wall[k][side];
+        return 1;
+      }
+      p[k] = (p[k] + n[k]) % n[k];
+    }
+  }
+  long t = ((long)p[2] * o->ny + p[1]) * o->nx + p[0];
+  if (o->solid[t]) {
+    *grp = o->solid[t] - 1;
+    return 1;
+  }
+  *tidx = t;
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Initial state
+ * ------------------------------------------------------------------------- */
+int orc_init_equilibrium(orc* o, const double* u0) {
+  const long N = o->N;
+  for (long i = 0; i < N; ++i) {
+    real u[3] = {0, 0, 0};
+    if (u0)
+      for (int k = 0; k < o->D; ++k) u[k] = u0[(long)k * N + i];
+    real B[3] = {o->B0[0], o->B0[1], o->B0[2]};
+    for (int q = 0; q < o->Q; ++q) {
+      real v = o->solid[i] ? 0 : feq_dev(o, q, o->rho0, u);
+      if (o->mhd && !o->solid[i]) v += phi_mhd(o, q, B);
+      o->d[(long)q * N + i] = v;
+    }
+    if (o->mhd) {
+      for (int k = 0; k < 7; ++k)
+        for (int c = 0; c < 3; ++c) {
+          real geq = w7(k) * B[c];
+          if (!o->solid[i])
+            for (int m = 0; m < 3; ++m)
+              geq += w7(k) * (e7[k][m] / (THETA7 * o->c)) * (u[m] * B[c] - B[m] * u[c]);
+          o->g[((long)k * 3 + c) * N + i] = geq;
+        }
+    }
+  }
+  o->step = 0;
+  o->have_step = 0;
+  return 0;
+}
+
+int orc_set_state(orc* o, const double* d, const double* d_im) {
+  for (long i = 0; i < (long)o->Q * o->N; ++i) o->d[i] = MK(d[i], d_im ? d_im[i] : 0.0);
+  o->have_step = 0;
+  return 0;
+}
+
+int orc_get_state(const orc* o, double* d, double* d_im) {
+  for (long i = 0; i < (long)o->Q * o->N; ++i) {
+    d[i] = RE(o->d[i]);
+    if (d_im) d_im[i] = IM(o->d[i]);
+  }
+  return 0;
+}
+
+int orc_get_induction(const orc* o, double* g) {
+  if (!o->mhd) return -1;
+  for (long i = 0; i < 21 * o->N; ++i) g[i] = RE(o->g[i]);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * One time step
+ * ------------------------------------------------------------------------- */
+/* per-row partial sums: [G][3][3] wall force, then M, P[3], rho_a[3] */
+static int part_size(const orc* o) { return o->G * 9 + 7; }
+
+static void update_node(orc* o, int x, int y, int z, real* part) {
+  const int D = o->D, Q = o->Q;
+  const long N = o->N;
+  const double c = o->c, c2 = c * c, dt = o->dt;
+  const double vol = o->lat == 0 ? o->dx * o->dx : o->dx * o->dx * o->dx; /* dx^D */
+  const long idx = ((long)z * o->ny + y) * o->nx + x;
+  real dl[19], drel[19];
+  for (int q = 0; q < Q; ++q) dl[q] = o->d[(long)q * N + idx];
+  real Bn[3] = {0, 0, 0};
+  real gl[7][3];
+  if (o->mhd) {
+    for (int k = 0; k < 7; ++k)
+      for (int m = 0; m < 3; ++m) {
+        gl[k][m] = o->g[((long)k * 3 + m) * N + idx];
+        Bn[m] += gl[k][m]; /* B = sum_k g_k */
+      }
+  }
+  node_t s;
+  node_setup(o, dl, idx, o->mhd ? Bn : NULL, &s);
+
+  /* balance partials at time t (Eq. 32): mass, momentum, body force */
+  real* pb = part + o->G * 9;
+  pb[0] += vol * s.rho;
+  for (int k = 0; k < 3; ++k) {
+    pb[1 + k] += vol * s.rho * s.u[k];
+    pb[4 + k] += vol * s.rho * s.a[k];
+  }
+
+  /* relaxation, Eq. (2): f_rel = f + (f^eq - f)/tau + F */
+  for (int q = 0; q < Q; ++q) {
+    real deq = feq_dev(o, q, s.rho, s.ueq);
+    if (o->mhd) deq += phi_mhd(o, q, s.B);
+    drel[q] = dl[q] + (deq - dl[q]) / s.tau + s.F[q];
+  }
+
+  /* propagation with halfway bounce-back and momentum exchange */
+  for (int q = 0; q < Q; ++q) {
+    long t;
+    int grp;
+    if (!link_target(o, x, y, z, o->e[q], &t, &grp)) {
+      o->dn[(long)q * N + t] = drel[q];
+      continue;
+    }
+    const int qb = o->opp[q];
+    /* moving wall: the returning population gains 6 w rho (e_qb . u_w) / c^2 */
+    real ladd = 6.0 * o->w[q] * s.rho * edot(o, qb, o->uw[grp]) / c2;
+    o->dn[(long)qb * N + idx] = drel[q] + ladd;
+    /* Eq. (25): outgoing f_bar = f_rel(x_f, t), incoming f_bar = f(x_f, t + dt) */
+    real fout = drel[q] + o->w[q] * o->rho0;
+    real fin = fout + ladd;
+    real* pw = part + grp * 9;
+    for (int k = 0; k < 3; ++k) {
+      double ek = c * o->e[q][k], ebk = c * o->e[qb][k];
+      pw[k] += vol / dt * (ek * fout - ebk * fin);          /* raw momentum exchange */
+      pw[3 + k] += -vol / dt * o->uw[grp][k] * (fout - fin); /* minus momentum flux */
+    }
+    if (o->mhd) {
+      /* minus Maxwell stress: the magnetic part of the equilibrium at the wall
+       * field carried by both populations of the link */
+      real Bw[3] = {o->B0[0], o->B0[1], o->B0[2]};
+      real ph = phi_mhd(o, q, Bw);
+      for (int k = 0; k < 3; ++k) pw[6 + k] += -vol / dt * 2.0 * (c * o->e[q][k]) * ph;
+    }
+  }
+
+  /* induction lattice (D3Q7 vector distributions, B Dirichlet on walls) */
+  if (o->mhd) {
+    for (int k = 0; k < 7; ++k) {
+      real grel[3];
+      for (int m = 0; m < 3; ++m) {
+        real geq = w7(k) * s.B[m];
+        for (int j = 0; j < 3; ++j)
+          geq += w7(k) * (e7[k][j] / (THETA7 * c)) * (s.v[j] * s.B[m] - s.B[j] * s.v[m]);
+        grel[m] = gl[k][m] + (geq - gl[k][m]) / o->tau_m;
+      }
+      long t;
+      int grp;
+      if (!link_target(o, x, y, z, e7[k], &t, &grp)) {
+        for (int m = 0; m < 3; ++m) o->gn[((long)k * 3 + m) * N + t] = grel[m];
+      } else {
+        /* anti-bounce-back imposing B = B0 at the halfway wall */
+        int kb = opp7[k];
+        for (int m = 0; m < 3; ++m) o->gn[((long)kb * 3 + m) * N + idx] = -grel[m] + 2.0 * w7(k) * o->B0[m];
+      }
+    }
+  }
+  (void)D;
+}
+
+int orc_step(orc* o, int n) {
+  if (n < 0) return -1;
+  const int P = part_size(o);
+  const long rows = (long)o->ny * o->nz;
+  real* part = (real*)malloc(sizeof(real) * P * rows);
+  for (int it = 0; it < n; ++it) {
+    memset(part, 0, sizeof(real) * P * rows);
+#pragma omp parallel for schedule(static)
+    for (long r = 0; r < rows; ++r) {
+      int y = (int)(r % o->ny), z = (int)(r / o->ny);
+      real* pr = part + r * P;
+      for (int x = 0; x < o->nx; ++x) {
+        long idx = ((long)z * o->ny + y) * o->nx + x;
+        if (o->solid[idx]) continue;
+        update_node(o, x, y, z, pr);
+      }
+    }
+    /* row partials summed in row order */
+    real tot[MAXG * 9 + 7];
+    memset(tot, 0, sizeof(tot));
+    for (long r = 0; r < rows; ++r)
+      for (int k = 0; k < P; ++k) tot[k] += part[r * P + k];
+    for (int gr = 0; gr < o->G; ++gr)
+      for (int v = 0; v < 3; ++v)
+        for (int k = 0; k < 3; ++k) o->wf[gr][v][k] = tot[gr * 9 + v * 3 + k];
+    o->M_t = tot[o->G * 9];
+    for (int k = 0; k < 3; ++k) {
+      o->P_t[k] = tot[o->G * 9 + 1 + k];
+      o->rho_a[k] = tot[o->G * 9 + 4 + k];
+    }
+    real* t = o->d;
+    o->d = o->dn;
+    o->dn = t;
+    if (o->mhd) {
+      t = o->g;
+      o->g = o->gn;
+      o->gn = t;
+    }
+    o->step++;
+    o->have_step = 1;
+  }
+  free(part);
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics
+ * ------------------------------------------------------------------------- */
+static void node_B(const orc* o, long idx, real* B) {
+  B[0] = B[1] = B[2] = 0;
+  if (!o->mhd) return;
+  for (int k = 0; k < 7; ++k)
+    for (int m = 0; m < 3; ++m) B[m] += o->g[((long)k * 3 + m) * o->N + idx];
+}
+
+static void load_node(const orc* o, long idx, real* dl) {
+  for (int q = 0; q < o->Q; ++q) dl[q] = o->d[(long)q * o->N + idx];
+}
+
+int orc_get_macro(const orc* o, double* rho, double* v, double* B) {
+  for (long i = 0; i < o->N; ++i) {
+    if (o->solid[i]) {
+      rho[i] = 0;
+      for (int k = 0; k < o->D; ++k) v[(long)k * o->N + i] = 0;
+      if (B)
+        for (int k = 0; k < 3; ++k) B[(long)k * o->N + i] = 0;
+      continue;
+    }
+    real dl[19], Bn[3];
+    load_node(o, i, dl);
+    node_B(o, i, Bn);
+    node_t s;
+    node_setup(o, dl, i, Bn, &s);
+    rho[i] = RE(s.rho);
+    for (int k = 0; k < o->D; ++k) v[(long)k * o->N + i] = RE(s.v[k]);
+    if (B)
+      for (int k = 0; k < 3; ++k) B[(long)k * o->N + i] = RE(Bn[k]);
+  }
+  return 0;
+}
+
+/* Eq. (8)-(9): S = -3 / (2 tau dt c^2 rho) (Pi^neq [+ E]),  sigma = 2 rho nu S
+ * with nu = dt c^2 (tau - 1/2) / 3, tau the relaxation time in use. */
+static void node_stress(const orc* o, const node_t* s, real sig[3][3], real S[3][3]) {
+  const double c2 = o->c * o->c, dt = o->dt;
+  real nu = dt * c2 * (s->tau - 0.5) / 3.0;
+  for (int i = 0; i < o->D; ++i)
+    for (int k = 0; k < o->D; ++k) {
+      real P = s->Pi[i][k] + (o->artefact ? s->E[i][k] : 0.0);
+      S[i][k] = -3.0 / (2.0 * s->tau * dt * c2 * s->rho) * P;
+      sig[i][k] = 2.0 * s->rho * nu * S[i][k];
+    }
+}
+
+static const int comp2[3][2] = {{0, 0}, {0, 1}, {1, 1}};
+static const int comp3[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+
+int orc_stress(const orc* o, double* sigma, double* strain) {
+  const int nc = o->D == 2 ? 3 : 6;
+  for (long i = 0; i < o->N; ++i) {
+    real sig[3][3], S[3][3];
+    memset(sig, 0, sizeof(sig));
+    memset(S, 0, sizeof(S));
+    if (!o->solid[i]) {
+      real dl[19], Bn[3];
+      load_node(o, i, dl);
+      node_B(o, i, Bn);
+      node_t s;
+      node_setup(o, dl, i, Bn, &s);
+      node_stress(o, &s, sig, S);
+    }
+    for (int m = 0; m < nc; ++m) {
+      int a = o->D == 2 ? comp2[m][0] : comp3[m][0];
+      int b = o->D == 2 ? comp2[m][1] : comp3[m][1];
+      if (sigma) sigma[(long)m * o->N + i] = RE(sig[a][b]);
+      if (strain) strain[(long)m * o->N + i] = RE(S[a][b]);
+    }
+  }
+  return 0;
+}
+
+int orc_wall_force(const orc* o, double* out, double* out_im, int G) {
+  for (int gr = 0; gr < G; ++gr) {
+    for (int k = 0; k < 3; ++k) {
+      real raw = gr < o->G ? o->wf[gr][0][k] : 0;
+      real mf = gr < o->G ? o->wf[gr][1][k] : 0;
+      real mx = gr < o->G ? o->wf[gr][2][k] : 0;
+      real v[4] = {raw, raw + mf, raw + mx, raw + mf + mx};
+      for (int var = 0; var < 4; ++var) {
+        out[(gr * 4 + var) * 3 + k] = RE(v[var]);
+        if (out_im) out_im[(gr * 4 + var) * 3 + k] = IM(v[var]);
+      }
+    }
+  }
+  return 0;
+}
+
+long orc_link_count(const orc* o, int group) {
+  long n = 0;
+  for (int z = 0; z < o->nz; ++z)
+    for (int y = 0; y < o->ny; ++y)
+      for (int x = 0; x < o->nx; ++x) {
+        long idx = ((long)z * o->ny + y) * o->nx + x;
+        if (o->solid[idx]) continue;
+        for (int q = 0; q < o->Q; ++q) {
+          long t;
+          int grp;
+          if (link_target(o, x, y, z, o->e[q], &t, &grp) && (group < 0 || grp == group)) ++n;
+        }
+      }
+  return n;
+}
+
+/* Surface sum of (-p delta + sigma) n over the plane walls, with p and sigma
+ * extrapolated linearly from the first two fluid layers to the halfway wall
+ * (the stress form of the wall force, Eqs. 26, 28 and 33). */
+static void stress_integral(const orc* o, real* F) {
+  const double c2 = o->c * o->c;
+  const double area = o->lat == 0 ? o->dx : o->dx * o->dx;
+  int n[3] = {o->nx, o->ny, o->nz};
+  F[0] = F[1] = F[2] = 0;
+  for (int ax = 0; ax < o->D; ++ax) {
+    if (n[ax] < 2) continue;
+    for (int side = 0; side < 2; ++side) {
+      if (o->wall[ax][side] < 0) continue;
+      int l0 = side == 0 ? 0 : n[ax] - 1, l1 = side == 0 ? 1 : n[ax] - 2;
+      double nrm = side == 0 ? 1.0 : -1.0; /* inward normal component along ax */
+      for (int z = 0; z < o->nz; ++z)
+        for (int y = 0; y < o->ny; ++y)
+          for (int x = 0; x < o->nx; ++x) {
+            int p[3] = {x, y, z};
+            if (p[ax] != l0) continue;
+            long i0 = ((long)z * o->ny + y) * o->nx + x;
+            p[ax] = l1;
+            long i1 = ((long)p[2] * o->ny + p[1]) * o->nx + p[0];
+            if (o->solid[i0] || o->solid[i1]) continue;
+            real T[2][3][3];
+            long ids[2] = {i0, i1};
+            for (int l = 0; l < 2; ++l) {
+              real dl[19], Bn[3], sig[3][3], S[3][3];
+              load_node(o, ids[l], dl);
+              node_B(o, ids[l], Bn);
+              node_t s;
+              node_setup(o, dl, ids[l], Bn, &s);
+              memset(sig, 0, sizeof(sig));
+              node_stress(o, &s, sig, S);
+              for (int i = 0; i < 3; ++i)
+                for (int k = 0; k < 3; ++k) T[l][i][k] = sig[i][k] - (i == k && i < o->D ? s.rho * c2 / 3.0 : 0.0);
+            }
+            for (int i = 0; i < o->D; ++i) F[i] += area * (1.5 * T[0][i][ax] - 0.5 * T[1][i][ax]) * nrm;
+          }
+    }
+  }
+}
+
+int orc_force_balance(const orc* o, double* out) {
+  memset(out, 0, sizeof(double) * NREC);
+  const double vol = o->lat == 0 ? o->dx * o->dx : o->dx * o->dx * o->dx;
+  /* moments of the current state, time t + dt */
+  real M1 = 0, P1[3] = {0, 0, 0};
+  for (long i = 0; i < o->N; ++i) {
+    if (o->solid[i]) continue;
+    real rho = o->rho0, j[3] = {0, 0, 0};
+    for (int q = 0; q < o->Q; ++q) {
+      real dq = o->d[(long)q * o->N + i];
+      rho += dq;
+      for (int k = 0; k < o->D; ++k) j[k] += (real)(o->c * o->e[q][k]) * dq;
+    }
+    M1 += vol * rho;
+    for (int k = 0; k < 3; ++k) P1[k] += vol * j[k];
+  }
+  real Fsi[3];
+  stress_integral(o, Fsi);
+  for (int k = 0; k < 3; ++k) {
+    real raw = 0, mx = 0, mf = 0;
+    for (int gr = 0; gr < o->G; ++gr) {
+      raw += o->wf[gr][0][k];
+      mf += o->wf[gr][1][k];
+      mx += o->wf[gr][2][k];
+    }
+    real dP = o->have_step ? (P1[k] - o->P_t[k]) / o->dt : 0;
+    out[0 + k] = RE(raw);
+    out[3 + k] = RE(o->rho_a[k]);
+    out[6 + k] = RE(dP);
+    out[9 + k] = RE(o->rho_a[k] - raw - dP);
+    out[12 + k] = RE(mx);
+    out[15 + k] = RE(mf);
+    out[18 + k] = RE(Fsi[k]);
+  }
+  out[21] = RE(M1);
+  out[22] = o->have_step ? RE(M1 - o->M_t) : 0;
+  out[23] = (double)o->step;
+  return 0;
+}
