@@ -200,13 +200,14 @@ int orc_set_solid(orc* o, const unsigned char* mask, int group) {
 
 int orc_set_wall_velocity(orc* o, int group, const double* u, const double* u_im) {
   if (group < 0 || group >= MAXG) return -1;
-  for (int k = 0; k < 3; ++k) o->uw[group][k] = MK(u[k], u_im ? u_im[k] : 0.0);
+  /* a two-dimensional lattice has no z component */
+  for (int k = 0; k < 3; ++k) o->uw[group][k] = k < o->D ? MK(u[k], u_im ? u_im[k] : 0.0) : 0.0;
   note_group(o, group);
   return 0;
 }
 
 int orc_set_body_force(orc* o, const double* a, const double* a_im) {
-  for (int k = 0; k < 3; ++k) o->a[k] = MK(a[k], a_im ? a_im[k] : 0.0);
+  for (int k = 0; k < 3; ++k) o->a[k] = k < o->D ? MK(a[k], a_im ? a_im[k] : 0.0) : 0.0;
   return 0;
 }
 
