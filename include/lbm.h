@@ -1,0 +1,192 @@
+/*
+ * lbm.h - C ABI of the MI355X lattice Boltzmann hot path.
+ *
+ * Method: J. Li, "Shear Stress and Fluid-Wall Interaction Force in LBM
+ * Simulations of Hydrodynamic and MHD Flows", arXiv 2512.12213.
+ *
+ * One context = one lattice on one GPU (the current HIP device when
+ * lbm_create is called).  The library owns every device buffer it allocates;
+ * host buffers passed in are owned by the caller and only read / written
+ * during the call; device pointers passed in are borrowed and must outlive
+ * their use.  A context is not thread-safe: call it from one host thread.
+ *
+ * Every int-returning call returns LBM_OK (0) or a negative error code and
+ * then sets a thread-local message readable with lbm_last_error().
+ *
+ * Units are physical: lattice spacing dx, time step dt, lattice speed
+ * c = dx/dt, kinematic viscosity nu = dt c^2 (tau - 1/2) / 3 (Section 2).
+ * Forces are per unit depth in 2D.
+ *
+ * Array layouts (all x fastest, "[a][b]" = a slowest):
+ *   scalar field   [nz][ny][nx]
+ *   vector field   [D][nz][ny][nx]   (D = 2 for D2Q9, 3 for D3Q19)
+ *   distributions  [Q][nz][ny][nx], deviations d = f - w * rho0, in the
+ *                  direction order below
+ *   stress tensor  [ncomp][nz][ny][nx]: ncomp = 3 (xx, xy, yy) in 2D,
+ *                  6 (xx, yy, zz, xy, xz, yz) in 3D
+ * Direction order:
+ *   D2Q9 : 0 rest; 1 +x; 2 -x; 3 +y; 4 -y; 5 (+x,+y); 6 (-x,-y); 7 (+x,-y); 8 (-x,+y)
+ *   D3Q19: 0 rest; 1,2 +-x; 3,4 +-y; 5,6 +-z; 7,8 +-(x+y); 9,10 +-(x-y);
+ *          11,12 +-(x+z); 13,14 +-(x-z); 15,16 +-(y+z); 17,18 +-(y-z)
+ *   D3Q7 (induction): 0 rest; 1,2 +-x; 3,4 +-y; 5,6 +-z
+ */
+#ifndef LBM_H
+#define LBM_H
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+/* Body-force models of Section 2: [a] He et al., [b] Martys-Shan-Chen / Luo
+ * (Eq. 3), [c] Shan-Chen reformulated, [d] exact-difference reformulated,
+ * [e] Guo. */
+enum { LBM_FORCE_HE = 0, LBM_FORCE_LUO = 1, LBM_FORCE_SHANCHEN = 2, LBM_FORCE_EDM = 3, LBM_FORCE_GUO = 4 };
+/* Storage precision of the distributions (arithmetic is FP32 for the
+ * reduced formats, FP64 for LBM_F64). */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3 };
+enum { LBM_OK = 0, LBM_EINVAL = -1, LBM_ENOMEM = -2, LBM_EHIP = -3, LBM_ESTATE = -4, LBM_EUNSTABLE = -5 };
+enum { LBM_MAX_GROUPS = 16, LBM_NREC = 24 };
+
+/* Create a lattice.  Section 2: uniform grid with spacing dx, time step dt,
+ * relaxation time tau (tau > 1/2), D2Q9 (nz must be 1) or D3Q19.  All axes
+ * are periodic until walls are added.  Storage defaults to LBM_F32, rho0 to 1.
+ * Limits: every axis <= 65536 nodes; a distribution plane must fit in 4 GiB.
+ * Returns NULL on error (lbm_last_error() explains). */
+lbm_ctx* lbm_create(int lattice, int nx, int ny, int nz, double tau, double dx, double dt, int force_model);
+
+/* Free every device buffer of the context; NULL is accepted. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* lbm_last_error(void);
+
+/* ---- set-up (before the first lbm_init_equilibrium / lbm_set_state unless noted) ---- */
+
+/* Storage precision, one of LBM_F64/F32/F16/BF16.  16-bit formats store
+ * d/w scaled by 2^10 (F16) or d/w (BF16), rounded to nearest even. */
+int lbm_set_storage(lbm_ctx* ctx, int precision);
+
+/* Reference density rho0 > 0 (the deviation origin and the initial density). */
+int lbm_set_rho0(lbm_ctx* ctx, double rho0);
+
+/* Halfway bounce-back plane walls half a spacing beyond the first and last
+ * node along `axis` (0 = x, 1 = y, 2 = z); all nodes stay fluid
+ * (Section 4, Eq. 25: wall a half grid away from the fluid node).  A group
+ * is a label in [0, 16) under which wall forces are summed; -1 leaves that
+ * end periodic.  A link crossing two walls (a corner) belongs to the
+ * lower-numbered axis. */
+int lbm_add_plane_walls(lbm_ctx* ctx, int axis, int group_lo, int group_hi);
+
+/* Solid nodes: mask_host [nz][ny][nx], nonzero = solid, links from fluid
+ * nodes into them are halfway bounce-back links of `group`. */
+int lbm_add_solid_mask(lbm_ctx* ctx, const unsigned char* mask_host, int group);
+
+/* Wall velocity of a group (moving-wall bounce-back adds
+ * 6 w rho (e.u_w)/c^2 to the returning population).  May change between
+ * steps. */
+int lbm_set_wall_velocity(lbm_ctx* ctx, int group, double ux, double uy, double uz);
+
+/* Uniform body force per unit mass a.  May change between steps. */
+int lbm_set_body_force(lbm_ctx* ctx, double ax, double ay, double az);
+
+/* Per-node body force: borrowed device pointer to float [3][nz][ny][nx]
+ * (e.g. a torch tensor's data_ptr), or NULL to return to the uniform force.
+ * May change between steps; must stay valid while steps run. */
+int lbm_set_body_force_field(lbm_ctx* ctx, const void* dev_ptr);
+
+/* Smagorinsky constant C_s >= 0 for the eddy viscosity built from the
+ * strain rate of Eq. (9); 0 disables it. */
+int lbm_set_les(lbm_ctx* ctx, double cs);
+
+/* Include the artefact term E_ij of Eq. (9) in the stress and strain
+ * outputs (0 = off, the default).  Any time. */
+int lbm_set_artefact(lbm_ctx* ctx, int include_Eij);
+
+/* MHD equilibrium of Eq. (10) (D3Q19 only, F32/F64 storage) with a D3Q7
+ * vector-distribution induction lattice (relaxation time tau_m > 1/2,
+ * magnetic diffusivity dt c^2 (tau_m - 1/2) / 4).  All walls are insulating:
+ * B = B0 on them.  mu is the magnetic permeability. */
+int lbm_set_mhd(lbm_ctx* ctx, double B0x, double B0y, double B0z, double mu, double tau_m);
+
+/* HIP stream (hipStream_t) on which all later work of the context is
+ * enqueued, e.g. torch.cuda.current_stream().cuda_stream; NULL = the
+ * context's own stream.  Any time. */
+int lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
+
+/* ---- state ---- */
+
+/* f = f^eq(rho0, u0) (Eq. 1; plus the magnetic term of Eq. 10 with B0 under
+ * MHD).  u0_host: [D][nz][ny][nx] doubles, the velocity u = sum(e f)/rho, or
+ * NULL for rest.  Resets the step counter. */
+int lbm_init_equilibrium(lbm_ctx* ctx, const double* u0_host);
+
+/* Upload / download deviations [Q][nz][ny][nx] (doubles, caller-owned),
+ * in the direction order above.  lbm_set_state resets the step counter. */
+int lbm_set_state(lbm_ctx* ctx, const double* d_host);
+int lbm_get_state(lbm_ctx* ctx, double* d_host);
+
+/* Induction distributions g [7][3][nz][ny][nx] (absolute values). MHD only. */
+int lbm_get_induction(lbm_ctx* ctx, double* g_host);
+
+/* ---- the hot path ---- */
+
+/* Advance n >= 0 steps of Eq. (2): f(x + dt e, t + dt) = f + (f^eq - f)/tau + F,
+ * with streaming in place, bounce-back, the force model and (if enabled)
+ * Smagorinsky closure and the MHD equilibrium.  All steps are enqueued on
+ * the stream with no host synchronisation between them; the last step also
+ * produces the wall-force and balance records.  The call ends with one
+ * stream synchronisation and a finiteness check of the total mass:
+ * LBM_EUNSTABLE if it is NaN or infinite. */
+int lbm_step(lbm_ctx* ctx, int n);
+
+/* Density rho [nz][ny][nx] and flow velocity v = u + dt a / 2 [D][nz][ny][nx]
+ * (Section 2) of the current state, into caller-owned host buffers (either
+ * may be NULL).  Solid nodes read 0. */
+int lbm_get_macro(lbm_ctx* ctx, double* rho, double* v);
+
+/* Magnetic field B = sum_k g_k [3][nz][ny][nx] of the current state (MHD). */
+int lbm_get_field_B(lbm_ctx* ctx, double* B);
+
+/* Shear stress sigma = 2 rho nu S (Eq. 8) and strain rate
+ * S = -3 / (2 tau dt c^2 rho) (Pi^neq [+ E]) (Eq. 9) of the current state,
+ * with Pi^neq = sum(e e f) - (p I + rho u^eq u^eq [+ L]) and tau the
+ * Smagorinsky-effective relaxation time when LES is on.  Caller-owned host
+ * buffers [ncomp][nz][ny][nx]; either may be NULL.  Solid nodes read 0. */
+int lbm_stress(lbm_ctx* ctx, double* sigma, double* strain);
+
+/* Momentum-exchange force on the walls of each group during the last step
+ * (Eq. 25, the populations leaving at t and returning at t + dt, per link
+ * (dx^D / dt)(e_out f_out - e_in f_in)).  out [G][4][3], G = lbm_num_groups:
+ * variant 0 raw; 1 minus the moving-boundary momentum flux
+ * -(dx^D/dt) u_w (f_out - f_in); 2 minus the Maxwell stress carried by the
+ * MHD equilibrium, -(dx^D/dt) 2 e_out phi_out(B0); 3 minus both.  z = 0 in 2D.
+ * LBM_ESTATE before the first step. */
+int lbm_wall_force(lbm_ctx* ctx, double* out);
+
+/* Global balance of the last step (Eq. 32), out[24] doubles:
+ *  0-2  F_wall raw (all groups)          3-5  sum rho a dx^D at t
+ *  6-8  (P(t+dt) - P(t)) / dt, P = sum rho u dx^D
+ *  9-11 residual (3-5) - (0-2) - (6-8)   (exactly 0 up to rounding)
+ * 12-14 total Maxwell correction        15-17 total momentum-flux correction
+ * 18-20 stress-integral force over plane walls: sum of (-p I + sigma) n dA
+ *       with p, sigma extrapolated linearly from the first two fluid layers
+ *       (Eqs. 26, 33), of the current state
+ * 21 mass M(t+dt) = sum rho dx^D    22 M(t+dt) - M(t)    23 steps taken
+ * LBM_ESTATE before the first step. */
+int lbm_force_balance(lbm_ctx* ctx, double* out);
+
+/* Number of wall groups (1 + largest group label in use). */
+int lbm_num_groups(lbm_ctx* ctx);
+
+/* Number of bounce-back links of a group (-1 = all groups). */
+long lbm_link_count(lbm_ctx* ctx, int group);
+
+/* Steps taken since the last initialisation. */
+long lbm_steps_taken(lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

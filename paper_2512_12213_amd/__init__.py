@@ -1,1 +1,14 @@
-"""MI355X-native lattice Boltzmann hot path (arXiv 2512.12213)."""
+"""MI355X-native lattice Boltzmann hot path (arXiv 2512.12213).
+
+The compute path is the HIP library ``liblbm.so`` (C ABI in include/lbm.h);
+``lbm`` is its ctypes binding and ``workloads`` holds the synthetic workload
+definitions and seeded input generators.
+"""
+from . import workloads  # noqa: F401
+
+
+def __getattr__(name):
+    if name in ("lbm", "Lattice", "from_workload"):
+        from . import lbm as _lbm
+        return _lbm if name == "lbm" else getattr(_lbm, name)
+    raise AttributeError(name)

@@ -1,0 +1,853 @@
+// Device kernels of the lattice Boltzmann hot path for gfx950 (MI355X).
+//
+// One thread per lattice node, 256-thread tiles of consecutive nodes (x
+// fastest).  Distributions live in one in-place array per lattice,
+// structure-of-arrays [Q][Np], updated with the A-A pattern: on even steps a
+// node reads its own slots and writes its post-collision values into the
+// opposite slots (no data movement between nodes); on odd steps it gathers
+// from its neighbours' opposite slots and scatters into its neighbours' slots.
+// Each slot is read and written by the same thread within a step, so the
+// update is race-free in place.  Halfway bounce-back only changes which slot a
+// link reads / writes; boundary nodes are described by compact per-row
+// records so that bulk rows pay no extra memory traffic.
+//
+// All quantities inside the kernels are dimensionless: velocities in units of
+// c = dx/dt, body force as a dt / c, magnetic field as B / (c sqrt(mu)).
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// storage formats
+// ---------------------------------------------------------------------------
+template <int P>
+struct Stor;
+template <>
+struct Stor<S_F64> {
+  using E = double;
+  using T = double;
+  static __device__ __forceinline__ T ld(const E* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ void st(E* p, T v) { __builtin_nontemporal_store(v, p); }
+};
+template <>
+struct Stor<S_F32> {
+  using E = float;
+  using T = float;
+  static __device__ __forceinline__ T ld(const E* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ void st(E* p, T v) { __builtin_nontemporal_store(v, p); }
+};
+template <>
+struct Stor<S_F16> {
+  using E = _Float16;
+  using T = float;
+  static __device__ __forceinline__ T ld(const E* p) { return (float)__builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ void st(E* p, T v) { __builtin_nontemporal_store((_Float16)v, p); }
+};
+template <>
+struct Stor<S_BF16> {
+  using E = uint16_t;
+  using T = float;
+  static __device__ __forceinline__ T ld(const E* p) {
+    return __uint_as_float(uint32_t(__builtin_nontemporal_load(p)) << 16);
+  }
+  static __device__ __forceinline__ void st(E* p, T v) {
+    uint32_t u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    __builtin_nontemporal_store(uint16_t(u >> 16), p);
+  }
+};
+
+template <class T>
+__device__ __forceinline__ T rcp(T x) {
+  return T(1) / x;
+}
+template <>
+__device__ __forceinline__ float rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+
+// ---------------------------------------------------------------------------
+// index helpers
+// ---------------------------------------------------------------------------
+struct Offs {
+  int xp, xm, yp, ym, zp, zm;
+};
+
+__device__ __forceinline__ void coords(const Geom& g, uint32_t n, uint32_t& x, uint32_t& y, uint32_t& z, uint32_t& r) {
+  r = g.nx == 1 ? n : (uint32_t)__umul64hi((uint64_t)n, g.mnx);
+  x = n - r * g.nx;
+  z = g.ny == 1 ? r : (uint32_t)__umul64hi((uint64_t)r, g.mny);
+  y = r - z * g.ny;
+}
+
+// Offsets (in nodes) to the six axis neighbours with periodic wrap.
+__device__ __forceinline__ Offs offsets(const Geom& g, uint32_t x, uint32_t y, uint32_t z) {
+  Offs o;
+  const int nx = (int)g.nx, ny = (int)g.ny, nz = (int)g.nz, sxy = nx * ny;
+  o.xp = (x + 1 == g.nx) ? 1 - nx : 1;
+  o.xm = (x == 0) ? nx - 1 : -1;
+  o.yp = (y + 1 == g.ny) ? (1 - ny) * nx : nx;
+  o.ym = (y == 0) ? (ny - 1) * nx : -nx;
+  o.zp = (z + 1 == g.nz) ? (1 - nz) * sxy : sxy;
+  o.zm = (z == 0) ? (nz - 1) * sxy : -sxy;
+  return o;
+}
+
+// Offset from a node to its neighbour along e_q.
+template <class L>
+__device__ __forceinline__ int off_of(int q, const Offs& o) {
+  int s = 0;
+  if (L::ex(q) > 0) s += o.xp;
+  if (L::ex(q) < 0) s += o.xm;
+  if (L::ey(q) > 0) s += o.yp;
+  if (L::ey(q) < 0) s += o.ym;
+  if (L::ez(q) > 0) s += o.zp;
+  if (L::ez(q) < 0) s += o.zm;
+  return s;
+}
+
+template <class L, class T>
+__device__ __forceinline__ T edot(int q, T vx, T vy, T vz) {
+  T s = T(0);
+  if (L::ex(q) > 0) s += vx;
+  if (L::ex(q) < 0) s -= vx;
+  if (L::ey(q) > 0) s += vy;
+  if (L::ey(q) < 0) s -= vy;
+  if (L::ez(q) > 0) s += vz;
+  if (L::ez(q) < 0) s -= vz;
+  return s;
+}
+
+__device__ __forceinline__ uint32_t nibble(const uint4& r, int q) {
+  const uint32_t w = q < 8 ? r.y : (q < 16 ? r.z : r.w);
+  return (w >> (4 * (q & 7))) & 15u;
+}
+
+// ---------------------------------------------------------------------------
+// A-A reads and writes of one node's distributions
+// ---------------------------------------------------------------------------
+// Reading the state f_q(x, t):
+//   even parity (natural layout): slot q of x;
+//   odd parity: slot opp(q) of x - e_q, or, when the link from x along
+//   -e_q ends in a wall, slot q of x (where the bounce-back value was put).
+template <class L, int P, int PAR, bool BND>
+__device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f, uint64_t Np, uint32_t n, const Offs& o,
+                                       uint32_t mask, const Phys& p, typename Stor<P>::T (&d)[L::Q]) {
+  using S = Stor<P>;
+  using T = typename S::T;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const int qb = opp(q);
+    const typename S::E* ptr;
+    if (PAR == 0) {
+      ptr = f + (uint64_t)q * Np + n;
+    } else {
+      const typename S::E* pn = f + (uint64_t)qb * Np + (uint32_t)(n + off_of<L>(qb, o));
+      if (BND) {
+        const bool bb = (mask >> qb) & 1u;
+        ptr = bb ? f + (uint64_t)q * Np + n : pn;
+      } else {
+        ptr = pn;
+      }
+    }
+    T v = S::ld(ptr);
+    if (P == S_F16 || P == S_BF16) v *= (T)p.inv_scale[q];
+    d[q] = v;
+  }
+}
+
+// Writing the post-collision value v_q of node x (v_q already holds the
+// bounce-back value, including the moving-wall term, for wall links):
+//   even parity: slot opp(q) of x;
+//   odd parity: slot q of x + e_q, or slot opp(q) of x for a wall link.
+template <class L, int P, int PAR, bool BND>
+__device__ __forceinline__ void write_f(typename Stor<P>::E* __restrict__ f, uint64_t Np, uint32_t n, const Offs& o,
+                                        uint32_t mask, const Phys& p, const typename Stor<P>::T (&v)[L::Q]) {
+  using S = Stor<P>;
+  using T = typename S::T;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const int qb = opp(q);
+    typename S::E* ptr;
+    if (PAR == 0) {
+      ptr = f + (uint64_t)qb * Np + n;
+    } else {
+      typename S::E* pn = f + (uint64_t)q * Np + (uint32_t)(n + off_of<L>(q, o));
+      if (BND) {
+        const bool bb = (mask >> q) & 1u;
+        ptr = bb ? f + (uint64_t)qb * Np + n : pn;
+      } else {
+        ptr = pn;
+      }
+    }
+    T s = v[q];
+    if (P == S_F16 || P == S_BF16) s *= (T)p.scale[q];
+    S::st(ptr, s);
+  }
+}
+
+// Same pattern for the 21 induction planes (7 directions x 3 components).
+template <int P, int PAR, bool BND>
+__device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g, uint64_t Np, uint32_t n, const Offs& o,
+                                       uint32_t mask, typename Stor<P>::T (&h)[7][3]) {
+  using S = Stor<P>;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const int kb = opp(k);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const typename S::E* ptr;
+      if (PAR == 0) {
+        ptr = g + (uint64_t)(3 * k + i) * Np + n;
+      } else {
+        const typename S::E* pn = g + (uint64_t)(3 * kb + i) * Np + (uint32_t)(n + off_of<D3Q19>(kb, o));
+        if (BND) {
+          const bool bb = (mask >> kb) & 1u;
+          ptr = bb ? g + (uint64_t)(3 * k + i) * Np + n : pn;
+        } else {
+          ptr = pn;
+        }
+      }
+      h[k][i] = S::ld(ptr);
+    }
+  }
+}
+
+template <int P, int PAR, bool BND>
+__device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, uint64_t Np, uint32_t n, const Offs& o,
+                                        uint32_t mask, const typename Stor<P>::T (&h)[7][3]) {
+  using S = Stor<P>;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const int kb = opp(k);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      typename S::E* ptr;
+      if (PAR == 0) {
+        ptr = g + (uint64_t)(3 * kb + i) * Np + n;
+      } else {
+        typename S::E* pn = g + (uint64_t)(3 * k + i) * Np + (uint32_t)(n + off_of<D3Q19>(k, o));
+        if (BND) {
+          const bool bb = (mask >> k) & 1u;
+          ptr = bb ? g + (uint64_t)(3 * kb + i) * Np + n : pn;
+        } else {
+          ptr = pn;
+        }
+      }
+      S::st(ptr, h[k][i]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// local physics
+// ---------------------------------------------------------------------------
+template <class T>
+struct Macro {
+  T drho, rho, irho;
+  T U[3], A[3], V[3], Ue[3], UF[3];
+  T pi[6];  // Pi^neq / c^2: xx, yy, zz, xy, xz, yz
+  T tau, itau, C;
+  T b[3];
+};
+
+// Moments (Section 2), model velocities, Pi^neq (cheap form after Eq. 9,
+// with the Maxwell stress of Eq. 11 under MHD), Smagorinsky tau.
+template <class L, class T, bool MHD, bool NEED_PI>
+__device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T Ay, T Az, const T (&b)[3], Macro<T>& m) {
+  T drho = T(0), jx = T(0), jy = T(0), jz = T(0);
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    drho += d[q];
+    if (L::ex(q) > 0) jx += d[q];
+    if (L::ex(q) < 0) jx -= d[q];
+    if (L::ey(q) > 0) jy += d[q];
+    if (L::ey(q) < 0) jy -= d[q];
+    if (L::ez(q) > 0) jz += d[q];
+    if (L::ez(q) < 0) jz -= d[q];
+  }
+  m.drho = drho;
+  m.rho = (T)p.rho0 + drho;
+  m.irho = rcp(m.rho);
+  m.U[0] = jx * m.irho;
+  m.U[1] = jy * m.irho;
+  m.U[2] = jz * m.irho;
+  m.A[0] = Ax;
+  m.A[1] = Ay;
+  m.A[2] = Az;
+  const T lEq = (T)p.lEq;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    m.V[k] = m.U[k] + T(0.5) * m.A[k];
+    m.Ue[k] = m.U[k] + lEq * m.A[k];
+    m.b[k] = b[k];
+  }
+  m.tau = (T)p.tau0;
+  m.itau = (T)p.inv_tau0;
+  if (NEED_PI || p.les_K > 0.0) {
+    T sxx = T(0), syy = T(0), szz = T(0), sxy = T(0), sxz = T(0), syz = T(0);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      if (L::ex(q) != 0) sxx += d[q];
+      if (L::ey(q) != 0) syy += d[q];
+      if (L::ez(q) != 0) szz += d[q];
+      if (L::ex(q) * L::ey(q) > 0) sxy += d[q];
+      if (L::ex(q) * L::ey(q) < 0) sxy -= d[q];
+      if (L::ex(q) * L::ez(q) > 0) sxz += d[q];
+      if (L::ex(q) * L::ez(q) < 0) sxz -= d[q];
+      if (L::ey(q) * L::ez(q) > 0) syz += d[q];
+      if (L::ey(q) * L::ez(q) < 0) syz -= d[q];
+    }
+    const T third = drho * T(1.0 / 3.0);
+    const T rho = m.rho;
+    m.pi[0] = sxx - third - rho * m.Ue[0] * m.Ue[0];
+    m.pi[1] = syy - third - rho * m.Ue[1] * m.Ue[1];
+    m.pi[2] = L::D == 3 ? szz - third - rho * m.Ue[2] * m.Ue[2] : T(0);
+    m.pi[3] = sxy - rho * m.Ue[0] * m.Ue[1];
+    m.pi[4] = L::D == 3 ? sxz - rho * m.Ue[0] * m.Ue[2] : T(0);
+    m.pi[5] = L::D == 3 ? syz - rho * m.Ue[1] * m.Ue[2] : T(0);
+    if (MHD) {
+      const T b2h = T(0.5) * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+      m.pi[0] -= b2h - b[0] * b[0];
+      m.pi[1] -= b2h - b[1] * b[1];
+      m.pi[2] -= b2h - b[2] * b[2];
+      m.pi[3] += b[0] * b[1];
+      m.pi[4] += b[0] * b[2];
+      m.pi[5] += b[1] * b[2];
+    }
+    if (p.les_K > 0.0) {
+      // nu_eff = nu0 + (Cs dx)^2 sqrt(2 S:S), S from Eq. (9) at tau_eff:
+      // positive root of tau^2 - tau0 tau - 9 sqrt(2) Cs^2 |Pi|/(2 rho) = 0
+      // (dimensionless form; dx / (c dt) = 1).
+      const T pp = m.pi[0] * m.pi[0] + m.pi[1] * m.pi[1] + m.pi[2] * m.pi[2] +
+                   T(2) * (m.pi[3] * m.pi[3] + m.pi[4] * m.pi[4] + m.pi[5] * m.pi[5]);
+      const T qn = sqrt(pp);
+      const T t0 = (T)p.tau0;
+      m.tau = T(0.5) * (t0 + sqrt(t0 * t0 + (T)p.les_K * qn * m.irho));
+      m.itau = rcp(m.tau);
+    }
+  }
+  m.C = T(1) - (T)p.cG * T(0.5) * m.itau;
+  const T lF = (T)p.lF0 + (T)p.lF1 * m.tau;
+  const T kF = (T)p.kF;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) m.UF[k] = kF * m.U[k] + lF * m.A[k];
+}
+
+// Eq. (2) with the equilibrium of Eq. (1) (+ magnetic part of Eq. 10) and
+// the force term of Section 2 / Eq. (3); d is replaced by d_rel.
+template <class L, class T, bool MHD>
+__device__ __forceinline__ void collide(T (&d)[L::Q], const Macro<T>& m) {
+  const T rho = m.rho;
+  const T usq = T(1.5) * (m.Ue[0] * m.Ue[0] + m.Ue[1] * m.Ue[1] + m.Ue[2] * m.Ue[2]);
+  const T ufa = m.UF[0] * m.A[0] + m.UF[1] * m.A[1] + m.UF[2] * m.A[2];
+  const T cr = m.C * rho;
+  const T itau = m.itau;
+  T b2 = T(0);
+  if (MHD) b2 = m.b[0] * m.b[0] + m.b[1] * m.b[1] + m.b[2] * m.b[2];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const T w = (T)L::w(q);
+    const T eu = edot<L>(q, m.Ue[0], m.Ue[1], m.Ue[2]);
+    T deq = w * (m.drho + rho * (T(3) * eu + T(4.5) * eu * eu - usq));
+    if (MHD) {
+      const T eb = edot<L>(q, m.b[0], m.b[1], m.b[2]);
+      deq += T(4.5) * w * (T(0.5) * b2 * (T)L::e2(q) - eb * eb - b2 * T(1.0 / 6.0));
+    }
+    const T ea = edot<L>(q, m.A[0], m.A[1], m.A[2]);
+    const T euf = edot<L>(q, m.UF[0], m.UF[1], m.UF[2]);
+    const T F = cr * w * (T(3) * (ea - ufa) + T(9) * euf * ea);
+    d[q] = d[q] + (deq - d[q]) * itau + F;
+  }
+}
+
+// Induction lattice: g^eq_{k,i} = W_k [b_i + (e_kj / theta)(V_j b_i - b_j V_i)],
+// stored as deviations from W_k b0_i; relaxation with 1/tau_m.
+template <class T>
+__device__ __forceinline__ void collide_g(T (&h)[7][3], const Macro<T>& m, const Phys& p) {
+  const T itm = (T)p.inv_tau_m;
+  const T b[3] = {m.b[0], m.b[1], m.b[2]};
+  const T V[3] = {m.V[0], m.V[1], m.V[2]};
+  const T b0[3] = {(T)p.b0[0], (T)p.b0[1], (T)p.b0[2]};
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const T w = (T)D3Q7::w(k);
+    const int ax = (k - 1) >> 1;           // axis of direction k (k >= 1)
+    const T sgn = (k & 1) ? T(1) : T(-1);  // +1 for odd k
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T heq = w * (b[i] - b0[i]);
+      if (k > 0) heq += w * sgn * T(1.0 / D3Q7::theta) * (V[ax] * b[i] - b[ax] * V[i]);
+      h[k][i] = h[k][i] + (heq - h[k][i]) * itm;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void tile_sum_store(double (&v)[NV], double* __restrict__ out) {
+  __shared__ double sh[NTHREADS / 64][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = v[k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    v[k] = s;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[wave][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int k = threadIdx.x;
+    out[k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the fused step
+// ---------------------------------------------------------------------------
+template <class L, int P, bool MHD, int PAR, bool DIAG, bool BND>
+__device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const Offs& o, const uint4& rec,
+                                            typename Stor<P>::T (&bal)[NBAL],
+                                            typename Stor<P>::T (&wacc)[MAXBG][NWALL], uint32_t bgrp) {
+  using S = Stor<P>;
+  using T = typename S::T;
+  const Geom& g = a.geo;
+  const uint32_t mask = rec.x;
+  T d[L::Q];
+  read_f<L, P, PAR, BND>((const typename S::E*)a.f, g.Np, n, o, mask, a.p, d);
+  T Ax, Ay, Az;
+  if (a.afield) {
+    const T s = (T)a.p.afield_scale;
+    Ax = (T)a.afield[n] * s;
+    Ay = (T)a.afield[g.N + n] * s;
+    Az = L::D == 3 ? (T)a.afield[2 * (uint64_t)g.N + n] * s : T(0);
+  } else {
+    Ax = (T)a.p.A[0];
+    Ay = (T)a.p.A[1];
+    Az = (T)a.p.A[2];
+  }
+  T h[7][3];
+  T b[3] = {T(0), T(0), T(0)};
+  if (MHD) {
+    read_g<P, PAR, BND>((const typename S::E*)a.g, g.Np, n, o, mask, h);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      T s = (T)a.p.b0[i];
+#pragma unroll
+      for (int k = 0; k < 7; ++k) s += h[k][i];  // B = sum_k g_k
+      b[i] = s;
+    }
+  }
+  Macro<T> m;
+  macro<L, T, MHD, false>(d, a.p, Ax, Ay, Az, b, m);
+  if (DIAG) {
+    bal[0] += m.drho;
+    bal[1] += m.rho * m.U[0];
+    bal[2] += m.rho * m.U[1];
+    bal[3] += m.rho * m.U[2];
+    bal[4] += m.rho * m.A[0];
+    bal[5] += m.rho * m.A[1];
+    bal[6] += m.rho * m.A[2];
+  }
+  collide<L, T, MHD>(d, m);
+  if (BND) {
+    // halfway bounce-back links: the returning population is d_rel plus
+    // the moving-wall term 6 w rho (e_opp . u_w) / c^2; Eq. (25) momentum
+    // exchange per link is proportional to e_q (2 d_rel + ladd) beyond the
+    // constant rest-state part, which the host adds from link counts.
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q) {
+      if ((mask >> q) & 1u) {
+        const uint32_t gr = nibble(rec, q);
+        const T ux = (T)a.uw[3 * gr], uy = (T)a.uw[3 * gr + 1], uz = (T)a.uw[3 * gr + 2];
+        const T ladd = T(-6) * (T)L::w(q) * m.rho * edot<L>(q, ux, uy, uz);
+        const T out = d[q];
+        d[q] = out + ladd;
+        if (DIAG) {
+          const T cq = out + d[q];
+#pragma unroll
+          for (int s = 0; s < MAXBG; ++s) {
+            if (((bgrp >> (4 * s)) & 15u) == gr) {
+              wacc[s][0] += (T)L::ex(q) * cq;
+              wacc[s][1] += (T)L::ey(q) * cq;
+              wacc[s][2] += (T)L::ez(q) * cq;
+              wacc[s][3] += ladd;
+            }
+          }
+        }
+      }
+    }
+  }
+  write_f<L, P, PAR, BND>((typename S::E*)a.f, g.Np, n, o, mask, a.p, d);
+  if (MHD) {
+    collide_g<T>(h, m, a.p);
+    if (BND) {
+      // insulating walls: anti-bounce-back to B = B0 (zero deviation)
+#pragma unroll
+      for (int k = 1; k < 7; ++k)
+        if ((mask >> k) & 1u) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) h[k][i] = -h[k][i];
+        }
+    }
+    write_g<P, PAR, BND>((typename S::E*)a.g, g.Np, n, o, mask, h);
+  }
+}
+
+template <class L, int P, bool MHD, int PAR, bool DIAG>
+__global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
+  using T = typename Stor<P>::T;
+  const Geom& g = a.geo;
+  const uint32_t n = blockIdx.x * NTHREADS + threadIdx.x;
+  const bool active = n < g.N;
+  T bal[NBAL];
+  T wacc[MAXBG][NWALL];
+  if (DIAG) {
+#pragma unroll
+    for (int k = 0; k < NBAL; ++k) bal[k] = T(0);
+#pragma unroll
+    for (int s = 0; s < MAXBG; ++s)
+#pragma unroll
+      for (int k = 0; k < NWALL; ++k) wacc[s][k] = T(0);
+  }
+  const uint32_t bgrp = DIAG ? a.blkgrp[blockIdx.x] : 0u;
+  if (active) {
+    uint32_t x, y, z, r;
+    coords(g, n, x, y, z, r);
+    const Offs o = offsets(g, x, y, z);
+    const int rr = a.rowrec[r];
+    if (rr < 0) {
+      const uint4 rec = make_uint4(0u, 0u, 0u, 0u);
+      node_update<L, P, MHD, PAR, DIAG, false>(a, n, o, rec, bal, wacc, bgrp);
+    } else {
+      const uint4 rec = a.rec[rr + x];
+      if (!(rec.x >> 31)) node_update<L, P, MHD, PAR, DIAG, true>(a, n, o, rec, bal, wacc, bgrp);
+    }
+  }
+  if (DIAG) {
+    double v[NPART];
+#pragma unroll
+    for (int k = 0; k < NBAL; ++k) v[k] = (double)bal[k];
+#pragma unroll
+    for (int s = 0; s < MAXBG; ++s)
+#pragma unroll
+      for (int k = 0; k < NWALL; ++k) v[NBAL + s * NWALL + k] = (double)wacc[s][k];
+    tile_sum_store<NPART>(v, a.part + (uint64_t)blockIdx.x * NPART);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics of the current state (read only)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool node_solid(const DiagArgs& a, uint32_t n) {
+  uint32_t x, y, z, r;
+  coords(a.geo, n, x, y, z, r);
+  const int rr = a.rowrec[r];
+  return rr >= 0 && (a.rec[rr + x].x >> 31);
+}
+
+template <class L, int P, bool MHD, int PAR>
+__global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
+  using S = Stor<P>;
+  using T = typename S::T;
+  const Geom& g = a.geo;
+  const uint32_t n = blockIdx.x * NTHREADS + threadIdx.x;
+  double part[NDIAGPART] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (n < g.N) {
+    uint32_t x, y, z, r;
+    coords(g, n, x, y, z, r);
+    const Offs o = offsets(g, x, y, z);
+    const int rr = a.rowrec[r];
+    const uint4 rec = rr >= 0 ? a.rec[rr + x] : make_uint4(0u, 0u, 0u, 0u);
+    const bool solid = rec.x >> 31;
+    T d[L::Q];
+    T h[7][3];
+    T b[3] = {T(0), T(0), T(0)};
+    Macro<T> m;
+    if (!solid) {
+      read_f<L, P, PAR, true>((const typename S::E*)a.f, g.Np, n, o, rec.x, a.p, d);
+      T Ax, Ay, Az;
+      if (a.afield) {
+        const T s = (T)a.p.afield_scale;
+        Ax = (T)a.afield[n] * s;
+        Ay = (T)a.afield[g.N + n] * s;
+        Az = L::D == 3 ? (T)a.afield[2 * (uint64_t)g.N + n] * s : T(0);
+      } else {
+        Ax = (T)a.p.A[0];
+        Ay = (T)a.p.A[1];
+        Az = (T)a.p.A[2];
+      }
+      if (MHD) {
+        read_g<P, PAR, true>((const typename S::E*)a.g, g.Np, n, o, rec.x, h);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          T s = (T)a.p.b0[i];
+#pragma unroll
+          for (int k = 0; k < 7; ++k) s += h[k][i];
+          b[i] = s;
+        }
+      }
+      macro<L, T, MHD, true>(d, a.p, Ax, Ay, Az, b, m);
+    }
+    if (a.state) {
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) a.state[(uint64_t)q * g.N + n] = solid ? 0.0 : (double)d[q];
+    }
+    if (a.gstate) {
+      // absolute g in units of B (the host rescales by c sqrt(mu))
+#pragma unroll
+      for (int k = 0; k < 7; ++k)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          a.gstate[(uint64_t)(3 * k + i) * g.N + n] = solid ? 0.0 : (double)h[k][i] + D3Q7::w(k) * a.p.b0[i];
+    }
+    if (a.rho) a.rho[n] = solid ? 0.0 : (double)m.rho;
+    if (a.vel) {
+#pragma unroll
+      for (int k = 0; k < L::D; ++k) a.vel[(uint64_t)k * g.N + n] = solid ? 0.0 : (double)m.V[k] * a.c;
+    }
+    if (a.B) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a.B[(uint64_t)k * g.N + n] = solid ? 0.0 : (double)b[k];
+    }
+    // stress and strain rate, Eqs. (8)-(9)
+    double sig[6] = {0, 0, 0, 0, 0, 0}, str[6] = {0, 0, 0, 0, 0, 0};
+    if (!solid) {
+      T Pn[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) Pn[c] = m.pi[c];
+      if (a.artefact) {
+        // E / c^2 = tau rho [(Ue_i A_j + Ue_j A_i) - C (UF_i A_j + UF_j A_i)] (Eq. 9 with Eq. 4)
+        const int ci[6] = {0, 1, 2, 0, 0, 1}, cj[6] = {0, 1, 2, 1, 2, 2};
+        const T thc = (T)a.p.thC * m.C;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const int i = ci[c], j = cj[c];
+          Pn[c] += m.tau * m.rho *
+                   ((m.Ue[i] * m.A[j] + m.Ue[j] * m.A[i]) - thc * (m.UF[i] * m.A[j] + m.UF[j] * m.A[i]));
+        }
+      }
+      const double cS = -3.0 / (2.0 * (double)m.tau * a.dt * (double)m.rho);
+      const double cs = -(1.0 - 0.5 / (double)m.tau) * a.c * a.c;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        str[c] = cS * (double)Pn[c];
+        sig[c] = cs * (double)Pn[c];
+      }
+    }
+    // output order: 2D xx, xy, yy; 3D xx, yy, zz, xy, xz, yz
+    const int map2[3] = {0, 3, 1};
+#pragma unroll
+    for (int c = 0; c < L::NC; ++c) {
+      const int src = L::D == 2 ? map2[c] : c;
+      if (a.sigma) a.sigma[(uint64_t)c * g.N + n] = sig[src];
+      if (a.strain) a.strain[(uint64_t)c * g.N + n] = str[src];
+    }
+    if (a.part && !solid) {
+      part[0] = (double)m.drho;
+      part[1] = (double)(m.rho * m.U[0]);
+      part[2] = (double)(m.rho * m.U[1]);
+      part[3] = (double)(m.rho * m.U[2]);
+      // plane-wall stress integral: weights 3/2 (first layer) and -1/2
+      // (second layer) extrapolate (-p I + sigma) n to the halfway wall
+      const uint32_t pos[3] = {x, y, z};
+      const uint32_t ext[3] = {g.nx, g.ny, g.nz};
+      const int ax_off_p[3] = {o.xp, o.yp, o.zp}, ax_off_m[3] = {o.xm, o.ym, o.zm};
+      const double p_iso = (double)m.rho * a.c * a.c / 3.0;
+      double T3[3][3];
+      const int fi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) T3[i][j] = (i < L::D && j < L::D) ? sig[fi[i][j]] - (i == j ? p_iso : 0.0) : 0.0;
+      for (int ax = 0; ax < L::D; ++ax) {
+        if (ext[ax] < 2) continue;
+        for (int side = 0; side < 2; ++side) {
+          if (!(side == 0 ? a.wall_lo[ax] : a.wall_hi[ax])) continue;
+          const uint32_t l0 = side == 0 ? 0u : ext[ax] - 1, l1 = side == 0 ? 1u : ext[ax] - 2;
+          double wgt = 0.0;
+          uint32_t partner = n;
+          if (pos[ax] == l0) {
+            wgt = 1.5;
+            partner = n + (side == 0 ? ax_off_p[ax] : ax_off_m[ax]);
+          } else if (pos[ax] == l1) {
+            wgt = -0.5;
+            partner = n + (side == 0 ? ax_off_m[ax] : ax_off_p[ax]);
+          }
+          if (wgt == 0.0 || node_solid(a, partner)) continue;
+          const double nrm = side == 0 ? 1.0 : -1.0;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) part[4 + i] += wgt * a.area * T3[i][ax] * nrm;
+        }
+      }
+    }
+  }
+  if (a.part) tile_sum_store<NDIAGPART>(part, a.part + (uint64_t)blockIdx.x * NDIAGPART);
+}
+
+// ---------------------------------------------------------------------------
+// initial state / upload
+// ---------------------------------------------------------------------------
+template <class L, int P, bool MHD>
+__global__ __launch_bounds__(NTHREADS) void k_init(const InitArgs a) {
+  using S = Stor<P>;
+  using T = typename S::T;
+  const Geom& g = a.geo;
+  const uint32_t n = blockIdx.x * NTHREADS + threadIdx.x;
+  if (n >= g.N) return;
+  uint32_t x, y, z, r;
+  coords(g, n, x, y, z, r);
+  const int rr = a.rowrec[r];
+  const bool solid = rr >= 0 && (a.rec[rr + x].x >> 31);
+  typename S::E* f = (typename S::E*)a.f;
+  double U[3] = {0, 0, 0};
+  if (a.u0 && !solid)
+    for (int k = 0; k < L::D; ++k) U[k] = a.u0[(uint64_t)k * g.N + n] * a.inv_c;
+  const double* b0 = a.p.b0;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    double v = 0.0;
+    if (!solid) {
+      if (a.state) {
+        v = a.state[(uint64_t)q * g.N + n];
+      } else {
+        const double w = L::w(q);
+        const double eu = edot<L>(q, U[0], U[1], U[2]);
+        const double usq = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+        v = w * a.p.rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+        if (MHD) {
+          const double eb = edot<L>(q, b0[0], b0[1], b0[2]);
+          const double b2 = b0[0] * b0[0] + b0[1] * b0[1] + b0[2] * b0[2];
+          v += 4.5 * w * (0.5 * b2 * L::e2(q) - eb * eb - b2 / 6.0);
+        }
+      }
+    }
+    T s = (T)v;
+    if (P == S_F16 || P == S_BF16) s = (T)(v * (double)a.p.scale[q]);
+    S::st(f + (uint64_t)q * g.Np + n, s);
+  }
+  if (MHD) {
+    typename S::E* gg = (typename S::E*)a.g;
+    for (int k = 0; k < 7; ++k) {
+      const int ax = (k - 1) >> 1;
+      const double sgn = (k & 1) ? 1.0 : -1.0;
+      for (int i = 0; i < 3; ++i) {
+        double hv = 0.0;
+        if (!solid && k > 0) hv = D3Q7::w(k) * sgn * (1.0 / D3Q7::theta) * (U[ax] * b0[i] - b0[ax] * U[i]);
+        S::st(gg + (uint64_t)(3 * k + i) * g.Np + n, (T)hv);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// deterministic reductions of per-tile partial sums
+// ---------------------------------------------------------------------------
+// mode 0: step partials [ntiles][NPART] -> out[NBAL + MAXG * NWALL]
+// mode 1: diagnostic partials [ntiles][NDIAGPART] -> out[NDIAGPART]
+__global__ __launch_bounds__(NTHREADS) void k_reduce(const double* __restrict__ part, const uint32_t* __restrict__ blkgrp,
+                                                     uint32_t ntiles, int mode, double* __restrict__ out) {
+  const int o = blockIdx.x;
+  double s = 0.0;
+  if (mode == 1) {
+    for (uint32_t t = threadIdx.x; t < ntiles; t += NTHREADS) s += part[(uint64_t)t * NDIAGPART + o];
+  } else if (o < NBAL) {
+    for (uint32_t t = threadIdx.x; t < ntiles; t += NTHREADS) s += part[(uint64_t)t * NPART + o];
+  } else {
+    const uint32_t grp = (o - NBAL) / NWALL, k = (o - NBAL) % NWALL;
+    for (uint32_t t = threadIdx.x; t < ntiles; t += NTHREADS) {
+      const uint32_t bg = blkgrp[t];
+      const uint32_t cnt = bg >> 28;
+      for (uint32_t sl = 0; sl < cnt; ++sl)
+        if (((bg >> (4 * sl)) & 15u) == grp) s += part[(uint64_t)t * NPART + NBAL + sl * NWALL + k];
+    }
+  }
+  double v[1] = {s};
+  tile_sum_store<1>(v, out + o);
+}
+
+// ---------------------------------------------------------------------------
+// launchers (called by the host library)
+// ---------------------------------------------------------------------------
+template <class L, int P, bool MHD>
+static hipError_t launch_step_t(const StepArgs& a, int parity, bool diag, hipStream_t st) {
+  const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
+  if (parity == 0) {
+    if (diag)
+      k_step<L, P, MHD, 0, true><<<nb, NTHREADS, 0, st>>>(a);
+    else
+      k_step<L, P, MHD, 0, false><<<nb, NTHREADS, 0, st>>>(a);
+  } else {
+    if (diag)
+      k_step<L, P, MHD, 1, true><<<nb, NTHREADS, 0, st>>>(a);
+    else
+      k_step<L, P, MHD, 1, false><<<nb, NTHREADS, 0, st>>>(a);
+  }
+  return hipGetLastError();
+}
+
+template <class L, int P, bool MHD>
+static hipError_t launch_diag_t(const DiagArgs& a, hipStream_t st) {
+  const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
+  if (a.parity == 0)
+    k_diag<L, P, MHD, 0><<<nb, NTHREADS, 0, st>>>(a);
+  else
+    k_diag<L, P, MHD, 1><<<nb, NTHREADS, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+template <class L, int P, bool MHD>
+static hipError_t launch_init_t(const InitArgs& a, hipStream_t st) {
+  const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
+  k_init<L, P, MHD><<<nb, NTHREADS, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+#define LBM_DISPATCH(FN, lattice, prec, mhd, ...)                                          \
+  do {                                                                                       \
+    if (lattice == 0) {                                                                      \
+      switch (prec) {                                                                        \
+        case S_F64: return FN<D2Q9, S_F64, false>(__VA_ARGS__);                              \
+        case S_F32: return FN<D2Q9, S_F32, false>(__VA_ARGS__);                              \
+        case S_F16: return FN<D2Q9, S_F16, false>(__VA_ARGS__);                              \
+        default: return FN<D2Q9, S_BF16, false>(__VA_ARGS__);                                \
+      }                                                                                      \
+    } else if (mhd) {                                                                        \
+      if (prec == S_F64) return FN<D3Q19, S_F64, true>(__VA_ARGS__);                         \
+      return FN<D3Q19, S_F32, true>(__VA_ARGS__);                                            \
+    } else {                                                                                 \
+      switch (prec) {                                                                        \
+        case S_F64: return FN<D3Q19, S_F64, false>(__VA_ARGS__);                             \
+        case S_F32: return FN<D3Q19, S_F32, false>(__VA_ARGS__);                             \
+        case S_F16: return FN<D3Q19, S_F16, false>(__VA_ARGS__);                             \
+        default: return FN<D3Q19, S_BF16, false>(__VA_ARGS__);                               \
+      }                                                                                      \
+    }                                                                                        \
+  } while (0)
+
+hipError_t launch_step(int lattice, int prec, bool mhd, const StepArgs& a, int parity, bool diag, hipStream_t st) {
+  LBM_DISPATCH(launch_step_t, lattice, prec, mhd, a, parity, diag, st);
+}
+
+hipError_t launch_diag(int lattice, int prec, bool mhd, const DiagArgs& a, hipStream_t st) {
+  LBM_DISPATCH(launch_diag_t, lattice, prec, mhd, a, st);
+}
+
+hipError_t launch_init(int lattice, int prec, bool mhd, const InitArgs& a, hipStream_t st) {
+  LBM_DISPATCH(launch_init_t, lattice, prec, mhd, a, st);
+}
+
+hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t ntiles, int mode, int nout, double* out,
+                         hipStream_t st) {
+  k_reduce<<<nout, NTHREADS, 0, st>>>(part, blkgrp, ntiles, mode, out);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,88 @@
+// Kernel argument blocks shared by the host library and the device kernels.
+#pragma once
+#include <cstdint>
+
+#include <hip/hip_runtime.h>
+
+namespace lbm {
+
+enum { S_F64 = 0, S_F32 = 1, S_F16 = 2, S_BF16 = 3 };
+constexpr int MAXG = 16;   // wall groups per context
+constexpr int MAXBG = 4;   // distinct wall groups inside one 256-node tile
+constexpr int NTHREADS = 256;
+constexpr int NBAL = 7;                    // sum drho, sum rho U (3), sum rho A (3)
+constexpr int NWALL = 4;                   // sum e (2 d_rel + ladd) (3), sum ladd
+constexpr int NPART = NBAL + MAXBG * NWALL;  // per-tile partial sums on diagnostic steps
+constexpr int NDIAGPART = 8;               // sum drho, sum rho U (3), stress integral (3), pad
+
+// Index geometry.  Nodes are numbered n = (z ny + y) nx + x; plane stride Np.
+struct Geom {
+  uint32_t nx, ny, nz, N;
+  uint64_t Np;
+  uint64_t mnx, mny;  // ceil(2^64 / d) for exact division by nx, ny (unused when d == 1)
+};
+
+// Physical parameters, all dimensionless (velocities in units of c).
+struct Phys {
+  double rho0;
+  double tau0, inv_tau0;
+  double A[3];         // uniform a dt / c
+  double afield_scale; // dt / c, applied to the per-node field a
+  double kF, lF0, lF1, lEq, cG, thC;  // force-model table (see host)
+  double les_K;        // 18 sqrt(2) C_s^2, 0 = no closure
+  double b0[3];        // MHD B0 / (c sqrt(mu))
+  double inv_tau_m;
+  float scale[19], inv_scale[19];  // storage scaling per direction
+};
+
+struct StepArgs {
+  void* f;                 // distributions [Q][Np]
+  void* g;                 // induction deviations [7][3][Np] (MHD) or null
+  const float* afield;     // [3][N] or null
+  const uint4* rec;        // boundary records: x = solid-link mask (bit 31: node solid), y..w = group nibbles
+  const int* rowrec;       // per row: index of the row's first record, or -1
+  const uint32_t* blkgrp;  // per tile: up to MAXBG group labels, 4 bits each, + count in bits 28..31
+  const float* uw;         // [MAXG][3] wall velocity / c
+  double* part;            // [ntiles][NPART] on diagnostic steps
+  Geom geo;
+  Phys p;
+};
+
+// Arguments of the read-only diagnostic kernel.
+struct DiagArgs {
+  const void* f;
+  const void* g;
+  const float* afield;
+  const uint4* rec;
+  const int* rowrec;
+  double* rho;     // [N] or null
+  double* vel;     // [D][N] or null (v = u + dt a / 2, physical units)
+  double* sigma;   // [NC][N] or null
+  double* strain;  // [NC][N] or null
+  double* B;       // [3][N] or null
+  double* state;   // [Q][N] natural-layout deviations or null
+  double* gstate;  // [21][N] absolute induction distributions or null
+  double* part;    // [ntiles][NDIAGPART] or null
+  Geom geo;
+  Phys p;
+  int parity;
+  int artefact;
+  double c, dt;
+  int wall_lo[3], wall_hi[3];  // plane walls present per axis end (stress integral)
+  double area;                 // dx^(D-1)
+};
+
+// Initial-state / upload kernel arguments.
+struct InitArgs {
+  void* f;
+  void* g;
+  const double* u0;    // [D][N] physical u, or null
+  const double* state; // [Q][N] deviations to upload, or null
+  const uint4* rec;
+  const int* rowrec;
+  Geom geo;
+  Phys p;
+  double inv_c;
+};
+
+}  // namespace lbm

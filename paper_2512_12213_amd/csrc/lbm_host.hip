@@ -1,0 +1,804 @@
+// Host side of the C ABI declared in include/lbm.h: validation, geometry ->
+// boundary records, buffer management, step loop, and assembly of the
+// wall-force and balance records in FP64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+namespace lbm {
+hipError_t launch_step(int lattice, int prec, bool mhd, const StepArgs& a, int parity, bool diag, hipStream_t st);
+hipError_t launch_diag(int lattice, int prec, bool mhd, const DiagArgs& a, hipStream_t st);
+hipError_t launch_init(int lattice, int prec, bool mhd, const InitArgs& a, hipStream_t st);
+hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t ntiles, int mode, int nout, double* out,
+                         hipStream_t st);
+}  // namespace lbm
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(LBM_EHIP, "%s: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t b) {
+    if (b <= bytes && p) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, b ? b : 1);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+};
+
+// lattice-generic helpers on the host
+int lat_Q(int lat) { return lat == 0 ? 9 : 19; }
+int lat_D(int lat) { return lat == 0 ? 2 : 3; }
+void lat_e(int lat, int q, int* e) {
+  if (lat == 0) {
+    e[0] = D2Q9::ex(q);
+    e[1] = D2Q9::ey(q);
+    e[2] = 0;
+  } else {
+    e[0] = D3Q19::ex(q);
+    e[1] = D3Q19::ey(q);
+    e[2] = D3Q19::ez(q);
+  }
+}
+double lat_w(int lat, int q) { return lat == 0 ? D2Q9::w(q) : D3Q19::w(q); }
+
+}  // namespace
+
+struct lbm_ctx {
+  int lattice, D, Q, NC;
+  int nx, ny, nz;
+  uint32_t N;
+  uint64_t Np;
+  double tau, dx, dt, c;
+  int model;
+  int prec = S_F32;
+  double rho0 = 1.0;
+  int wall[3][2] = {{-1, -1}, {-1, -1}, {-1, -1}};
+  std::vector<uint8_t> solid;  // 0 fluid, 1 + group
+  double uw[MAXG][3] = {};
+  double a[3] = {0, 0, 0};
+  const float* afield = nullptr;
+  double cs = 0;
+  int artefact = 0;
+  bool mhd = false;
+  double B0[3] = {0, 0, 0}, mu = 1, tau_m = 1;
+  int device = 0;
+  hipStream_t own = nullptr, stream = nullptr;
+
+  // geometry
+  bool geom_ok = false;
+  int G = 1;
+  uint32_t ntiles = 0;
+  uint32_t nfluid = 0;
+  std::vector<long> nlink;  // [MAXG][Q]
+
+  DevBuf f, g, rec, rowrec, blkgrp, uwdev, part, red, dpart, dred, tmp;
+  double* hred = nullptr;  // pinned [NBAL + MAXG * NWALL]
+  bool uw_dirty = true;
+  bool have_state = false;
+  long steps = 0;
+  int parity = 0;
+  bool have_step = false;
+  double last[NBAL + MAXG * NWALL] = {};
+  double last_uw[MAXG][3] = {};
+};
+
+namespace {
+
+Phys make_phys(const lbm_ctx* h) {
+  Phys p = {};
+  p.rho0 = h->rho0;
+  p.tau0 = h->tau;
+  p.inv_tau0 = 1.0 / h->tau;
+  for (int k = 0; k < 3; ++k) p.A[k] = h->a[k] * h->dt / h->c;
+  p.afield_scale = h->dt / h->c;
+  // force-model table: u^F = kF u + (lF0 + lF1 tau) dt a, u^eq = u + lEq dt a,
+  // C = 1 - cG / (2 tau); thC = 1 when Theta follows Eq. (4).
+  switch (h->model) {
+    case LBM_FORCE_HE: p.kF = 0; p.lF0 = 0; p.lF1 = 0; p.lEq = 0; p.cG = 0; p.thC = 0; break;
+    case LBM_FORCE_LUO: p.kF = 1; p.lF0 = 0; p.lF1 = 0; p.lEq = 0; p.cG = 0; p.thC = 1; break;
+    case LBM_FORCE_SHANCHEN: p.kF = 1; p.lF0 = 0; p.lF1 = 0.5; p.lEq = 0; p.cG = 0; p.thC = 1; break;
+    case LBM_FORCE_EDM: p.kF = 1; p.lF0 = 0.5; p.lF1 = 0; p.lEq = 0; p.cG = 0; p.thC = 1; break;
+    default: p.kF = 1; p.lF0 = 0.5; p.lF1 = 0; p.lEq = 0.5; p.cG = 1; p.thC = 1; break;
+  }
+  p.les_K = 18.0 * std::sqrt(2.0) * h->cs * h->cs;
+  const double bs = h->mhd ? 1.0 / (h->c * std::sqrt(h->mu)) : 0.0;
+  for (int k = 0; k < 3; ++k) p.b0[k] = h->B0[k] * bs;
+  p.inv_tau_m = h->mhd ? 1.0 / h->tau_m : 0.0;
+  for (int q = 0; q < 19; ++q) {
+    double s = 1.0;
+    if (q < h->Q) {
+      if (h->prec == S_F16) s = 1024.0 / lat_w(h->lattice, q);
+      if (h->prec == S_BF16) s = 1.0 / lat_w(h->lattice, q);
+    }
+    p.scale[q] = (float)s;
+    p.inv_scale[q] = (float)(1.0 / s);
+  }
+  return p;
+}
+
+Geom make_geom(const lbm_ctx* h) {
+  Geom g = {};
+  g.nx = h->nx;
+  g.ny = h->ny;
+  g.nz = h->nz;
+  g.N = h->N;
+  g.Np = h->Np;
+  g.mnx = h->nx > 1 ? UINT64_MAX / (uint64_t)h->nx + 1 : 0;
+  g.mny = h->ny > 1 ? UINT64_MAX / (uint64_t)h->ny + 1 : 0;
+  return g;
+}
+
+size_t elem_bytes(int prec) { return prec == S_F64 ? 8 : (prec == S_F32 ? 4 : 2); }
+
+// Where does the link from (x,y,z) along e end?  0 = fluid node, 1 = wall or
+// solid (group returned).  Corner links belong to the lowest axis.
+int link_end(const lbm_ctx* h, int x, int y, int z, const int* e, int* grp) {
+  int p[3] = {x + e[0], y + e[1], z + e[2]};
+  const int n[3] = {h->nx, h->ny, h->nz};
+  for (int k = 0; k < 3; ++k) {
+    if (p[k] < 0 || p[k] >= n[k]) {
+      const int side = p[k] < 0 ? 0 : 1;
+      if (h->wall[k][side] >= 0) {
+        *grp = h->wall[k][side];
+        return 1;
+      }
+      p[k] = (p[k] + n[k]) % n[k];
+    }
+  }
+  const uint8_t s = h->solid[((size_t)p[2] * h->ny + p[1]) * h->nx + p[0]];
+  if (s) {
+    *grp = s - 1;
+    return 1;
+  }
+  return 0;
+}
+
+int build_geometry(lbm_ctx* h) {
+  if (h->geom_ok) return LBM_OK;
+  const int Q = h->Q;
+  const size_t rows = (size_t)h->ny * h->nz;
+  std::vector<int> rowrec(rows, -1);
+  std::vector<uint4> recs;
+  std::vector<uint4> rowbuf(h->nx);
+  h->nlink.assign((size_t)MAXG * Q, 0);
+  h->ntiles = (h->N + NTHREADS - 1) / NTHREADS;
+  std::vector<uint32_t> tilegrp(h->ntiles, 0);
+  std::vector<uint32_t> tilemask(h->ntiles, 0);  // bit per group present in the tile
+  int gmax = 0;
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 2; ++s) gmax = std::max(gmax, h->wall[a][s]);
+  for (size_t i = 0; i < h->solid.size(); ++i)
+    if (h->solid[i]) gmax = std::max(gmax, (int)h->solid[i] - 1);
+  h->G = gmax + 1;
+  h->nfluid = 0;
+  for (int z = 0; z < h->nz; ++z)
+    for (int y = 0; y < h->ny; ++y) {
+      bool any = false;
+      for (int x = 0; x < h->nx; ++x) {
+        const size_t n = ((size_t)z * h->ny + y) * h->nx + x;
+        uint4 r = make_uint4(0u, 0u, 0u, 0u);
+        if (h->solid[n]) {
+          r.x = 1u << 31;
+          any = true;
+        } else {
+          ++h->nfluid;
+          for (int q = 1; q < Q; ++q) {
+            int e[3], grp;
+            lat_e(h->lattice, q, e);
+            if (link_end(h, x, y, z, e, &grp)) {
+              r.x |= 1u << q;
+              uint32_t* wv = q < 8 ? &r.y : (q < 16 ? &r.z : &r.w);
+              *wv |= (uint32_t)grp << (4 * (q & 7));
+              h->nlink[(size_t)grp * Q + q]++;
+              tilemask[n / NTHREADS] |= 1u << grp;
+              any = true;
+            }
+          }
+        }
+        rowbuf[x] = r;
+      }
+      if (any) {
+        rowrec[(size_t)z * h->ny + y] = (int)recs.size();
+        recs.insert(recs.end(), rowbuf.begin(), rowbuf.end());
+      }
+    }
+  if (recs.size() > (size_t)INT32_MAX) return fail(LBM_EINVAL, "too many boundary rows");
+  for (uint32_t t = 0; t < h->ntiles; ++t) {
+    uint32_t cnt = 0, packed = 0;
+    for (int gr = 0; gr < MAXG; ++gr)
+      if (tilemask[t] >> gr & 1u) {
+        if (cnt == MAXBG)
+          return fail(LBM_EINVAL, "more than %d wall groups meet within one tile of %d nodes (tile %u)", MAXBG,
+                      NTHREADS, t);
+        packed |= (uint32_t)gr << (4 * cnt);
+        ++cnt;
+      }
+    tilegrp[t] = packed | (cnt << 28);
+  }
+  HIPCHK(h->rowrec.ensure(rows * sizeof(int)));
+  HIPCHK(h->rec.ensure(std::max<size_t>(recs.size(), 1) * sizeof(uint4)));
+  HIPCHK(h->blkgrp.ensure((size_t)h->ntiles * sizeof(uint32_t)));
+  HIPCHK(hipMemcpy(h->rowrec.p, rowrec.data(), rows * sizeof(int), hipMemcpyHostToDevice));
+  if (!recs.empty()) HIPCHK(hipMemcpy(h->rec.p, recs.data(), recs.size() * sizeof(uint4), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(h->blkgrp.p, tilegrp.data(), (size_t)h->ntiles * sizeof(uint32_t), hipMemcpyHostToDevice));
+  HIPCHK(h->part.ensure((size_t)h->ntiles * NPART * sizeof(double)));
+  HIPCHK(h->dpart.ensure((size_t)h->ntiles * NDIAGPART * sizeof(double)));
+  HIPCHK(h->red.ensure((NBAL + MAXG * NWALL) * sizeof(double)));
+  HIPCHK(h->dred.ensure(NDIAGPART * sizeof(double)));
+  HIPCHK(h->uwdev.ensure(MAXG * 3 * sizeof(float)));
+  h->uw_dirty = true;
+  h->geom_ok = true;
+  return LBM_OK;
+}
+
+int alloc_state(lbm_ctx* h) {
+  const size_t eb = elem_bytes(h->prec);
+  HIPCHK(h->f.ensure((size_t)h->Q * h->Np * eb));
+  if (h->mhd) HIPCHK(h->g.ensure((size_t)21 * h->Np * eb));
+  return LBM_OK;
+}
+
+StepArgs step_args(lbm_ctx* h) {
+  StepArgs a = {};
+  a.f = h->f.p;
+  a.g = h->mhd ? h->g.p : nullptr;
+  a.afield = h->afield;
+  a.rec = (const uint4*)h->rec.p;
+  a.rowrec = (const int*)h->rowrec.p;
+  a.blkgrp = (const uint32_t*)h->blkgrp.p;
+  a.uw = (const float*)h->uwdev.p;
+  a.part = (double*)h->part.p;
+  a.geo = make_geom(h);
+  a.p = make_phys(h);
+  return a;
+}
+
+DiagArgs diag_args(lbm_ctx* h) {
+  DiagArgs a = {};
+  a.f = h->f.p;
+  a.g = h->mhd ? h->g.p : nullptr;
+  a.afield = h->afield;
+  a.rec = (const uint4*)h->rec.p;
+  a.rowrec = (const int*)h->rowrec.p;
+  a.geo = make_geom(h);
+  a.p = make_phys(h);
+  a.parity = h->parity;
+  a.artefact = h->artefact;
+  a.c = h->c;
+  a.dt = h->dt;
+  for (int k = 0; k < 3; ++k) {
+    a.wall_lo[k] = h->wall[k][0] >= 0;
+    a.wall_hi[k] = h->wall[k][1] >= 0;
+  }
+  a.area = h->D == 2 ? h->dx : h->dx * h->dx;
+  return a;
+}
+
+double vol(const lbm_ctx* h) { return h->D == 2 ? h->dx * h->dx : h->dx * h->dx * h->dx; }
+
+int check_ready(lbm_ctx* h) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (!h->have_state) return fail(LBM_ESTATE, "no state: call lbm_init_equilibrium or lbm_set_state first");
+  return LBM_OK;
+}
+
+int setup_guard(lbm_ctx* h) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (h->have_state) return fail(LBM_ESTATE, "geometry and storage must be set before the state is initialised");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+lbm_ctx* lbm_create(int lattice, int nx, int ny, int nz, double tau, double dx, double dt, int force_model) {
+  if (lattice != LBM_D2Q9 && lattice != LBM_D3Q19) {
+    fail(LBM_EINVAL, "lattice must be LBM_D2Q9 or LBM_D3Q19");
+    return nullptr;
+  }
+  if (nx < 1 || ny < 1 || nz < 1 || nx > 65536 || ny > 65536 || nz > 65536) {
+    fail(LBM_EINVAL, "sizes must be in [1, 65536]");
+    return nullptr;
+  }
+  if (lattice == LBM_D2Q9 && nz != 1) {
+    fail(LBM_EINVAL, "D2Q9 requires nz == 1");
+    return nullptr;
+  }
+  if (!(tau > 0.5) || !std::isfinite(tau)) {
+    fail(LBM_EINVAL, "tau must be > 1/2 (tau = %g)", tau);
+    return nullptr;
+  }
+  if (!(dx > 0) || !(dt > 0) || !std::isfinite(dx) || !std::isfinite(dt)) {
+    fail(LBM_EINVAL, "dx and dt must be positive");
+    return nullptr;
+  }
+  if (force_model < 0 || force_model > 4) {
+    fail(LBM_EINVAL, "force model must be in [0, 4]");
+    return nullptr;
+  }
+  const uint64_t N = (uint64_t)nx * ny * nz;
+  if (N >= (1ull << 31)) {
+    fail(LBM_EINVAL, "lattice too large: %llu nodes (limit 2^31)", (unsigned long long)N);
+    return nullptr;
+  }
+  lbm_ctx* h = new lbm_ctx();
+  h->lattice = lattice;
+  h->D = lat_D(lattice);
+  h->Q = lat_Q(lattice);
+  h->NC = lattice == 0 ? 3 : 6;
+  h->nx = nx;
+  h->ny = ny;
+  h->nz = nz;
+  h->N = (uint32_t)N;
+  h->Np = (N + 63) & ~(uint64_t)63;  // planes start on 256-byte boundaries for 4-byte storage
+  h->tau = tau;
+  h->dx = dx;
+  h->dt = dt;
+  h->c = dx / dt;
+  h->model = force_model;
+  h->solid.assign(N, 0);
+  if (hipGetDevice(&h->device) != hipSuccess || hipStreamCreate(&h->own) != hipSuccess) {
+    fail(LBM_EHIP, "no HIP device / stream");
+    delete h;
+    return nullptr;
+  }
+  h->stream = h->own;
+  if (hipHostMalloc((void**)&h->hred, (NBAL + MAXG * NWALL + NDIAGPART) * sizeof(double)) != hipSuccess) {
+    fail(LBM_ENOMEM, "pinned host buffer");
+    (void)hipStreamDestroy(h->own);
+    delete h;
+    return nullptr;
+  }
+  return h;
+}
+
+void lbm_destroy(lbm_ctx* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->hred) (void)hipHostFree(h->hred);
+  if (h->own) (void)hipStreamDestroy(h->own);
+  delete h;
+}
+
+int lbm_set_storage(lbm_ctx* h, int precision) {
+  int rc = setup_guard(h);
+  if (rc) return rc;
+  if (precision < LBM_F64 || precision > LBM_BF16) return fail(LBM_EINVAL, "unknown storage precision %d", precision);
+  if (h->mhd && (precision == LBM_F16 || precision == LBM_BF16))
+    return fail(LBM_EINVAL, "MHD supports F32 and F64 storage only");
+  h->prec = precision;
+  h->f.release();
+  h->g.release();
+  return LBM_OK;
+}
+
+int lbm_set_rho0(lbm_ctx* h, double rho0) {
+  int rc = setup_guard(h);
+  if (rc) return rc;
+  if (!(rho0 > 0) || !std::isfinite(rho0)) return fail(LBM_EINVAL, "rho0 must be positive");
+  h->rho0 = rho0;
+  return LBM_OK;
+}
+
+int lbm_add_plane_walls(lbm_ctx* h, int axis, int glo, int ghi) {
+  int rc = setup_guard(h);
+  if (rc) return rc;
+  if (axis < 0 || axis >= h->D) return fail(LBM_EINVAL, "axis %d out of range", axis);
+  if (glo < -1 || glo >= MAXG || ghi < -1 || ghi >= MAXG) return fail(LBM_EINVAL, "group out of range");
+  h->wall[axis][0] = glo;
+  h->wall[axis][1] = ghi;
+  h->geom_ok = false;
+  return LBM_OK;
+}
+
+int lbm_add_solid_mask(lbm_ctx* h, const unsigned char* mask, int group) {
+  int rc = setup_guard(h);
+  if (rc) return rc;
+  if (!mask) return fail(LBM_EINVAL, "null mask");
+  if (group < 0 || group >= MAXG) return fail(LBM_EINVAL, "group out of range");
+  for (uint32_t i = 0; i < h->N; ++i)
+    if (mask[i]) h->solid[i] = (uint8_t)(1 + group);
+  h->geom_ok = false;
+  return LBM_OK;
+}
+
+int lbm_set_wall_velocity(lbm_ctx* h, int group, double ux, double uy, double uz) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (group < 0 || group >= MAXG) return fail(LBM_EINVAL, "group out of range");
+  if (!std::isfinite(ux) || !std::isfinite(uy) || !std::isfinite(uz)) return fail(LBM_EINVAL, "non-finite velocity");
+  h->uw[group][0] = ux;
+  h->uw[group][1] = uy;
+  h->uw[group][2] = h->D == 3 ? uz : 0.0;
+  h->uw_dirty = true;
+  return LBM_OK;
+}
+
+int lbm_set_body_force(lbm_ctx* h, double ax, double ay, double az) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (!std::isfinite(ax) || !std::isfinite(ay) || !std::isfinite(az)) return fail(LBM_EINVAL, "non-finite force");
+  h->a[0] = ax;
+  h->a[1] = ay;
+  h->a[2] = h->D == 3 ? az : 0.0;
+  return LBM_OK;
+}
+
+int lbm_set_body_force_field(lbm_ctx* h, const void* dev_ptr) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  h->afield = (const float*)dev_ptr;
+  return LBM_OK;
+}
+
+int lbm_set_les(lbm_ctx* h, double cs) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (!(cs >= 0) || !std::isfinite(cs)) return fail(LBM_EINVAL, "C_s must be >= 0");
+  h->cs = cs;
+  return LBM_OK;
+}
+
+int lbm_set_artefact(lbm_ctx* h, int on) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  h->artefact = on ? 1 : 0;
+  return LBM_OK;
+}
+
+int lbm_set_mhd(lbm_ctx* h, double B0x, double B0y, double B0z, double mu, double tau_m) {
+  int rc = setup_guard(h);
+  if (rc) return rc;
+  if (h->lattice != LBM_D3Q19) return fail(LBM_EINVAL, "MHD requires D3Q19");
+  if (h->prec == S_F16 || h->prec == S_BF16) return fail(LBM_EINVAL, "MHD supports F32 and F64 storage only");
+  if (!(mu > 0) || !(tau_m > 0.5)) return fail(LBM_EINVAL, "need mu > 0 and tau_m > 1/2");
+  h->mhd = true;
+  h->B0[0] = B0x;
+  h->B0[1] = B0y;
+  h->B0[2] = B0z;
+  h->mu = mu;
+  h->tau_m = tau_m;
+  return LBM_OK;
+}
+
+int lbm_set_stream(lbm_ctx* h, void* s) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  h->stream = s ? (hipStream_t)s : h->own;
+  return LBM_OK;
+}
+
+int lbm_init_equilibrium(lbm_ctx* h, const double* u0) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  int rc = build_geometry(h);
+  if (rc) return rc;
+  rc = alloc_state(h);
+  if (rc) return rc;
+  InitArgs a = {};
+  a.f = h->f.p;
+  a.g = h->mhd ? h->g.p : nullptr;
+  a.rec = (const uint4*)h->rec.p;
+  a.rowrec = (const int*)h->rowrec.p;
+  a.geo = make_geom(h);
+  a.p = make_phys(h);
+  a.inv_c = 1.0 / h->c;
+  if (u0) {
+    HIPCHK(h->tmp.ensure((size_t)h->D * h->N * sizeof(double)));
+    HIPCHK(hipMemcpyAsync(h->tmp.p, u0, (size_t)h->D * h->N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    a.u0 = (const double*)h->tmp.p;
+  }
+  HIPCHK(launch_init(h->lattice, h->prec, h->mhd, a, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->have_state = true;
+  h->steps = 0;
+  h->parity = 0;
+  h->have_step = false;
+  return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx* h, const double* d) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (!d) return fail(LBM_EINVAL, "null state");
+  int rc = build_geometry(h);
+  if (rc) return rc;
+  rc = alloc_state(h);
+  if (rc) return rc;
+  InitArgs a = {};
+  a.f = h->f.p;
+  a.g = h->mhd ? h->g.p : nullptr;
+  a.rec = (const uint4*)h->rec.p;
+  a.rowrec = (const int*)h->rowrec.p;
+  a.geo = make_geom(h);
+  a.p = make_phys(h);
+  a.inv_c = 1.0 / h->c;
+  HIPCHK(h->tmp.ensure((size_t)h->Q * h->N * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(h->tmp.p, d, (size_t)h->Q * h->N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  a.state = (const double*)h->tmp.p;
+  HIPCHK(launch_init(h->lattice, h->prec, h->mhd, a, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->have_state = true;
+  h->steps = 0;
+  h->parity = 0;
+  h->have_step = false;
+  return LBM_OK;
+}
+
+static int run_diag(lbm_ctx* h, DiagArgs& a) {
+  HIPCHK(launch_diag(h->lattice, h->prec, h->mhd, a, h->stream));
+  return LBM_OK;
+}
+
+int lbm_get_state(lbm_ctx* h, double* d) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!d) return fail(LBM_EINVAL, "null buffer");
+  const size_t bytes = (size_t)h->Q * h->N * sizeof(double);
+  HIPCHK(h->tmp.ensure(bytes));
+  DiagArgs a = diag_args(h);
+  a.state = (double*)h->tmp.p;
+  rc = run_diag(h, a);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(d, h->tmp.p, bytes, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_get_induction(lbm_ctx* h, double* gout) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!h->mhd) return fail(LBM_ESTATE, "MHD is not enabled");
+  if (!gout) return fail(LBM_EINVAL, "null buffer");
+  const size_t bytes = (size_t)21 * h->N * sizeof(double);
+  HIPCHK(h->tmp.ensure(bytes));
+  DiagArgs a = diag_args(h);
+  a.gstate = (double*)h->tmp.p;
+  rc = run_diag(h, a);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(gout, h->tmp.p, bytes, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const double s = h->c * std::sqrt(h->mu);
+  for (size_t i = 0; i < (size_t)21 * h->N; ++i) gout[i] *= s;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* h, int n) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (n < 0) return fail(LBM_EINVAL, "negative step count");
+  if (n == 0) return LBM_OK;
+  if (h->uw_dirty) {
+    float t[MAXG * 3];
+    for (int gr = 0; gr < MAXG; ++gr)
+      for (int k = 0; k < 3; ++k) t[3 * gr + k] = (float)(h->uw[gr][k] / h->c);
+    HIPCHK(hipMemcpy(h->uwdev.p, t, sizeof(t), hipMemcpyHostToDevice));
+    h->uw_dirty = false;
+  }
+  StepArgs a = step_args(h);
+  for (int i = 0; i < n; ++i) {
+    const bool diag = i == n - 1;
+    HIPCHK(launch_step(h->lattice, h->prec, h->mhd, a, h->parity, diag, h->stream));
+    h->parity ^= 1;
+  }
+  HIPCHK(launch_reduce((const double*)h->part.p, (const uint32_t*)h->blkgrp.p, h->ntiles, 0, NBAL + MAXG * NWALL,
+                       (double*)h->red.p, h->stream));
+  HIPCHK(hipMemcpyAsync(h->hred, h->red.p, (NBAL + MAXG * NWALL) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  std::memcpy(h->last, h->hred, sizeof(h->last));
+  std::memcpy(h->last_uw, h->uw, sizeof(h->last_uw));
+  h->steps += n;
+  h->have_step = true;
+  if (!std::isfinite(h->last[0])) return fail(LBM_EUNSTABLE, "total mass is not finite after step %ld", h->steps);
+  return LBM_OK;
+}
+
+int lbm_get_macro(lbm_ctx* h, double* rho, double* v) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  const size_t N = h->N;
+  HIPCHK(h->tmp.ensure((1 + (size_t)h->D) * N * sizeof(double)));
+  DiagArgs a = diag_args(h);
+  double* base = (double*)h->tmp.p;
+  a.rho = rho ? base : nullptr;
+  a.vel = v ? base + N : nullptr;
+  rc = run_diag(h, a);
+  if (rc) return rc;
+  if (rho) HIPCHK(hipMemcpyAsync(rho, base, N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (v) HIPCHK(hipMemcpyAsync(v, base + N, (size_t)h->D * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_get_field_B(lbm_ctx* h, double* B) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!h->mhd) return fail(LBM_ESTATE, "MHD is not enabled");
+  const size_t N = h->N;
+  HIPCHK(h->tmp.ensure(3 * N * sizeof(double)));
+  DiagArgs a = diag_args(h);
+  a.B = (double*)h->tmp.p;
+  rc = run_diag(h, a);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(B, h->tmp.p, 3 * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const double s = h->c * std::sqrt(h->mu);
+  for (size_t i = 0; i < 3 * N; ++i) B[i] *= s;
+  return LBM_OK;
+}
+
+int lbm_stress(lbm_ctx* h, double* sigma, double* strain) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  const size_t N = h->N, nc = h->NC;
+  HIPCHK(h->tmp.ensure(2 * nc * N * sizeof(double)));
+  DiagArgs a = diag_args(h);
+  double* base = (double*)h->tmp.p;
+  a.sigma = sigma ? base : nullptr;
+  a.strain = strain ? base + nc * N : nullptr;
+  rc = run_diag(h, a);
+  if (rc) return rc;
+  if (sigma) HIPCHK(hipMemcpyAsync(sigma, base, nc * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (strain) HIPCHK(hipMemcpyAsync(strain, base + nc * N, nc * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+// Wall-force variants per group from the last step's FP64 sums plus the
+// constant per-link parts (rest-state pressure, Maxwell stress at B0).
+static void wall_variants(const lbm_ctx* h, int gr, double out[4][3]) {
+  const double fscale = vol(h) * h->c / h->dt;  // (dx^D / dt) c
+  const double* s = h->last + NBAL + gr * NWALL;
+  double raw[3], mf[3], mx[3] = {0, 0, 0};
+  double stat[3] = {0, 0, 0};
+  const double b = h->mhd ? 1.0 / (h->c * std::sqrt(h->mu)) : 0.0;
+  const double bb[3] = {h->B0[0] * b, h->B0[1] * b, h->B0[2] * b};
+  const double b2 = bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
+  for (int q = 1; q < h->Q; ++q) {
+    const long nl = h->nlink[(size_t)gr * h->Q + q];
+    if (!nl) continue;
+    int e[3];
+    lat_e(h->lattice, q, e);
+    const double w = lat_w(h->lattice, q);
+    double phi = 0.0;
+    if (h->mhd) {
+      const double eb = e[0] * bb[0] + e[1] * bb[1] + e[2] * bb[2];
+      const double e2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+      phi = 4.5 * w * (0.5 * b2 * e2 - eb * eb - b2 / 6.0);
+    }
+    for (int k = 0; k < 3; ++k) {
+      stat[k] += (double)nl * 2.0 * w * h->rho0 * e[k];
+      mx[k] += -(double)nl * 2.0 * e[k] * phi;
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    raw[k] = fscale * (s[k] + stat[k]);
+    mf[k] = fscale * (h->last_uw[gr][k] / h->c) * s[3];
+    mx[k] *= fscale;
+    out[0][k] = raw[k];
+    out[1][k] = raw[k] + mf[k];
+    out[2][k] = raw[k] + mx[k];
+    out[3][k] = raw[k] + mf[k] + mx[k];
+  }
+}
+
+int lbm_wall_force(lbm_ctx* h, double* out) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!h->have_step) return fail(LBM_ESTATE, "no step taken yet");
+  if (!out) return fail(LBM_EINVAL, "null buffer");
+  for (int gr = 0; gr < h->G; ++gr) {
+    double v[4][3];
+    wall_variants(h, gr, v);
+    for (int var = 0; var < 4; ++var)
+      for (int k = 0; k < 3; ++k) out[(gr * 4 + var) * 3 + k] = v[var][k];
+  }
+  return LBM_OK;
+}
+
+int lbm_force_balance(lbm_ctx* h, double* out) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!h->have_step) return fail(LBM_ESTATE, "no step taken yet");
+  if (!out) return fail(LBM_EINVAL, "null buffer");
+  DiagArgs a = diag_args(h);
+  a.part = (double*)h->dpart.p;
+  rc = run_diag(h, a);
+  if (rc) return rc;
+  HIPCHK(launch_reduce((const double*)h->dpart.p, nullptr, h->ntiles, 1, NDIAGPART, (double*)h->dred.p, h->stream));
+  double* dr = h->hred + NBAL + MAXG * NWALL;
+  HIPCHK(hipMemcpyAsync(dr, h->dred.p, NDIAGPART * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const double V = vol(h), c = h->c, dt = h->dt;
+  const double M1 = V * ((double)h->nfluid * h->rho0 + dr[0]);
+  const double M0 = V * ((double)h->nfluid * h->rho0 + h->last[0]);
+  std::memset(out, 0, sizeof(double) * LBM_NREC);
+  double Fraw[3] = {0, 0, 0}, Fmf[3] = {0, 0, 0}, Fmx[3] = {0, 0, 0};
+  for (int gr = 0; gr < h->G; ++gr) {
+    double v[4][3];
+    wall_variants(h, gr, v);
+    for (int k = 0; k < 3; ++k) {
+      Fraw[k] += v[0][k];
+      Fmf[k] += v[1][k] - v[0][k];
+      Fmx[k] += v[2][k] - v[0][k];
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    const double bt = V * c / dt * h->last[4 + k];
+    const double dP = V * c * (dr[1 + k] - h->last[1 + k]) / dt;
+    out[0 + k] = Fraw[k];
+    out[3 + k] = bt;
+    out[6 + k] = dP;
+    out[9 + k] = bt - Fraw[k] - dP;
+    out[12 + k] = Fmx[k];
+    out[15 + k] = Fmf[k];
+    out[18 + k] = dr[4 + k];
+  }
+  out[21] = M1;
+  out[22] = V * (dr[0] - h->last[0]);
+  out[23] = (double)h->steps;
+  (void)M0;
+  return LBM_OK;
+}
+
+int lbm_num_groups(lbm_ctx* h) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (!h->geom_ok) {
+    int rc = build_geometry(h);
+    if (rc) return rc;
+  }
+  return h->G;
+}
+
+long lbm_link_count(lbm_ctx* h, int group) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (!h->geom_ok) {
+    int rc = build_geometry(h);
+    if (rc) return rc;
+  }
+  long s = 0;
+  for (int gr = 0; gr < MAXG; ++gr) {
+    if (group >= 0 && gr != group) continue;
+    for (int q = 0; q < h->Q; ++q) s += h->nlink[(size_t)gr * h->Q + q];
+  }
+  return s;
+}
+
+long lbm_steps_taken(lbm_ctx* h) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  return h->steps;
+}
+
+}  // extern "C"

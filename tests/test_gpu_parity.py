@@ -1,0 +1,203 @@
+"""GPU (HIP, gfx950) path against the CPU oracle, element by element.
+
+Tolerances (relative, max-norm over the field, Z22-style metric
+max|X - X_ref| / max|X_ref|): FP64 storage 1e-12; FP32 storage 1e-5 on
+fields and 1e-4 on wall forces; 16-bit storage 2e-3.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from closed_forms import channel_recurrence
+from helpers import make_oracle, rel_inf
+from paper_2512_12213_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_FIELD = {W.F64: 1e-12, W.F32: 1e-5, W.F16: 2e-3, W.BF16: 2e-3}
+TOL_WALL = {W.F64: 1e-12, W.F32: 1e-4, W.F16: 2e-3, W.BF16: 2e-3}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_2512_12213_amd import lbm as L
+    L.lib()
+    return L
+
+
+def gpu_from(w, lbm, storage=None, u0=None, init=True):
+    return lbm.from_workload(w, storage=storage, u0=u0, init=init)
+
+
+def compare_all(g, o, storage, groups, what=""):
+    rg, vg = g.get_macro()
+    ro, vo = o.get_macro()
+    tf = TOL_FIELD[storage]
+    e_rho = np.abs(rg - ro).max()
+    e_v = rel_inf(vg, vo)
+    sg, Sg = g.stress()
+    so, So = o.stress()
+    e_s = rel_inf(sg, so)
+    e_S = rel_inf(Sg, So)
+    fg = g.wall_force()[:groups]
+    fo = o.wall_force(groups)
+    e_f = max(np.linalg.norm(fg[k, var] - fo[k, var]) / max(np.linalg.norm(fo[k, var]), 1e-300)
+              for k in range(groups) for var in range(4) if np.linalg.norm(fo[k, var]) > 0)
+    say("%s rho %.2e v %.2e sigma %.2e S %.2e wall %.2e" % (what, e_rho, e_v, e_s, e_S, e_f))
+    assert e_rho <= tf
+    assert e_v <= tf
+    assert e_s <= tf
+    assert e_S <= tf
+    assert e_f <= TOL_WALL[storage]
+    return dict(rho=e_rho, v=e_v, sigma=e_s, strain=e_S, wall=e_f)
+
+
+@pytest.mark.parametrize("model", [0, 1, 2, 3, 4])
+def test_poiseuille_fp64_5000_steps(lbm, model):
+    """Force-driven D2Q9 channel 64x32, FP64, 5000 steps: GPU vs oracle and
+    vs the exact class-sum recurrence."""
+    w = W.poiseuille(model=model)
+    say("case poiseuille model", model)
+    g = gpu_from(w, lbm)
+    o = make_oracle(w)
+    g.step(w.steps)
+    o.step(w.steps)
+    compare_all(g, o, W.F64, 2, "poiseuille")
+    _, v = g.get_macro()
+    assert rel_inf(v[0, 0, :, 0], channel_recurrence(w.ny, w.tau, 1e-6, w.steps)) < 1e-12
+    bg, bo = g.force_balance(), o.force_balance()
+    assert abs(bg[9]) < 1e-12 * bg[3] and abs(bg[22]) < 1e-12 * bg[21]
+    assert rel_inf(bg[[0, 1, 3, 4, 6, 7, 18, 19, 21]], bo[[0, 1, 3, 4, 6, 7, 18, 19, 21]]) < 1e-12
+
+
+STORAGES = [W.F64, W.F32, W.F16, W.BF16]
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+@pytest.mark.parametrize("model", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("lattice", [W.D2Q9, W.D3Q19])
+def test_random_state_two_steps(lbm, lattice, model, storage):
+    """Two steps (both A-A parities) from an arbitrary seeded state on a
+    ragged lattice with plane walls, a moving wall, a solid body, LES and a
+    non-unity dx, dt: every term of the step is exercised."""
+    if lattice == W.D2Q9:
+        nx, ny, nz = 37, 19, 1
+        mask = W.cylinder_mask(nx, ny, 12.3, 9.1, 3.2)
+        walls = ((1, 0, 1),)
+    else:
+        nx, ny, nz = 21, 13, 11
+        mask = W.sphere_mask(nx, ny, nz, 9.4, 6.2, 5.1, 2.6)
+        walls = ((1, 0, 1), (2, 2, 3))
+    w = W.Workload("random", lattice, nx, ny, nz, 0.62, dx=0.5, dt=0.2, model=model, storage=storage,
+                   body_force=(0.05, -0.02, 0.03), walls=walls, wall_velocity=((1, 0.08, 0.0, 0.03),),
+                   obstacle=None, les_cs=0.1, groups=5)
+    Q = 9 if lattice == W.D2Q9 else 19
+    say("case random", lattice, model, storage)
+    d0 = W.random_state(Q, nx, ny, nz, 2e-3, seed=17) * (1 - mask[None])
+    g = gpu_from(w, lbm, init=False)
+    g.add_solid_mask(mask, 4)
+    g.set_state(d0)
+    o = make_oracle(w, init=False)
+    o.set_solid(mask, 4)
+    o.groups = 5
+    o.set_state(d0)
+    for k in range(2):
+        g.step(1)
+        o.step(1)
+        st = rel_inf(g.get_state(), o.get_state())
+        say("  step", k + 1, "state err %.2e" % st)
+        assert st <= TOL_FIELD[storage]
+        compare_all(g, o, storage, 5, "  step %d" % (k + 1))
+    g.set_artefact(True)
+    o.set_artefact(True)
+    sg, Sg = g.stress()
+    so, So = o.stress()
+    assert rel_inf(sg, so) <= TOL_FIELD[storage] and rel_inf(Sg, So) <= TOL_FIELD[storage]
+
+
+def test_couette_cylinder_fp32(lbm):
+    """D2Q9 Couette + force + cylinder (reduced 128x32 version, 3000 steps),
+    FP32 storage vs FP64 oracle; the momentum-flux correction vanishes."""
+    w = W.couette_cylinder(nx=128, ny=32, r=6.0, cx=32.0, cy=16.0, steps=3000)
+    g = gpu_from(w, lbm)
+    o = make_oracle(w)
+    g.step(w.steps)
+    o.step(w.steps)
+    compare_all(g, o, W.F32, 3, "couette")
+    fw = g.wall_force()
+    assert np.abs(fw[:, 1] - fw[:, 0]).max() < 1e-6 * np.abs(fw[:, 0]).max()
+
+
+@pytest.mark.parametrize("storage", STORAGES)
+def test_duct_les_small(lbm, storage):
+    """Square duct with Smagorinsky closure and seeded +-1e-3 initial
+    velocity (reduced 40x24x20, 300 steps), every storage vs FP64 oracle."""
+    w = W.duct_les(nx=40, ny=24, nz=20, steps=300)
+    say("case duct", storage)
+    g = gpu_from(w, lbm, storage=storage)
+    o = make_oracle(w)
+    g.step(w.steps)
+    o.step(w.steps)
+    compare_all(g, o, storage, 4, "duct %d" % storage)
+
+
+def test_duct_les_full_size_fp32(lbm):
+    """256x128x128 duct with LES, FP32, in the bench's launch configuration:
+    4 steps from the seeded start, full-field comparison."""
+    w = W.duct_les()
+    say("case duct full size")
+    g = gpu_from(w, lbm)
+    o = make_oracle(w)
+    for k in range(2):
+        g.step(2)
+        o.step(2)
+    compare_all(g, o, W.F32, 4, "duct full")
+    bg = g.force_balance()
+    assert np.abs(bg[9:12]).max() < 1e-4 * abs(bg[3])
+
+
+def test_mhd_small(lbm):
+    """Hartmann duct (reduced 12x16x12, 200 steps), FP32 and FP64 storage."""
+    for storage in (W.F64, W.F32):
+        w = W.hartmann_duct(nx=12, ny=16, nz=12, steps=200)
+        say("case mhd", storage)
+        g = gpu_from(w, lbm, storage=storage)
+        o = make_oracle(w)
+        g.step(w.steps)
+        o.step(w.steps)
+        compare_all(g, o, storage, 4, "mhd %d" % storage)
+        Bg = g.get_field_B()
+        _, _, Bo = o.get_macro(with_B=True)
+        assert rel_inf(Bg - np.array(w.mhd[:3])[:, None, None, None],
+                       Bo - np.array(w.mhd[:3])[:, None, None, None]) <= max(TOL_FIELD[storage], 1e-4)
+        rg, ro = g.force_balance(), o.force_balance()
+        assert abs(rg[12:15] - ro[12:15]).max() <= 1e-10 * max(np.abs(ro[12:15]).max(), 1.0)
+
+
+def test_determinism(lbm):
+    w = W.duct_sphere(nx=32, ny=16, nz=16, r=3.0)
+    outs = []
+    for _ in range(2):
+        g = gpu_from(w, lbm)
+        g.step(37)
+        outs.append((g.get_state(), g.wall_force(), g.force_balance()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_unstable_state_is_reported(lbm):
+    w = W.poiseuille(nx=8, ny=8)
+    g = gpu_from(w, lbm, init=False)
+    d = np.zeros((9, 1, 8, 8))
+    d[3, 0, 4, 4] = np.nan
+    g.set_state(d)
+    with pytest.raises(lbm.LBMError) as ei:
+        g.step(3)
+    assert ei.value.code == lbm.LBM_EUNSTABLE
