@@ -255,13 +255,13 @@ static real edot(const orc* o, int q, const real* v) {
   return s;
 }
 
-/* Equilibrium of Eq. (1), as a deviation from w*rho0. */
-static real feq_dev(const orc* o, int q, real rho, const real* u) {
+/* Equilibrium of Eq. (1), as a deviation from w*rho0; drho = rho - rho0. */
+static real feq_dev(const orc* o, int q, real rho, real drho, const real* u) {
   const double c2 = o->c * o->c;
   real eu = edot(o, q, u);
   real uu = 0;
   for (int k = 0; k < o->D; ++k) uu += u[k] * u[k];
-  return o->w[q] * ((rho - o->rho0) + rho * (3.0 * eu / c2 + 4.5 * eu * eu / (c2 * c2) - 1.5 * uu / c2));
+  return o->w[q] * (drho + rho * (3.0 * eu / c2 + 4.5 * eu * eu / (c2 * c2) - 1.5 * uu / c2));
 }
 
 /* Magnetic part of the MHD equilibrium, Eq. (10) (three-dimensional form). */
@@ -289,7 +289,7 @@ static real body_force(const orc* o, long idx, int k) {
 
 /* Per-node state needed by the collision and by the diagnostics. */
 typedef struct {
-  real rho, u[3], v[3], a[3], ueq[3], uF[3], B[3];
+  real rho, drho, u[3], v[3], a[3], ueq[3], uF[3], B[3];
   real C;      /* force-term coefficient */
   real tau;    /* relaxation time in use (Smagorinsky or molecular) */
   real Pi[3][3]; /* non-equilibrium second moment, Pi^neq */
@@ -302,13 +302,16 @@ static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, n
   const int D = o->D, Q = o->Q;
   const double c = o->c, c2 = c * c, dt = o->dt;
   memset(s, 0, sizeof(*s));
-  /* rho = sum f, rho u = sum e f (Section 2) */
-  real rho = o->rho0, j[3] = {0, 0, 0};
+  /* rho = sum f, rho u = sum e f (Section 2); with f = d + w rho0 and
+   * sum w = 1, rho - rho0 = sum d exactly, which is kept as such */
+  real drho = 0, j[3] = {0, 0, 0};
   for (int q = 0; q < Q; ++q) {
-    rho += dl[q];
+    drho += dl[q];
     for (int k = 0; k < D; ++k) j[k] += (real)(c * o->e[q][k]) * dl[q];
   }
+  real rho = o->rho0 + drho;
   s->rho = rho;
+  s->drho = drho;
   for (int k = 0; k < 3; ++k) {
     s->u[k] = k < D ? j[k] / rho : 0;
     s->a[k] = k < D ? body_force(o, idx, k) : 0;
@@ -331,7 +334,7 @@ static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, n
     for (int k = 0; k < D; ++k) {
       real m = 0;
       for (int q = 0; q < Q; ++q) m += (real)(c2 * o->e[q][i] * o->e[q][k]) * dl[q];
-      real eqm = (i == k ? (rho - o->rho0) * c2 / 3.0 : 0.0) + rho * s->ueq[i] * s->ueq[k];
+      real eqm = (i == k ? drho * c2 / 3.0 : 0.0) + rho * s->ueq[i] * s->ueq[k];
       if (o->mhd) eqm += maxwell(o, i, k, s->B);
       s->Pi[i][k] = m - eqm;
     }
@@ -377,7 +380,7 @@ static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, n
       /* original exact-difference form: F = feq(rho, u + dt a) - feq(rho, u) */
       real us[3];
       for (int k = 0; k < 3; ++k) us[k] = s->u[k] + dt * s->a[k];
-      s->F[q] = feq_dev(o, q, rho, us) - feq_dev(o, q, rho, s->u);
+      s->F[q] = feq_dev(o, q, rho, drho, us) - feq_dev(o, q, rho, drho, s->u);
     } else {
       s->F[q] = 0; /* original Shan-Chen: no force term */
     }
@@ -429,7 +432,7 @@ int orc_init_equilibrium(orc* o, const double* u0) {
       for (int k = 0; k < o->D; ++k) u[k] = u0[(long)k * N + i];
     real B[3] = {o->B0[0], o->B0[1], o->B0[2]};
     for (int q = 0; q < o->Q; ++q) {
-      real v = o->solid[i] ? 0 : feq_dev(o, q, o->rho0, u);
+      real v = o->solid[i] ? 0 : feq_dev(o, q, o->rho0, 0.0, u);
       if (o->mhd && !o->solid[i]) v += phi_mhd(o, q, B);
       o->d[(long)q * N + i] = v;
     }
@@ -505,7 +508,7 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
 
   /* relaxation, Eq. (2): f_rel = f + (f^eq - f)/tau + F */
   for (int q = 0; q < Q; ++q) {
-    real deq = feq_dev(o, q, s.rho, s.ueq);
+    real deq = feq_dev(o, q, s.rho, s.drho, s.ueq);
     if (o->mhd) deq += phi_mhd(o, q, s.B);
     drel[q] = dl[q] + (deq - dl[q]) / s.tau + s.F[q];
   }
