@@ -48,6 +48,7 @@ def _lib(complex_step: bool):
         lib.orc_init_equilibrium.argtypes = [P, dp]
         lib.orc_set_state.argtypes = [P, dp, dp]
         lib.orc_get_state.argtypes = [P, dp, dp]
+        lib.orc_replace_state.argtypes = [P, dp]
         lib.orc_get_induction.argtypes = [P, dp]
         lib.orc_step.argtypes = [P, C.c_int]
         lib.orc_get_macro.argtypes = [P, dp, dp, dp]
@@ -144,10 +145,13 @@ class Oracle:
     def init_equilibrium(self, u0=None):
         self._chk(self.lib.orc_init_equilibrium(self.h, _dp(_f64(u0))))
 
-    def set_state(self, d, d_im=None):
+    def set_state(self, d, d_im=None, keep_records=False):
         d = _f64(d)
         assert d.size == self.Q * self.N
-        self._chk(self.lib.orc_set_state(self.h, _dp(d), _dp(_f64(d_im))))
+        if keep_records:
+            self._chk(self.lib.orc_replace_state(self.h, _dp(d)))
+        else:
+            self._chk(self.lib.orc_set_state(self.h, _dp(d), _dp(_f64(d_im))))
 
     def get_state(self, imag=False):
         d = np.empty((self.Q, self.nz, self.ny, self.nx))

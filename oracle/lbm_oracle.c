@@ -458,6 +458,12 @@ int orc_set_state(orc* o, const double* d, const double* d_im) {
   return 0;
 }
 
+/* Replace the state without forgetting the records of the last step. */
+int orc_replace_state(orc* o, const double* d) {
+  for (long i = 0; i < (long)o->Q * o->N; ++i) o->d[i] = MK(d[i], 0.0);
+  return 0;
+}
+
 int orc_get_state(const orc* o, double* d, double* d_im) {
   for (long i = 0; i < (long)o->Q * o->N; ++i) {
     d[i] = RE(o->d[i]);

@@ -54,6 +54,7 @@ int orc_set_mhd(orc* o, double B0x, double B0y, double B0z, double mu, double ta
 int orc_init_equilibrium(orc* o, const double* u0);   /* u0 [D][N] or NULL */
 int orc_set_state(orc* o, const double* d, const double* d_im);   /* [Q][N] deviations */
 int orc_get_state(const orc* o, double* d, double* d_im);
+int orc_replace_state(orc* o, const double* d);            /* keeps the last-step records */
 int orc_get_induction(const orc* o, double* g);                   /* [7][3][N] */
 
 int orc_step(orc* o, int n);

@@ -246,6 +246,9 @@ __device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, uin
 template <class T>
 struct Macro {
   T drho, rho, irho;
+  T J[3];   // momentum sum e d, rounded to T
+  T drho_lo, J_lo[3];  // rounding residuals of drho and J (FP64 sums minus T values)
+  T Je[3];  // rho u^eq formed from J: J + lEq rho A
   T U[3], A[3], V[3], Ue[3], UF[3];
   T pi[6];  // Pi^neq / c^2: xx, yy, zz, xy, xz, yz
   T tau, itau, C;
@@ -254,22 +257,36 @@ struct Macro {
 
 // Moments (Section 2), model velocities, Pi^neq (cheap form after Eq. 9,
 // with the Maxwell stress of Eq. 11 under MHD), Smagorinsky tau.
+// Under MHD the stored deviations are taken from w rho0 + phi(B0) (the rest
+// equilibrium in the uniform field), db = b - b0 is the induced field.
 template <class L, class T, bool MHD, bool NEED_PI>
-__device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T Ay, T Az, const T (&b)[3], Macro<T>& m) {
-  T drho = T(0), jx = T(0), jy = T(0), jz = T(0);
+__device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T Ay, T Az, const T (&db)[3], Macro<T>& m) {
+  // The zeroth and first moments are summed in FP64: the relaxation resets
+  // each node's mass and momentum to these sums, so their rounding would be
+  // re-injected every step (FP64 adds run at the FP32 rate on this GPU).
+  double drho_a = 0.0, jx_a = 0.0, jy_a = 0.0, jz_a = 0.0;
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) {
-    drho += d[q];
-    if (L::ex(q) > 0) jx += d[q];
-    if (L::ex(q) < 0) jx -= d[q];
-    if (L::ey(q) > 0) jy += d[q];
-    if (L::ey(q) < 0) jy -= d[q];
-    if (L::ez(q) > 0) jz += d[q];
-    if (L::ez(q) < 0) jz -= d[q];
+    const double v = (double)d[q];
+    drho_a += v;
+    if (L::ex(q) > 0) jx_a += v;
+    if (L::ex(q) < 0) jx_a -= v;
+    if (L::ey(q) > 0) jy_a += v;
+    if (L::ey(q) < 0) jy_a -= v;
+    if (L::ez(q) > 0) jz_a += v;
+    if (L::ez(q) < 0) jz_a -= v;
   }
+  const T drho = (T)drho_a, jx = (T)jx_a, jy = (T)jy_a, jz = (T)jz_a;
+  m.drho_lo = (T)(drho_a - (double)drho);
+  m.J_lo[0] = (T)(jx_a - (double)jx);
+  m.J_lo[1] = (T)(jy_a - (double)jy);
+  m.J_lo[2] = (T)(jz_a - (double)jz);
   m.drho = drho;
-  m.rho = (T)p.rho0 + drho;
+  m.rho = (T)(p.rho0 + drho_a);
   m.irho = rcp(m.rho);
+  m.J[0] = jx;
+  m.J[1] = jy;
+  m.J[2] = jz;
   m.U[0] = jx * m.irho;
   m.U[1] = jy * m.irho;
   m.U[2] = jz * m.irho;
@@ -281,7 +298,8 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
   for (int k = 0; k < 3; ++k) {
     m.V[k] = m.U[k] + T(0.5) * m.A[k];
     m.Ue[k] = m.U[k] + lEq * m.A[k];
-    m.b[k] = b[k];
+    m.Je[k] = m.J[k] + lEq * m.rho * m.A[k];
+    m.b[k] = (T)p.b0[k] + db[k];
   }
   m.tau = (T)p.tau0;
   m.itau = (T)p.inv_tau0;
@@ -308,13 +326,17 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
     m.pi[4] = L::D == 3 ? sxz - rho * m.Ue[0] * m.Ue[2] : T(0);
     m.pi[5] = L::D == 3 ? syz - rho * m.Ue[1] * m.Ue[2] : T(0);
     if (MHD) {
-      const T b2h = T(0.5) * (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-      m.pi[0] -= b2h - b[0] * b[0];
-      m.pi[1] -= b2h - b[1] * b[1];
-      m.pi[2] -= b2h - b[2] * b[2];
-      m.pi[3] += b[0] * b[1];
-      m.pi[4] += b[0] * b[2];
-      m.pi[5] += b[1] * b[2];
+      // the stored second moment lacks L(b0); subtract L(b) - L(b0),
+      // L_ij = b^2 delta_ij / 2 - b_i b_j, formed from db to keep precision
+      const T bs[3] = {m.b[0] + (T)p.b0[0], m.b[1] + (T)p.b0[1], m.b[2] + (T)p.b0[2]};  // b + b0
+      const T b2h = T(0.5) * (db[0] * bs[0] + db[1] * bs[1] + db[2] * bs[2]);      // (b^2 - b0^2)/2
+      // b_i b_j - b0_i b0_j = (db_i bs_j + bs_i db_j) / 2
+      m.pi[0] -= b2h - db[0] * bs[0];
+      m.pi[1] -= b2h - db[1] * bs[1];
+      m.pi[2] -= b2h - db[2] * bs[2];
+      m.pi[3] += T(0.5) * (db[0] * bs[1] + bs[0] * db[1]);
+      m.pi[4] += T(0.5) * (db[0] * bs[2] + bs[0] * db[2]);
+      m.pi[5] += T(0.5) * (db[1] * bs[2] + bs[1] * db[2]);
     }
     if (p.les_K > 0.0) {
       // nu_eff = nu0 + (Cs dx)^2 sqrt(2 S:S), S from Eq. (9) at tau_eff:
@@ -337,28 +359,64 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
 
 // Eq. (2) with the equilibrium of Eq. (1) (+ magnetic part of Eq. 10) and
 // the force term of Section 2 / Eq. (3); d is replaced by d_rel.
+// Relaxation of Eq. (2) with the equilibrium of Eq. (1) (+ magnetic part of
+// Eq. 10) and the force term of Section 2 / Eq. (3); d is replaced by d_rel.
+//
+// Rounding design (FP32 arithmetic, FP32 or 16-bit storage).  In a steady or
+// slowly varying flow every rounding below repeats with the same sign at
+// each step, so a rounding that is large compared with the per-step changes
+// (the force increment rho a dt ~ 1e-7 beside f ~ 1e-2) accumulates like a
+// bias.  The equilibrium is therefore split into
+//   a large part at the node's own velocity u = j / rho from the rounded
+//   moments, whose difference with d (the small non-equilibrium part) is
+//   formed first, and
+//   a small part holding the shift u -> u^eq = u + lEq dt a, the rounding
+//   residuals of rho - rho0 and j (their sums are taken in FP64), and the
+//   magnetic term,
+// so that small quantities are never rounded at the scale of large ones.  The
+// weights 1/9, 1/18, 1/36 are applied as hi + lo parts so that the large
+// part's moments are not scaled by the weights' own rounding.
 template <class L, class T, bool MHD>
-__device__ __forceinline__ void collide(T (&d)[L::Q], const Macro<T>& m) {
+__device__ __forceinline__ void collide(T (&d)[L::Q], const Macro<T>& m, const T (&db)[3], const Phys& p) {
   const T rho = m.rho;
-  const T usq = T(1.5) * (m.Ue[0] * m.Ue[0] + m.Ue[1] * m.Ue[1] + m.Ue[2] * m.Ue[2]);
+  const T lEq = (T)p.lEq;
+  const T usq = T(1.5) * (m.U[0] * m.U[0] + m.U[1] * m.U[1] + m.U[2] * m.U[2]);
+  const T ua = m.U[0] * m.A[0] + m.U[1] * m.A[1] + m.U[2] * m.A[2];
+  const T aa = m.A[0] * m.A[0] + m.A[1] * m.A[1] + m.A[2] * m.A[2];
   const T ufa = m.UF[0] * m.A[0] + m.UF[1] * m.A[1] + m.UF[2] * m.A[2];
   const T cr = m.C * rho;
   const T itau = m.itau;
-  T b2 = T(0);
-  if (MHD) b2 = m.b[0] * m.b[0] + m.b[1] * m.b[1] + m.b[2] * m.b[2];
+  const T rl = rho * lEq, rl2 = rho * lEq * lEq;
+  T bs[3] = {T(0), T(0), T(0)}, db2 = T(0);
+  if (MHD) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) bs[k] = m.b[k] + (T)p.b0[k];  // b + b0
+    db2 = db[0] * bs[0] + db[1] * bs[1] + db[2] * bs[2];     // b^2 - b0^2
+  }
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) {
     const T w = (T)L::w(q);
-    const T eu = edot<L>(q, m.Ue[0], m.Ue[1], m.Ue[2]);
-    T deq = w * (m.drho + rho * (T(3) * eu + T(4.5) * eu * eu - usq));
-    if (MHD) {
-      const T eb = edot<L>(q, m.b[0], m.b[1], m.b[2]);
-      deq += T(4.5) * w * (T(0.5) * b2 * (T)L::e2(q) - eb * eb - b2 * T(1.0 / 6.0));
-    }
+    const T wlo = (T)(L::w(q) - (double)w);
+    const T eu = edot<L>(q, m.U[0], m.U[1], m.U[2]);
+    const T ej = edot<L>(q, m.J[0], m.J[1], m.J[2]);
     const T ea = edot<L>(q, m.A[0], m.A[1], m.A[2]);
+    // large part: w [drho + 3 e.j + rho (9/2 (e.u)^2 - 3/2 u.u)]
+    const T Rb = m.drho + T(3) * ej + rho * (T(4.5) * eu * eu - usq);
+    const T neq = (w * Rb + wlo * Rb) - d[q];
+    // small part: rounding residuals of the moments, the u^eq shift
+    //   rho [(e.ue)^2 9/2 - ue.ue 3/2] - (same at u) + 3 e.(rho lEq A),
+    // and the magnetic term phi(b) - phi(b0)
+    T Rs = m.drho_lo + T(3) * edot<L>(q, m.J_lo[0], m.J_lo[1], m.J_lo[2]);
+    Rs += rl * (T(3) * ea + T(9) * eu * ea - T(3) * ua) + rl2 * (T(4.5) * ea * ea - T(1.5) * aa);
+    if (MHD) {
+      // (e.b)^2 - (e.b0)^2 = (e.db)(e.(b + b0))
+      const T edb = edot<L>(q, db[0], db[1], db[2]);
+      const T ebs = edot<L>(q, bs[0], bs[1], bs[2]);
+      Rs += T(4.5) * (T(0.5) * db2 * (T)L::e2(q) - edb * ebs - db2 * T(1.0 / 6.0));
+    }
     const T euf = edot<L>(q, m.UF[0], m.UF[1], m.UF[2]);
     const T F = cr * w * (T(3) * (ea - ufa) + T(9) * euf * ea);
-    d[q] = d[q] + (deq - d[q]) * itau + F;
+    d[q] = d[q] + (neq + w * Rs) * itau + F;
   }
 }
 
@@ -434,19 +492,19 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
     Az = (T)a.p.A[2];
   }
   T h[7][3];
-  T b[3] = {T(0), T(0), T(0)};
+  T db[3] = {T(0), T(0), T(0)};
   if (MHD) {
     read_g<P, PAR, BND>((const typename S::E*)a.g, g.Np, n, o, mask, h);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      T s = (T)a.p.b0[i];
+      T s = T(0);
 #pragma unroll
-      for (int k = 0; k < 7; ++k) s += h[k][i];  // B = sum_k g_k
-      b[i] = s;
+      for (int k = 0; k < 7; ++k) s += h[k][i];  // B - B0 = sum_k (g_k - W_k B0)
+      db[i] = s;
     }
   }
   Macro<T> m;
-  macro<L, T, MHD, false>(d, a.p, Ax, Ay, Az, b, m);
+  macro<L, T, MHD, false>(d, a.p, Ax, Ay, Az, db, m);
   if (DIAG) {
     bal[0] += m.drho;
     bal[1] += m.rho * m.U[0];
@@ -456,7 +514,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
     bal[5] += m.rho * m.A[1];
     bal[6] += m.rho * m.A[2];
   }
-  collide<L, T, MHD>(d, m);
+  collide<L, T, MHD>(d, m, db, a.p);
   if (BND) {
     // halfway bounce-back links: the returning population is d_rel plus
     // the moving-wall term 6 w rho (e_opp . u_w) / c^2; Eq. (25) momentum
@@ -466,7 +524,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
     for (int q = 1; q < L::Q; ++q) {
       if ((mask >> q) & 1u) {
         const uint32_t gr = nibble(rec, q);
-        const T ux = (T)a.uw[3 * gr], uy = (T)a.uw[3 * gr + 1], uz = (T)a.uw[3 * gr + 2];
+        const T ux = (T)a.uw[3 * gr], uy = (T)a.uw[3 * gr + 1], uz = (T)a.uw[3 * gr + 2];  // u_w / c
         const T ladd = T(-6) * (T)L::w(q) * m.rho * edot<L>(q, ux, uy, uz);
         const T out = d[q];
         d[q] = out + ladd;
@@ -543,6 +601,15 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   }
 }
 
+// Magnetic part of the rest equilibrium in the uniform field b0 (Eq. 10).
+template <class L>
+__device__ __forceinline__ double mhd_phi0(int q, const Phys& p) {
+  const double* b0 = p.b0;
+  const double eb = edot<L>(q, b0[0], b0[1], b0[2]);
+  const double b2 = b0[0] * b0[0] + b0[1] * b0[1] + b0[2] * b0[2];
+  return 4.5 * L::w(q) * (0.5 * b2 * L::e2(q) - eb * eb - b2 / 6.0);
+}
+
 // ---------------------------------------------------------------------------
 // diagnostics of the current state (read only)
 // ---------------------------------------------------------------------------
@@ -553,10 +620,12 @@ __device__ __forceinline__ bool node_solid(const DiagArgs& a, uint32_t n) {
   return rr >= 0 && (a.rec[rr + x].x >> 31);
 }
 
+// All diagnostic arithmetic is FP64, applied to the stored values.
 template <class L, int P, bool MHD, int PAR>
 __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
   using S = Stor<P>;
-  using T = typename S::T;
+  using T = double;
+  using TS = typename S::T;
   const Geom& g = a.geo;
   const uint32_t n = blockIdx.x * NTHREADS + threadIdx.x;
   double part[NDIAGPART] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -567,12 +636,16 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
     const int rr = a.rowrec[r];
     const uint4 rec = rr >= 0 ? a.rec[rr + x] : make_uint4(0u, 0u, 0u, 0u);
     const bool solid = rec.x >> 31;
-    T d[L::Q];
-    T h[7][3];
+    T d[L::Q] = {};
+    T h[7][3] = {};
     T b[3] = {T(0), T(0), T(0)};
-    Macro<T> m;
+    T db[3] = {T(0), T(0), T(0)};
+    Macro<T> m = {};
     if (!solid) {
-      read_f<L, P, PAR, true>((const typename S::E*)a.f, g.Np, n, o, rec.x, a.p, d);
+      TS ds[L::Q];
+      read_f<L, P, PAR, true>((const typename S::E*)a.f, g.Np, n, o, rec.x, a.p, ds);
+#pragma unroll
+      for (int q = 0; q < L::Q; ++q) d[q] = (T)ds[q];
       T Ax, Ay, Az;
       if (a.afield) {
         const T s = (T)a.p.afield_scale;
@@ -585,20 +658,31 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
         Az = (T)a.p.A[2];
       }
       if (MHD) {
-        read_g<P, PAR, true>((const typename S::E*)a.g, g.Np, n, o, rec.x, h);
+        TS hs[7][3];
+        read_g<P, PAR, true>((const typename S::E*)a.g, g.Np, n, o, rec.x, hs);
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+#pragma unroll
+          for (int i = 0; i < 3; ++i) h[k][i] = (T)hs[k][i];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          T s = (T)a.p.b0[i];
+          T s = T(0);
 #pragma unroll
           for (int k = 0; k < 7; ++k) s += h[k][i];
-          b[i] = s;
+          db[i] = s;
         }
       }
-      macro<L, T, MHD, true>(d, a.p, Ax, Ay, Az, b, m);
+      macro<L, T, MHD, true>(d, a.p, Ax, Ay, Az, db, m);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) b[i] = m.b[i];
     }
     if (a.state) {
 #pragma unroll
-      for (int q = 0; q < L::Q; ++q) a.state[(uint64_t)q * g.N + n] = solid ? 0.0 : (double)d[q];
+      for (int q = 0; q < L::Q; ++q) {
+        double v = (double)d[q];
+        if (MHD) v += mhd_phi0<L>(q, a.p);  // back to f - w rho0
+        a.state[(uint64_t)q * g.N + n] = solid ? 0.0 : v;
+      }
     }
     if (a.gstate) {
       // absolute g in units of B (the host rescales by c sqrt(mu))
@@ -717,16 +801,13 @@ __global__ __launch_bounds__(NTHREADS) void k_init(const InitArgs a) {
     if (!solid) {
       if (a.state) {
         v = a.state[(uint64_t)q * g.N + n];
+        if (MHD) v -= mhd_phi0<L>(q, a.p);  // stored relative to the rest equilibrium in B0
       } else {
+        // f^eq(rho0, u0) (+ phi(B0), which the stored deviation excludes)
         const double w = L::w(q);
         const double eu = edot<L>(q, U[0], U[1], U[2]);
         const double usq = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
         v = w * a.p.rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
-        if (MHD) {
-          const double eb = edot<L>(q, b0[0], b0[1], b0[2]);
-          const double b2 = b0[0] * b0[0] + b0[1] * b0[1] + b0[2] * b0[2];
-          v += 4.5 * w * (0.5 * b2 * L::e2(q) - eb * eb - b2 / 6.0);
-        }
       }
     }
     T s = (T)v;

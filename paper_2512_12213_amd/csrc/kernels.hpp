@@ -42,7 +42,7 @@ struct StepArgs {
   const uint4* rec;        // boundary records: x = solid-link mask (bit 31: node solid), y..w = group nibbles
   const int* rowrec;       // per row: index of the row's first record, or -1
   const uint32_t* blkgrp;  // per tile: up to MAXBG group labels, 4 bits each, + count in bits 28..31
-  const float* uw;         // [MAXG][3] wall velocity / c
+  const double* uw;        // [MAXG][3] wall velocity / c
   double* part;            // [ntiles][NPART] on diagnostic steps
   Geom geo;
   Phys p;

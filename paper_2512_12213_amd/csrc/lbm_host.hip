@@ -262,7 +262,7 @@ int build_geometry(lbm_ctx* h) {
   HIPCHK(h->dpart.ensure((size_t)h->ntiles * NDIAGPART * sizeof(double)));
   HIPCHK(h->red.ensure((NBAL + MAXG * NWALL) * sizeof(double)));
   HIPCHK(h->dred.ensure(NDIAGPART * sizeof(double)));
-  HIPCHK(h->uwdev.ensure(MAXG * 3 * sizeof(float)));
+  HIPCHK(h->uwdev.ensure(MAXG * 3 * sizeof(double)));
   h->uw_dirty = true;
   h->geom_ok = true;
   return LBM_OK;
@@ -283,7 +283,7 @@ StepArgs step_args(lbm_ctx* h) {
   a.rec = (const uint4*)h->rec.p;
   a.rowrec = (const int*)h->rowrec.p;
   a.blkgrp = (const uint32_t*)h->blkgrp.p;
-  a.uw = (const float*)h->uwdev.p;
+  a.uw = (const double*)h->uwdev.p;
   a.part = (double*)h->part.p;
   a.geo = make_geom(h);
   a.p = make_phys(h);
@@ -601,9 +601,9 @@ int lbm_step(lbm_ctx* h, int n) {
   if (n < 0) return fail(LBM_EINVAL, "negative step count");
   if (n == 0) return LBM_OK;
   if (h->uw_dirty) {
-    float t[MAXG * 3];
+    double t[MAXG * 3];
     for (int gr = 0; gr < MAXG; ++gr)
-      for (int k = 0; k < 3; ++k) t[3 * gr + k] = (float)(h->uw[gr][k] / h->c);
+      for (int k = 0; k < 3; ++k) t[3 * gr + k] = h->uw[gr][k] / h->c;
     HIPCHK(hipMemcpy(h->uwdev.p, t, sizeof(t), hipMemcpyHostToDevice));
     h->uw_dirty = false;
   }
@@ -699,7 +699,9 @@ static void wall_variants(const lbm_ctx* h, int gr, double out[4][3]) {
       phi = 4.5 * w * (0.5 * b2 * e2 - eb * eb - b2 / 6.0);
     }
     for (int k = 0; k < 3; ++k) {
-      stat[k] += (double)nl * 2.0 * w * h->rho0 * e[k];
+      // rest-state part of 2 f_out: 2 (w rho0 + phi(B0)) per link (the stored
+      // deviations exclude both)
+      stat[k] += (double)nl * 2.0 * (w * h->rho0 + phi) * e[k];
       mx[k] += -(double)nl * 2.0 * e[k] * phi;
     }
   }

@@ -35,3 +35,44 @@ def rel_inf(x, ref):
     if den == 0:
         return float(num)
     return float(num / den)
+
+
+# ---------------------------------------------------------------------------
+# Storage formats of include/lbm.h, applied to oracle states.  They let the
+# 16-bit GPU paths be compared element-wise with the oracle's FP64 arithmetic
+# carrying the same storage rounding (the "quantized oracle").
+# ---------------------------------------------------------------------------
+def _weights(Q):
+    from closed_forms import lattice
+    _, w = lattice("D2Q9" if Q == 9 else "D3Q19")
+    return w
+
+
+def bf16_round(x):
+    """Round float64 -> float32 -> bfloat16 (nearest even), back to float64."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def quantize_state(d, storage):
+    """Deviations d [Q, ...] rounded as the library stores them."""
+    from paper_2512_12213_amd import workloads as W
+    if storage == W.F64:
+        return d
+    if storage == W.F32:
+        return d.astype(np.float32).astype(np.float64)
+    w = _weights(d.shape[0]).reshape((-1,) + (1,) * (d.ndim - 1))
+    if storage == W.F16:
+        s = 1024.0 / w
+        return (d * s).astype(np.float32).astype(np.float16).astype(np.float64) / s
+    return bf16_round(d / w) * w
+
+
+def quantized_steps(o, storage, n):
+    """Advance the oracle n steps, rounding the state to the storage format
+    after each step (the wall-force / balance records of the last step are
+    kept by the oracle)."""
+    for _ in range(n):
+        o.step(1)
+        o.set_state(quantize_state(o.get_state(), storage), keep_records=True)
