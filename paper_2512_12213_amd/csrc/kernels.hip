@@ -1,8 +1,11 @@
 // Device kernels of the lattice Boltzmann hot path for gfx950 (MI355X).
 //
 // One thread per lattice node, 256-thread tiles of consecutive nodes (x
-// fastest).  Distributions live in one in-place array per lattice,
-// structure-of-arrays [Q][Np], updated with the A-A pattern: on even steps a
+// fastest).  Distributions live in one in-place array per lattice, blocked by
+// x-row: element (q, row, x) at (row Q + q) nx + x, so that all Q populations
+// of a row form one contiguous block (for DRAM page locality; each population
+// is still contiguous along x for coalesced access).  The array is updated
+// with the A-A pattern: on even steps a
 // node reads its own slots and writes its post-collision values into the
 // opposite slots (no data movement between nodes); on odd steps it gathers
 // from its neighbours' opposite slots and scatters into its neighbours' slots.
@@ -70,8 +73,11 @@ __device__ __forceinline__ float rcp<float>(float x) {
 // ---------------------------------------------------------------------------
 // index helpers
 // ---------------------------------------------------------------------------
+// Element offsets to the six axis neighbours (periodic wrap) in a row-blocked
+// array whose rows hold P planes (row stride rs = P nx).
 struct Offs {
-  int xp, xm, yp, ym, zp, zm;
+  int xp, xm;
+  int64_t yp, ym, zp, zm;
 };
 
 __device__ __forceinline__ void coords(const Geom& g, uint32_t n, uint32_t& x, uint32_t& y, uint32_t& z, uint32_t& r) {
@@ -81,23 +87,23 @@ __device__ __forceinline__ void coords(const Geom& g, uint32_t n, uint32_t& x, u
   y = r - z * g.ny;
 }
 
-// Offsets (in nodes) to the six axis neighbours with periodic wrap.
-__device__ __forceinline__ Offs offsets(const Geom& g, uint32_t x, uint32_t y, uint32_t z) {
+__device__ __forceinline__ Offs offsets(const Geom& g, uint32_t x, uint32_t y, uint32_t z, uint64_t rs) {
   Offs o;
-  const int nx = (int)g.nx, ny = (int)g.ny, nz = (int)g.nz, sxy = nx * ny;
+  const int nx = (int)g.nx;
+  const int64_t ry = (int64_t)rs, rz = (int64_t)rs * g.ny;
   o.xp = (x + 1 == g.nx) ? 1 - nx : 1;
   o.xm = (x == 0) ? nx - 1 : -1;
-  o.yp = (y + 1 == g.ny) ? (1 - ny) * nx : nx;
-  o.ym = (y == 0) ? (ny - 1) * nx : -nx;
-  o.zp = (z + 1 == g.nz) ? (1 - nz) * sxy : sxy;
-  o.zm = (z == 0) ? (nz - 1) * sxy : -sxy;
+  o.yp = (y + 1 == g.ny) ? (1 - (int64_t)g.ny) * ry : ry;
+  o.ym = (y == 0) ? ((int64_t)g.ny - 1) * ry : -ry;
+  o.zp = (z + 1 == g.nz) ? (1 - (int64_t)g.nz) * rz : rz;
+  o.zm = (z == 0) ? ((int64_t)g.nz - 1) * rz : -rz;
   return o;
 }
 
 // Offset from a node to its neighbour along e_q.
 template <class L>
-__device__ __forceinline__ int off_of(int q, const Offs& o) {
-  int s = 0;
+__device__ __forceinline__ int64_t off_of(int q, const Offs& o) {
+  int64_t s = 0;
   if (L::ex(q) > 0) s += o.xp;
   if (L::ex(q) < 0) s += o.xm;
   if (L::ey(q) > 0) s += o.yp;
@@ -132,7 +138,7 @@ __device__ __forceinline__ uint32_t nibble(const uint4& r, int q) {
 //   odd parity: slot opp(q) of x - e_q, or, when the link from x along
 //   -e_q ends in a wall, slot q of x (where the bounce-back value was put).
 template <class L, int P, int PAR, bool BND>
-__device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f, uint64_t Np, uint32_t n, const Offs& o,
+__device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f, uint32_t nx, uint64_t n, const Offs& o,
                                        uint32_t mask, const Phys& p, typename Stor<P>::T (&d)[L::Q]) {
   using S = Stor<P>;
   using T = typename S::T;
@@ -141,12 +147,12 @@ __device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f
     const int qb = opp(q);
     const typename S::E* ptr;
     if (PAR == 0) {
-      ptr = f + (uint64_t)q * Np + n;
+      ptr = f + n + q * nx;
     } else {
-      const typename S::E* pn = f + (uint64_t)qb * Np + (uint32_t)(n + off_of<L>(qb, o));
+      const typename S::E* pn = f + (n + off_of<L>(qb, o)) + qb * nx;
       if (BND) {
         const bool bb = (mask >> qb) & 1u;
-        ptr = bb ? f + (uint64_t)q * Np + n : pn;
+        ptr = bb ? f + n + q * nx : pn;
       } else {
         ptr = pn;
       }
@@ -162,7 +168,7 @@ __device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f
 //   even parity: slot opp(q) of x;
 //   odd parity: slot q of x + e_q, or slot opp(q) of x for a wall link.
 template <class L, int P, int PAR, bool BND>
-__device__ __forceinline__ void write_f(typename Stor<P>::E* __restrict__ f, uint64_t Np, uint32_t n, const Offs& o,
+__device__ __forceinline__ void write_f(typename Stor<P>::E* __restrict__ f, uint32_t nx, uint64_t n, const Offs& o,
                                         uint32_t mask, const Phys& p, const typename Stor<P>::T (&v)[L::Q]) {
   using S = Stor<P>;
   using T = typename S::T;
@@ -171,12 +177,12 @@ __device__ __forceinline__ void write_f(typename Stor<P>::E* __restrict__ f, uin
     const int qb = opp(q);
     typename S::E* ptr;
     if (PAR == 0) {
-      ptr = f + (uint64_t)qb * Np + n;
+      ptr = f + n + qb * nx;
     } else {
-      typename S::E* pn = f + (uint64_t)q * Np + (uint32_t)(n + off_of<L>(q, o));
+      typename S::E* pn = f + (n + off_of<L>(q, o)) + q * nx;
       if (BND) {
         const bool bb = (mask >> q) & 1u;
-        ptr = bb ? f + (uint64_t)qb * Np + n : pn;
+        ptr = bb ? f + n + qb * nx : pn;
       } else {
         ptr = pn;
       }
@@ -189,7 +195,7 @@ __device__ __forceinline__ void write_f(typename Stor<P>::E* __restrict__ f, uin
 
 // Same pattern for the 21 induction planes (7 directions x 3 components).
 template <int P, int PAR, bool BND>
-__device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g, uint64_t Np, uint32_t n, const Offs& o,
+__device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g, uint32_t nx, uint64_t n, const Offs& o,
                                        uint32_t mask, typename Stor<P>::T (&h)[7][3]) {
   using S = Stor<P>;
 #pragma unroll
@@ -199,12 +205,12 @@ __device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g
     for (int i = 0; i < 3; ++i) {
       const typename S::E* ptr;
       if (PAR == 0) {
-        ptr = g + (uint64_t)(3 * k + i) * Np + n;
+        ptr = g + n + (3 * k + i) * nx;
       } else {
-        const typename S::E* pn = g + (uint64_t)(3 * kb + i) * Np + (uint32_t)(n + off_of<D3Q19>(kb, o));
+        const typename S::E* pn = g + (n + off_of<D3Q19>(kb, o)) + (3 * kb + i) * nx;
         if (BND) {
           const bool bb = (mask >> kb) & 1u;
-          ptr = bb ? g + (uint64_t)(3 * k + i) * Np + n : pn;
+          ptr = bb ? g + n + (3 * k + i) * nx : pn;
         } else {
           ptr = pn;
         }
@@ -215,7 +221,7 @@ __device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g
 }
 
 template <int P, int PAR, bool BND>
-__device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, uint64_t Np, uint32_t n, const Offs& o,
+__device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, uint32_t nx, uint64_t n, const Offs& o,
                                         uint32_t mask, const typename Stor<P>::T (&h)[7][3]) {
   using S = Stor<P>;
 #pragma unroll
@@ -225,12 +231,12 @@ __device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, uin
     for (int i = 0; i < 3; ++i) {
       typename S::E* ptr;
       if (PAR == 0) {
-        ptr = g + (uint64_t)(3 * kb + i) * Np + n;
+        ptr = g + n + (3 * kb + i) * nx;
       } else {
-        typename S::E* pn = g + (uint64_t)(3 * k + i) * Np + (uint32_t)(n + off_of<D3Q19>(k, o));
+        typename S::E* pn = g + (n + off_of<D3Q19>(k, o)) + (3 * k + i) * nx;
         if (BND) {
           const bool bb = (mask >> k) & 1u;
-          ptr = bb ? g + (uint64_t)(3 * kb + i) * Np + n : pn;
+          ptr = bb ? g + n + (3 * kb + i) * nx : pn;
         } else {
           ptr = pn;
         }
@@ -471,15 +477,18 @@ __device__ __forceinline__ void tile_sum_store(double (&v)[NV], double* __restri
 // the fused step
 // ---------------------------------------------------------------------------
 template <class L, int P, bool MHD, int PAR, bool DIAG, bool BND>
-__device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const Offs& o, const uint4& rec,
+__device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, uint32_t x, uint32_t y, uint32_t z, uint32_t r,
+                                            const uint4& rec,
                                             typename Stor<P>::T (&bal)[NBAL],
                                             typename Stor<P>::T (&wacc)[MAXBG][NWALL], uint32_t bgrp) {
   using S = Stor<P>;
   using T = typename S::T;
   const Geom& g = a.geo;
   const uint32_t mask = rec.x;
+  const uint64_t bf = (uint64_t)r * (L::Q * g.nx) + x;  // row-blocked base of this node
+  const Offs o = offsets(g, x, y, z, (uint64_t)L::Q * g.nx);
   T d[L::Q];
-  read_f<L, P, PAR, BND>((const typename S::E*)a.f, g.Np, n, o, mask, a.p, d);
+  read_f<L, P, PAR, BND>((const typename S::E*)a.f, g.nx, bf, o, mask, a.p, d);
   T Ax, Ay, Az;
   if (a.afield) {
     const T s = (T)a.p.afield_scale;
@@ -493,8 +502,10 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
   }
   T h[7][3];
   T db[3] = {T(0), T(0), T(0)};
+  const uint64_t bg = (uint64_t)r * (21 * g.nx) + x;
+  const Offs og = offsets(g, x, y, z, (uint64_t)21 * g.nx);
   if (MHD) {
-    read_g<P, PAR, BND>((const typename S::E*)a.g, g.Np, n, o, mask, h);
+    read_g<P, PAR, BND>((const typename S::E*)a.g, g.nx, bg, og, mask, h);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       T s = T(0);
@@ -543,7 +554,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
       }
     }
   }
-  write_f<L, P, PAR, BND>((typename S::E*)a.f, g.Np, n, o, mask, a.p, d);
+  write_f<L, P, PAR, BND>((typename S::E*)a.f, g.nx, bf, o, mask, a.p, d);
   if (MHD) {
     collide_g<T>(h, m, a.p);
     if (BND) {
@@ -555,7 +566,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
           for (int i = 0; i < 3; ++i) h[k][i] = -h[k][i];
         }
     }
-    write_g<P, PAR, BND>((typename S::E*)a.g, g.Np, n, o, mask, h);
+    write_g<P, PAR, BND>((typename S::E*)a.g, g.nx, bg, og, mask, h);
   }
 }
 
@@ -579,14 +590,13 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   if (active) {
     uint32_t x, y, z, r;
     coords(g, n, x, y, z, r);
-    const Offs o = offsets(g, x, y, z);
     const int rr = a.rowrec[r];
     if (rr < 0) {
       const uint4 rec = make_uint4(0u, 0u, 0u, 0u);
-      node_update<L, P, MHD, PAR, DIAG, false>(a, n, o, rec, bal, wacc, bgrp);
+      node_update<L, P, MHD, PAR, DIAG, false>(a, n, x, y, z, r, rec, bal, wacc, bgrp);
     } else {
       const uint4 rec = a.rec[rr + x];
-      if (!(rec.x >> 31)) node_update<L, P, MHD, PAR, DIAG, true>(a, n, o, rec, bal, wacc, bgrp);
+      if (!(rec.x >> 31)) node_update<L, P, MHD, PAR, DIAG, true>(a, n, x, y, z, r, rec, bal, wacc, bgrp);
     }
   }
   if (DIAG) {
@@ -632,7 +642,11 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
   if (n < g.N) {
     uint32_t x, y, z, r;
     coords(g, n, x, y, z, r);
-    const Offs o = offsets(g, x, y, z);
+    const Offs o = offsets(g, x, y, z, (uint64_t)L::Q * g.nx);
+    const Offs og = offsets(g, x, y, z, (uint64_t)21 * g.nx);
+    const Offs on = offsets(g, x, y, z, (uint64_t)g.nx);  // node-index offsets
+    const uint64_t bf = (uint64_t)r * (L::Q * g.nx) + x;
+    const uint64_t bg = (uint64_t)r * (21 * g.nx) + x;
     const int rr = a.rowrec[r];
     const uint4 rec = rr >= 0 ? a.rec[rr + x] : make_uint4(0u, 0u, 0u, 0u);
     const bool solid = rec.x >> 31;
@@ -643,7 +657,7 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
     Macro<T> m = {};
     if (!solid) {
       TS ds[L::Q];
-      read_f<L, P, PAR, true>((const typename S::E*)a.f, g.Np, n, o, rec.x, a.p, ds);
+      read_f<L, P, PAR, true>((const typename S::E*)a.f, g.nx, bf, o, rec.x, a.p, ds);
 #pragma unroll
       for (int q = 0; q < L::Q; ++q) d[q] = (T)ds[q];
       T Ax, Ay, Az;
@@ -659,7 +673,7 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
       }
       if (MHD) {
         TS hs[7][3];
-        read_g<P, PAR, true>((const typename S::E*)a.g, g.Np, n, o, rec.x, hs);
+        read_g<P, PAR, true>((const typename S::E*)a.g, g.nx, bg, og, rec.x, hs);
 #pragma unroll
         for (int k = 0; k < 7; ++k)
 #pragma unroll
@@ -743,7 +757,7 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
       // (second layer) extrapolate (-p I + sigma) n to the halfway wall
       const uint32_t pos[3] = {x, y, z};
       const uint32_t ext[3] = {g.nx, g.ny, g.nz};
-      const int ax_off_p[3] = {o.xp, o.yp, o.zp}, ax_off_m[3] = {o.xm, o.ym, o.zm};
+      const int64_t ax_off_p[3] = {on.xp, on.yp, on.zp}, ax_off_m[3] = {on.xm, on.ym, on.zm};
       const double p_iso = (double)m.rho * a.c * a.c / 3.0;
       double T3[3][3];
       const int fi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
@@ -757,13 +771,13 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
           if (!(side == 0 ? a.wall_lo[ax] : a.wall_hi[ax])) continue;
           const uint32_t l0 = side == 0 ? 0u : ext[ax] - 1, l1 = side == 0 ? 1u : ext[ax] - 2;
           double wgt = 0.0;
-          uint32_t partner = n;
+          uint32_t partner = n;  // node index of the other extrapolation layer
           if (pos[ax] == l0) {
             wgt = 1.5;
-            partner = n + (side == 0 ? ax_off_p[ax] : ax_off_m[ax]);
+            partner = (uint32_t)((int64_t)n + (side == 0 ? ax_off_p[ax] : ax_off_m[ax]));
           } else if (pos[ax] == l1) {
             wgt = -0.5;
-            partner = n + (side == 0 ? ax_off_m[ax] : ax_off_p[ax]);
+            partner = (uint32_t)((int64_t)n + (side == 0 ? ax_off_m[ax] : ax_off_p[ax]));
           }
           if (wgt == 0.0 || node_solid(a, partner)) continue;
           const double nrm = side == 0 ? 1.0 : -1.0;
@@ -812,7 +826,7 @@ __global__ __launch_bounds__(NTHREADS) void k_init(const InitArgs a) {
     }
     T s = (T)v;
     if (P == S_F16 || P == S_BF16) s = (T)(v * (double)a.p.scale[q]);
-    S::st(f + (uint64_t)q * g.Np + n, s);
+    S::st(f + ((uint64_t)r * (L::Q * g.nx) + x) + q * g.nx, s);
   }
   if (MHD) {
     typename S::E* gg = (typename S::E*)a.g;
@@ -822,7 +836,7 @@ __global__ __launch_bounds__(NTHREADS) void k_init(const InitArgs a) {
       for (int i = 0; i < 3; ++i) {
         double hv = 0.0;
         if (!solid && k > 0) hv = D3Q7::w(k) * sgn * (1.0 / D3Q7::theta) * (U[ax] * b0[i] - b0[ax] * U[i]);
-        S::st(gg + (uint64_t)(3 * k + i) * g.Np + n, (T)hv);
+        S::st(gg + ((uint64_t)r * (21 * g.nx) + x) + (3 * k + i) * g.nx, (T)hv);
       }
     }
   }

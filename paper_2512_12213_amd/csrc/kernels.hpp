@@ -15,10 +15,10 @@ constexpr int NWALL = 4;                   // sum e (2 d_rel + ladd) (3), sum la
 constexpr int NPART = NBAL + MAXBG * NWALL;  // per-tile partial sums on diagnostic steps
 constexpr int NDIAGPART = 8;               // sum drho, sum rho U (3), stress integral (3), pad
 
-// Index geometry.  Nodes are numbered n = (z ny + y) nx + x; plane stride Np.
+// Index geometry.  Nodes are numbered n = (z ny + y) nx + x = row nx + x; an
+// array with P planes stores element (q, row, x) at (row P + q) nx + x.
 struct Geom {
   uint32_t nx, ny, nz, N;
-  uint64_t Np;
   uint64_t mnx, mny;  // ceil(2^64 / d) for exact division by nx, ny (unused when d == 1)
 };
 
@@ -36,8 +36,8 @@ struct Phys {
 };
 
 struct StepArgs {
-  void* f;                 // distributions [Q][Np]
-  void* g;                 // induction deviations [7][3][Np] (MHD) or null
+  void* f;                 // distributions, row-blocked [ny nz][Q][nx]
+  void* g;                 // induction deviations, row-blocked [ny nz][21][nx] (MHD) or null
   const float* afield;     // [3][N] or null
   const uint4* rec;        // boundary records: x = solid-link mask (bit 31: node solid), y..w = group nibbles
   const int* rowrec;       // per row: index of the row's first record, or -1

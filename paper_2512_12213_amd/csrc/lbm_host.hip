@@ -84,7 +84,6 @@ struct lbm_ctx {
   int lattice, D, Q, NC;
   int nx, ny, nz;
   uint32_t N;
-  uint64_t Np;
   double tau, dx, dt, c;
   int model;
   int prec = S_F32;
@@ -159,7 +158,6 @@ Geom make_geom(const lbm_ctx* h) {
   g.ny = h->ny;
   g.nz = h->nz;
   g.N = h->N;
-  g.Np = h->Np;
   g.mnx = h->nx > 1 ? UINT64_MAX / (uint64_t)h->nx + 1 : 0;
   g.mny = h->ny > 1 ? UINT64_MAX / (uint64_t)h->ny + 1 : 0;
   return g;
@@ -270,8 +268,8 @@ int build_geometry(lbm_ctx* h) {
 
 int alloc_state(lbm_ctx* h) {
   const size_t eb = elem_bytes(h->prec);
-  HIPCHK(h->f.ensure((size_t)h->Q * h->Np * eb));
-  if (h->mhd) HIPCHK(h->g.ensure((size_t)21 * h->Np * eb));
+  HIPCHK(h->f.ensure((size_t)h->Q * h->N * eb));
+  if (h->mhd) HIPCHK(h->g.ensure((size_t)21 * h->N * eb));
   return LBM_OK;
 }
 
@@ -370,7 +368,6 @@ lbm_ctx* lbm_create(int lattice, int nx, int ny, int nz, double tau, double dx, 
   h->ny = ny;
   h->nz = nz;
   h->N = (uint32_t)N;
-  h->Np = (N + 63) & ~(uint64_t)63;  // planes start on 256-byte boundaries for 4-byte storage
   h->tau = tau;
   h->dx = dx;
   h->dt = dt;

@@ -23,7 +23,10 @@ pytestmark = pytest.mark.gpu
 # BF16 keeps 8 significant bits: its rounding unit 2^-8 = 3.9e-3 is larger
 # than the 2e-3 target, so one rounding that lands on the other side already
 # exceeds it.  It is held to two of its own rounding units.
+# The stress is a small difference of stored values, so under BF16 its error
+# is the storage unit times |d| / |Pi^neq| (about 2-4 in these flows).
 TOL_FIELD = {W.F64: 1e-12, W.F32: 1e-5, W.F16: 2e-3, W.BF16: 8e-3}
+TOL_STRESS = {W.F64: 1e-12, W.F32: 1e-5, W.F16: 2e-3, W.BF16: 2e-2}
 TOL_WALL = {W.F64: 1e-12, W.F32: 1e-4, W.F16: 2e-3, W.BF16: 8e-3}
 
 
@@ -60,8 +63,8 @@ def compare_all(g, o, storage, groups, what=""):
     say("%s rho %.2e v %.2e sigma %.2e S %.2e wall %.2e" % (what, e_rho, e_v, e_s, e_S, e_f))
     assert e_rho <= tf
     assert e_v <= tf
-    assert e_s <= tf
-    assert e_S <= tf
+    assert e_s <= TOL_STRESS[storage]
+    assert e_S <= TOL_STRESS[storage]
     assert e_f <= TOL_WALL[storage]
     return dict(rho=e_rho, v=e_v, sigma=e_s, strain=e_S, wall=e_f)
 
@@ -130,7 +133,7 @@ def test_random_state_two_steps(lbm, lattice, model, storage):
     o.set_artefact(True)
     sg, Sg = g.stress()
     so, So = o.stress()
-    assert rel_inf(sg, so) <= TOL_FIELD[storage] and rel_inf(Sg, So) <= TOL_FIELD[storage]
+    assert rel_inf(sg, so) <= TOL_STRESS[storage] and rel_inf(Sg, So) <= TOL_STRESS[storage]
 
 
 def test_couette_cylinder_fp32(lbm):
