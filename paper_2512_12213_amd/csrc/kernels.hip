@@ -113,6 +113,65 @@ __device__ __forceinline__ int64_t off_of(int q, const Offs& o) {
   return s;
 }
 
+// Addressing of one node's slots in a row-blocked array with P planes:
+// ptr<L>(f, plane, q) points at `plane` of the neighbour x + e_q (q < 0: the
+// node itself).
+//
+// Generic form: a per-lane element index of the node plus neighbour offsets.
+struct AddrG {
+  uint64_t b;
+  Offs o;
+  uint32_t nx;
+  template <class L, class E>
+  __device__ __forceinline__ E* ptr(E* f, int plane, int q) const {
+    return f + ((q < 0 ? b : b + off_of<L>(q, o)) + (uint32_t)plane * nx);
+  }
+};
+
+// Row-uniform form, used when nx is a multiple of 64: a wavefront then never
+// leaves its x-row, so the start of each of the nine neighbour rows is
+// wave-uniform (scalar registers) and each lane only adds its 32-bit x index
+// (scalar base + vector offset addressing).
+struct AddrR {
+  uint64_t rb[3][3];  // element index of row (y + dy, z + dz), dy, dz in {-1, 0, 1}
+  uint32_t xi[3];     // x - 1, x, x + 1 (periodic)
+  uint32_t nx;
+  template <class L, class E>
+  __device__ __forceinline__ E* ptr(E* f, int plane, int q) const {
+    const int dx = q < 0 ? 0 : L::ex(q), dy = q < 0 ? 0 : L::ey(q), dz = q < 0 ? 0 : L::ez(q);
+    E* base = f + (rb[dy + 1][dz + 1] + (uint32_t)plane * nx);  // wave-uniform
+    const uint32_t off = xi[dx + 1] * (uint32_t)sizeof(E);         // 32-bit byte offset
+    return (E*)((char*)base + off);
+  }
+};
+
+__device__ __forceinline__ AddrG addr_g(const Geom& g, uint32_t x, uint32_t y, uint32_t z, uint32_t r, uint32_t P) {
+  AddrG a;
+  a.b = (uint64_t)r * (P * g.nx) + x;
+  a.o = offsets(g, x, y, z, (uint64_t)P * g.nx);
+  a.nx = g.nx;
+  return a;
+}
+
+// y, z must be wave-uniform.
+__device__ __forceinline__ AddrR addr_r(const Geom& g, uint32_t x, uint32_t y, uint32_t z, uint32_t P) {
+  AddrR a;
+  const uint64_t rs = (uint64_t)P * g.nx;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz) {
+      uint32_t yy = (dy < 0) ? (y == 0 ? g.ny - 1 : y - 1) : (dy > 0 ? (y + 1 == g.ny ? 0 : y + 1) : y);
+      uint32_t zz = (dz < 0) ? (z == 0 ? g.nz - 1 : z - 1) : (dz > 0 ? (z + 1 == g.nz ? 0 : z + 1) : z);
+      a.rb[dy + 1][dz + 1] = ((uint64_t)zz * g.ny + yy) * rs;
+    }
+  a.xi[0] = x == 0 ? g.nx - 1 : x - 1;
+  a.xi[1] = x;
+  a.xi[2] = x + 1 == g.nx ? 0 : x + 1;
+  a.nx = g.nx;
+  return a;
+}
+
 template <class L, class T>
 __device__ __forceinline__ T edot(int q, T vx, T vy, T vz) {
   T s = T(0);
@@ -137,9 +196,9 @@ __device__ __forceinline__ uint32_t nibble(const uint4& r, int q) {
 //   even parity (natural layout): slot q of x;
 //   odd parity: slot opp(q) of x - e_q, or, when the link from x along
 //   -e_q ends in a wall, slot q of x (where the bounce-back value was put).
-template <class L, int P, int PAR, bool BND>
-__device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f, uint32_t nx, uint64_t n, const Offs& o,
-                                       uint32_t mask, const Phys& p, typename Stor<P>::T (&d)[L::Q]) {
+template <class L, int P, int PAR, bool BND, class AD>
+__device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask,
+                                       const Phys& p, typename Stor<P>::T (&d)[L::Q]) {
   using S = Stor<P>;
   using T = typename S::T;
 #pragma unroll
@@ -147,17 +206,14 @@ __device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f
     const int qb = opp(q);
     const typename S::E* ptr;
     if (PAR == 0) {
-      ptr = f + n + q * nx;
+      ptr = A.template ptr<L>(f, q, -1);
     } else {
-      const typename S::E* pn = f + (n + off_of<L>(qb, o)) + qb * nx;
-      if (BND) {
-        const bool bb = (mask >> qb) & 1u;
-        ptr = bb ? f + n + q * nx : pn;
-      } else {
-        ptr = pn;
-      }
+      ptr = A.template ptr<L>(f, qb, qb);
     }
     T v = S::ld(ptr);
+    // a wall link: the value was put in the node's own slot q (the neighbour
+    // slot read above lies across the wall and is not used)
+    if (PAR == 1 && BND && ((mask >> qb) & 1u)) v = S::ld(A.template ptr<L>(f, q, -1));
     if (P == S_F16 || P == S_BF16) v *= (T)p.inv_scale[q];
     d[q] = v;
   }
@@ -167,9 +223,9 @@ __device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f
 // bounce-back value, including the moving-wall term, for wall links):
 //   even parity: slot opp(q) of x;
 //   odd parity: slot q of x + e_q, or slot opp(q) of x for a wall link.
-template <class L, int P, int PAR, bool BND>
-__device__ __forceinline__ void write_f(typename Stor<P>::E* __restrict__ f, uint32_t nx, uint64_t n, const Offs& o,
-                                        uint32_t mask, const Phys& p, const typename Stor<P>::T (&v)[L::Q]) {
+template <class L, int P, int PAR, bool BND, class AD>
+__device__ __forceinline__ void write_f(typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask, const Phys& p,
+                                        const typename Stor<P>::T (&v)[L::Q]) {
   using S = Stor<P>;
   using T = typename S::T;
 #pragma unroll
@@ -177,26 +233,23 @@ __device__ __forceinline__ void write_f(typename Stor<P>::E* __restrict__ f, uin
     const int qb = opp(q);
     typename S::E* ptr;
     if (PAR == 0) {
-      ptr = f + n + qb * nx;
+      ptr = A.template ptr<L>(f, qb, -1);
     } else {
-      typename S::E* pn = f + (n + off_of<L>(q, o)) + q * nx;
-      if (BND) {
-        const bool bb = (mask >> q) & 1u;
-        ptr = bb ? f + n + qb * nx : pn;
-      } else {
-        ptr = pn;
-      }
+      ptr = A.template ptr<L>(f, q, q);
     }
     T s = v[q];
     if (P == S_F16 || P == S_BF16) s *= (T)p.scale[q];
-    S::st(ptr, s);
+    if (PAR == 1 && BND && ((mask >> q) & 1u))
+      S::st(A.template ptr<L>(f, qb, -1), s);  // wall link: back into the node's own slot
+    else
+      S::st(ptr, s);
   }
 }
 
 // Same pattern for the 21 induction planes (7 directions x 3 components).
-template <int P, int PAR, bool BND>
-__device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g, uint32_t nx, uint64_t n, const Offs& o,
-                                       uint32_t mask, typename Stor<P>::T (&h)[7][3]) {
+template <int P, int PAR, bool BND, class AD>
+__device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g, const AD& A, uint32_t mask,
+                                       typename Stor<P>::T (&h)[7][3]) {
   using S = Stor<P>;
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
@@ -205,24 +258,19 @@ __device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g
     for (int i = 0; i < 3; ++i) {
       const typename S::E* ptr;
       if (PAR == 0) {
-        ptr = g + n + (3 * k + i) * nx;
+        ptr = A.template ptr<D3Q19>(g, 3 * k + i, -1);
       } else {
-        const typename S::E* pn = g + (n + off_of<D3Q19>(kb, o)) + (3 * kb + i) * nx;
-        if (BND) {
-          const bool bb = (mask >> kb) & 1u;
-          ptr = bb ? g + n + (3 * k + i) * nx : pn;
-        } else {
-          ptr = pn;
-        }
+        ptr = A.template ptr<D3Q19>(g, 3 * kb + i, kb);
       }
       h[k][i] = S::ld(ptr);
+      if (PAR == 1 && BND && ((mask >> kb) & 1u)) h[k][i] = S::ld(A.template ptr<D3Q19>(g, 3 * k + i, -1));
     }
   }
 }
 
-template <int P, int PAR, bool BND>
-__device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, uint32_t nx, uint64_t n, const Offs& o,
-                                        uint32_t mask, const typename Stor<P>::T (&h)[7][3]) {
+template <int P, int PAR, bool BND, class AD>
+__device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, const AD& A, uint32_t mask,
+                                        const typename Stor<P>::T (&h)[7][3]) {
   using S = Stor<P>;
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
@@ -231,17 +279,14 @@ __device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, uin
     for (int i = 0; i < 3; ++i) {
       typename S::E* ptr;
       if (PAR == 0) {
-        ptr = g + n + (3 * kb + i) * nx;
+        ptr = A.template ptr<D3Q19>(g, 3 * kb + i, -1);
       } else {
-        typename S::E* pn = g + (n + off_of<D3Q19>(k, o)) + (3 * k + i) * nx;
-        if (BND) {
-          const bool bb = (mask >> k) & 1u;
-          ptr = bb ? g + n + (3 * kb + i) * nx : pn;
-        } else {
-          ptr = pn;
-        }
+        ptr = A.template ptr<D3Q19>(g, 3 * k + i, k);
       }
-      S::st(ptr, h[k][i]);
+      if (PAR == 1 && BND && ((mask >> k) & 1u))
+        S::st(A.template ptr<D3Q19>(g, 3 * kb + i, -1), h[k][i]);
+      else
+        S::st(ptr, h[k][i]);
     }
   }
 }
@@ -252,8 +297,7 @@ __device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, uin
 template <class T>
 struct Macro {
   T drho, rho, irho;
-  T J[3];   // momentum sum e d, rounded to T
-  T drho_lo, J_lo[3];  // rounding residuals of drho and J (FP64 sums minus T values)
+  T J[3];   // momentum sum e d
   T Je[3];  // rho u^eq formed from J: J + lEq rho A
   T U[3], A[3], V[3], Ue[3], UF[3];
   T pi[6];  // Pi^neq / c^2: xx, yy, zz, xy, xz, yz
@@ -267,28 +311,31 @@ struct Macro {
 // equilibrium in the uniform field), db = b - b0 is the induced field.
 template <class L, class T, bool MHD, bool NEED_PI>
 __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T Ay, T Az, const T (&db)[3], Macro<T>& m) {
-  // The zeroth and first moments are summed in FP64: the relaxation resets
-  // each node's mass and momentum to these sums, so their rounding would be
-  // re-injected every step (FP64 adds run at the FP32 rate on this GPU).
-  double drho_a = 0.0, jx_a = 0.0, jy_a = 0.0, jz_a = 0.0;
+  // Moments from sums and differences of opposite populations (q odd, q + 1):
+  // s = d_q + d_q+1 carries the even moments (rho, second moments), t = d_q -
+  // d_q+1 the odd ones (momentum).  Pairing values of like size first keeps
+  // the rounding of these sums small; the equilibrium below re-injects it
+  // every step.
+  T ps[(L::Q - 1) / 2], pt[(L::Q - 1) / 2];
 #pragma unroll
-  for (int q = 0; q < L::Q; ++q) {
-    const double v = (double)d[q];
-    drho_a += v;
-    if (L::ex(q) > 0) jx_a += v;
-    if (L::ex(q) < 0) jx_a -= v;
-    if (L::ey(q) > 0) jy_a += v;
-    if (L::ey(q) < 0) jy_a -= v;
-    if (L::ez(q) > 0) jz_a += v;
-    if (L::ez(q) < 0) jz_a -= v;
+  for (int k = 0; k < (L::Q - 1) / 2; ++k) {
+    ps[k] = d[2 * k + 1] + d[2 * k + 2];
+    pt[k] = d[2 * k + 1] - d[2 * k + 2];
   }
-  const T drho = (T)drho_a, jx = (T)jx_a, jy = (T)jy_a, jz = (T)jz_a;
-  m.drho_lo = (T)(drho_a - (double)drho);
-  m.J_lo[0] = (T)(jx_a - (double)jx);
-  m.J_lo[1] = (T)(jy_a - (double)jy);
-  m.J_lo[2] = (T)(jz_a - (double)jz);
+  T drho = d[0], jx = T(0), jy = T(0), jz = T(0);
+#pragma unroll
+  for (int k = 0; k < (L::Q - 1) / 2; ++k) {
+    const int q = 2 * k + 1;
+    drho += ps[k];
+    if (L::ex(q) > 0) jx += pt[k];
+    if (L::ex(q) < 0) jx -= pt[k];
+    if (L::ey(q) > 0) jy += pt[k];
+    if (L::ey(q) < 0) jy -= pt[k];
+    if (L::ez(q) > 0) jz += pt[k];
+    if (L::ez(q) < 0) jz -= pt[k];
+  }
   m.drho = drho;
-  m.rho = (T)(p.rho0 + drho_a);
+  m.rho = (T)p.rho0 + drho;
   m.irho = rcp(m.rho);
   m.J[0] = jx;
   m.J[1] = jy;
@@ -312,16 +359,17 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
   if (NEED_PI || p.les_K > 0.0) {
     T sxx = T(0), syy = T(0), szz = T(0), sxy = T(0), sxz = T(0), syz = T(0);
 #pragma unroll
-    for (int q = 0; q < L::Q; ++q) {
-      if (L::ex(q) != 0) sxx += d[q];
-      if (L::ey(q) != 0) syy += d[q];
-      if (L::ez(q) != 0) szz += d[q];
-      if (L::ex(q) * L::ey(q) > 0) sxy += d[q];
-      if (L::ex(q) * L::ey(q) < 0) sxy -= d[q];
-      if (L::ex(q) * L::ez(q) > 0) sxz += d[q];
-      if (L::ex(q) * L::ez(q) < 0) sxz -= d[q];
-      if (L::ey(q) * L::ez(q) > 0) syz += d[q];
-      if (L::ey(q) * L::ez(q) < 0) syz -= d[q];
+    for (int k = 0; k < (L::Q - 1) / 2; ++k) {
+      const int q = 2 * k + 1;  // e_q e_q is the same for q and its opposite
+      if (L::ex(q) != 0) sxx += ps[k];
+      if (L::ey(q) != 0) syy += ps[k];
+      if (L::ez(q) != 0) szz += ps[k];
+      if (L::ex(q) * L::ey(q) > 0) sxy += ps[k];
+      if (L::ex(q) * L::ey(q) < 0) sxy -= ps[k];
+      if (L::ex(q) * L::ez(q) > 0) sxz += ps[k];
+      if (L::ex(q) * L::ez(q) < 0) sxz -= ps[k];
+      if (L::ey(q) * L::ez(q) > 0) syz += ps[k];
+      if (L::ey(q) * L::ez(q) < 0) syz -= ps[k];
     }
     const T third = drho * T(1.0 / 3.0);
     const T rho = m.rho;
@@ -376,8 +424,7 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
 //   a large part at the node's own velocity u = j / rho from the rounded
 //   moments, whose difference with d (the small non-equilibrium part) is
 //   formed first, and
-//   a small part holding the shift u -> u^eq = u + lEq dt a, the rounding
-//   residuals of rho - rho0 and j (their sums are taken in FP64), and the
+//   a small part holding the shift u -> u^eq = u + lEq dt a and the
 //   magnetic term,
 // so that small quantities are never rounded at the scale of large ones.  The
 // weights 1/9, 1/18, 1/36 are applied as hi + lo parts so that the large
@@ -409,11 +456,10 @@ __device__ __forceinline__ void collide(T (&d)[L::Q], const Macro<T>& m, const T
     // large part: w [drho + 3 e.j + rho (9/2 (e.u)^2 - 3/2 u.u)]
     const T Rb = m.drho + T(3) * ej + rho * (T(4.5) * eu * eu - usq);
     const T neq = (w * Rb + wlo * Rb) - d[q];
-    // small part: rounding residuals of the moments, the u^eq shift
+    // small part: the u^eq shift
     //   rho [(e.ue)^2 9/2 - ue.ue 3/2] - (same at u) + 3 e.(rho lEq A),
     // and the magnetic term phi(b) - phi(b0)
-    T Rs = m.drho_lo + T(3) * edot<L>(q, m.J_lo[0], m.J_lo[1], m.J_lo[2]);
-    Rs += rl * (T(3) * ea + T(9) * eu * ea - T(3) * ua) + rl2 * (T(4.5) * ea * ea - T(1.5) * aa);
+    T Rs = rl * (T(3) * ea + T(9) * eu * ea - T(3) * ua) + rl2 * (T(4.5) * ea * ea - T(1.5) * aa);
     if (MHD) {
       // (e.b)^2 - (e.b0)^2 = (e.db)(e.(b + b0))
       const T edb = edot<L>(q, db[0], db[1], db[2]);
@@ -476,19 +522,16 @@ __device__ __forceinline__ void tile_sum_store(double (&v)[NV], double* __restri
 // ---------------------------------------------------------------------------
 // the fused step
 // ---------------------------------------------------------------------------
-template <class L, int P, bool MHD, int PAR, bool DIAG, bool BND>
-__device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, uint32_t x, uint32_t y, uint32_t z, uint32_t r,
-                                            const uint4& rec,
+template <class L, int P, bool MHD, int PAR, bool DIAG, bool BND, class AD>
+__device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const AD& Af, const AD& Ag, const uint4& rec,
                                             typename Stor<P>::T (&bal)[NBAL],
                                             typename Stor<P>::T (&wacc)[MAXBG][NWALL], uint32_t bgrp) {
   using S = Stor<P>;
   using T = typename S::T;
   const Geom& g = a.geo;
   const uint32_t mask = rec.x;
-  const uint64_t bf = (uint64_t)r * (L::Q * g.nx) + x;  // row-blocked base of this node
-  const Offs o = offsets(g, x, y, z, (uint64_t)L::Q * g.nx);
   T d[L::Q];
-  read_f<L, P, PAR, BND>((const typename S::E*)a.f, g.nx, bf, o, mask, a.p, d);
+  read_f<L, P, PAR, BND>((const typename S::E*)a.f, Af, mask, a.p, d);
   T Ax, Ay, Az;
   if (a.afield) {
     const T s = (T)a.p.afield_scale;
@@ -502,10 +545,8 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, uint3
   }
   T h[7][3];
   T db[3] = {T(0), T(0), T(0)};
-  const uint64_t bg = (uint64_t)r * (21 * g.nx) + x;
-  const Offs og = offsets(g, x, y, z, (uint64_t)21 * g.nx);
   if (MHD) {
-    read_g<P, PAR, BND>((const typename S::E*)a.g, g.nx, bg, og, mask, h);
+    read_g<P, PAR, BND>((const typename S::E*)a.g, Ag, mask, h);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       T s = T(0);
@@ -554,7 +595,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, uint3
       }
     }
   }
-  write_f<L, P, PAR, BND>((typename S::E*)a.f, g.nx, bf, o, mask, a.p, d);
+  write_f<L, P, PAR, BND>((typename S::E*)a.f, Af, mask, a.p, d);
   if (MHD) {
     collide_g<T>(h, m, a.p);
     if (BND) {
@@ -566,11 +607,11 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, uint3
           for (int i = 0; i < 3; ++i) h[k][i] = -h[k][i];
         }
     }
-    write_g<P, PAR, BND>((typename S::E*)a.g, g.nx, bg, og, mask, h);
+    write_g<P, PAR, BND>((typename S::E*)a.g, Ag, mask, h);
   }
 }
 
-template <class L, int P, bool MHD, int PAR, bool DIAG>
+template <class L, int P, bool MHD, int PAR, bool DIAG, bool RU>
 __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   using T = typename Stor<P>::T;
   const Geom& g = a.geo;
@@ -590,13 +631,30 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   if (active) {
     uint32_t x, y, z, r;
     coords(g, n, x, y, z, r);
+    if (RU) {
+      // every lane of the wavefront is in the same row
+      r = __builtin_amdgcn_readfirstlane(r);
+      y = __builtin_amdgcn_readfirstlane(y);
+      z = __builtin_amdgcn_readfirstlane(z);
+    }
     const int rr = a.rowrec[r];
-    if (rr < 0) {
-      const uint4 rec = make_uint4(0u, 0u, 0u, 0u);
-      node_update<L, P, MHD, PAR, DIAG, false>(a, n, x, y, z, r, rec, bal, wacc, bgrp);
-    } else {
-      const uint4 rec = a.rec[rr + x];
-      if (!(rec.x >> 31)) node_update<L, P, MHD, PAR, DIAG, true>(a, n, x, y, z, r, rec, bal, wacc, bgrp);
+    const uint4 rec = rr < 0 ? make_uint4(0u, 0u, 0u, 0u) : a.rec[rr + x];
+    if (!(rec.x >> 31)) {
+      if (RU) {
+        const AddrR Af = addr_r(g, x, y, z, L::Q);
+        const AddrR Ag = addr_r(g, x, y, z, MHD ? 21 : L::Q);
+        if (rr < 0)
+          node_update<L, P, MHD, PAR, DIAG, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+        else
+          node_update<L, P, MHD, PAR, DIAG, true>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+      } else {
+        const AddrG Af = addr_g(g, x, y, z, r, L::Q);
+        const AddrG Ag = addr_g(g, x, y, z, r, MHD ? 21 : L::Q);
+        if (rr < 0)
+          node_update<L, P, MHD, PAR, DIAG, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+        else
+          node_update<L, P, MHD, PAR, DIAG, true>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+      }
     }
   }
   if (DIAG) {
@@ -642,11 +700,9 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
   if (n < g.N) {
     uint32_t x, y, z, r;
     coords(g, n, x, y, z, r);
-    const Offs o = offsets(g, x, y, z, (uint64_t)L::Q * g.nx);
-    const Offs og = offsets(g, x, y, z, (uint64_t)21 * g.nx);
+    const AddrG Af = addr_g(g, x, y, z, r, L::Q);
+    const AddrG Ag = addr_g(g, x, y, z, r, 21);
     const Offs on = offsets(g, x, y, z, (uint64_t)g.nx);  // node-index offsets
-    const uint64_t bf = (uint64_t)r * (L::Q * g.nx) + x;
-    const uint64_t bg = (uint64_t)r * (21 * g.nx) + x;
     const int rr = a.rowrec[r];
     const uint4 rec = rr >= 0 ? a.rec[rr + x] : make_uint4(0u, 0u, 0u, 0u);
     const bool solid = rec.x >> 31;
@@ -657,7 +713,7 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
     Macro<T> m = {};
     if (!solid) {
       TS ds[L::Q];
-      read_f<L, P, PAR, true>((const typename S::E*)a.f, g.nx, bf, o, rec.x, a.p, ds);
+      read_f<L, P, PAR, true>((const typename S::E*)a.f, Af, rec.x, a.p, ds);
 #pragma unroll
       for (int q = 0; q < L::Q; ++q) d[q] = (T)ds[q];
       T Ax, Ay, Az;
@@ -673,7 +729,7 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
       }
       if (MHD) {
         TS hs[7][3];
-        read_g<P, PAR, true>((const typename S::E*)a.g, g.nx, bg, og, rec.x, hs);
+        read_g<P, PAR, true>((const typename S::E*)a.g, Ag, rec.x, hs);
 #pragma unroll
         for (int k = 0; k < 7; ++k)
 #pragma unroll
@@ -871,20 +927,28 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // launchers (called by the host library)
 // ---------------------------------------------------------------------------
+template <class L, int P, bool MHD, bool RU>
+static void launch_step_ru(const StepArgs& a, int parity, bool diag, uint32_t nb, hipStream_t st) {
+  if (parity == 0) {
+    if (diag)
+      k_step<L, P, MHD, 0, true, RU><<<nb, NTHREADS, 0, st>>>(a);
+    else
+      k_step<L, P, MHD, 0, false, RU><<<nb, NTHREADS, 0, st>>>(a);
+  } else {
+    if (diag)
+      k_step<L, P, MHD, 1, true, RU><<<nb, NTHREADS, 0, st>>>(a);
+    else
+      k_step<L, P, MHD, 1, false, RU><<<nb, NTHREADS, 0, st>>>(a);
+  }
+}
+
 template <class L, int P, bool MHD>
 static hipError_t launch_step_t(const StepArgs& a, int parity, bool diag, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
-  if (parity == 0) {
-    if (diag)
-      k_step<L, P, MHD, 0, true><<<nb, NTHREADS, 0, st>>>(a);
-    else
-      k_step<L, P, MHD, 0, false><<<nb, NTHREADS, 0, st>>>(a);
-  } else {
-    if (diag)
-      k_step<L, P, MHD, 1, true><<<nb, NTHREADS, 0, st>>>(a);
-    else
-      k_step<L, P, MHD, 1, false><<<nb, NTHREADS, 0, st>>>(a);
-  }
+  if (a.geo.nx % 64 == 0)
+    launch_step_ru<L, P, MHD, true>(a, parity, diag, nb, st);
+  else
+    launch_step_ru<L, P, MHD, false>(a, parity, diag, nb, st);
   return hipGetLastError();
 }
 
