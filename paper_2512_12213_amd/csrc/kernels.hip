@@ -129,19 +129,24 @@ struct AddrG {
 };
 
 // Row-uniform form, used when nx is a multiple of 64: a wavefront then never
-// leaves its x-row, so the start of each of the nine neighbour rows is
-// wave-uniform (scalar registers) and each lane only adds its 32-bit x index
-// (scalar base + vector offset addressing).
+// leaves its x-row, so y, z and every neighbour-row base are wave-uniform
+// (scalar registers) and each lane only adds its 32-bit x byte offset
+// (scalar base + vector offset addressing).  The row bases are recomputed in
+// ptr() rather than kept in an array, so that the compiler never turns a
+// per-lane choice between two slots into a dynamic index of private memory.
 struct AddrR {
-  uint64_t rb[3][3];  // element index of row (y + dy, z + dz), dy, dz in {-1, 0, 1}
-  uint32_t xi[3];     // x - 1, x, x + 1 (periodic)
+  uint32_t y, z, ny, nz;
+  uint32_t x, xm, xp;  // x, x - 1, x + 1 (periodic), per lane
   uint32_t nx;
+  uint64_t rs;         // row stride, planes * nx
   template <class L, class E>
   __device__ __forceinline__ E* ptr(E* f, int plane, int q) const {
     const int dx = q < 0 ? 0 : L::ex(q), dy = q < 0 ? 0 : L::ey(q), dz = q < 0 ? 0 : L::ez(q);
-    E* base = f + (rb[dy + 1][dz + 1] + (uint32_t)plane * nx);  // wave-uniform
-    const uint32_t off = xi[dx + 1] * (uint32_t)sizeof(E);         // 32-bit byte offset
-    return (E*)((char*)base + off);
+    const uint32_t yy = dy < 0 ? (y == 0 ? ny - 1 : y - 1) : (dy > 0 ? (y + 1 == ny ? 0 : y + 1) : y);
+    const uint32_t zz = dz < 0 ? (z == 0 ? nz - 1 : z - 1) : (dz > 0 ? (z + 1 == nz ? 0 : z + 1) : z);
+    E* base = f + (((uint64_t)zz * ny + yy) * rs + (uint32_t)plane * nx);  // wave-uniform
+    const uint32_t xs = dx < 0 ? xm : (dx > 0 ? xp : x);
+    return (E*)((char*)base + xs * (uint32_t)sizeof(E));  // 32-bit byte offset
   }
 };
 
@@ -156,20 +161,25 @@ __device__ __forceinline__ AddrG addr_g(const Geom& g, uint32_t x, uint32_t y, u
 // y, z must be wave-uniform.
 __device__ __forceinline__ AddrR addr_r(const Geom& g, uint32_t x, uint32_t y, uint32_t z, uint32_t P) {
   AddrR a;
-  const uint64_t rs = (uint64_t)P * g.nx;
-#pragma unroll
-  for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-    for (int dz = -1; dz <= 1; ++dz) {
-      uint32_t yy = (dy < 0) ? (y == 0 ? g.ny - 1 : y - 1) : (dy > 0 ? (y + 1 == g.ny ? 0 : y + 1) : y);
-      uint32_t zz = (dz < 0) ? (z == 0 ? g.nz - 1 : z - 1) : (dz > 0 ? (z + 1 == g.nz ? 0 : z + 1) : z);
-      a.rb[dy + 1][dz + 1] = ((uint64_t)zz * g.ny + yy) * rs;
-    }
-  a.xi[0] = x == 0 ? g.nx - 1 : x - 1;
-  a.xi[1] = x;
-  a.xi[2] = x + 1 == g.nx ? 0 : x + 1;
+  a.y = y;
+  a.z = z;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.x = x;
+  a.xm = x == 0 ? g.nx - 1 : x - 1;
+  a.xp = x + 1 == g.nx ? 0 : x + 1;
   a.nx = g.nx;
+  a.rs = (uint64_t)P * g.nx;
   return a;
+}
+
+// Per-lane choice between two addresses, written as mask arithmetic on the
+// address values so that it is not folded into an indexed access of the
+// address objects' fields.
+template <class E>
+__device__ __forceinline__ E* pick(bool c, E* a, E* b) {
+  const uint64_t m = 0ull - (uint64_t)c;
+  return (E*)(((uint64_t)a & m) | ((uint64_t)b & ~m));
 }
 
 template <class L, class T>
@@ -210,10 +220,9 @@ __device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f
     } else {
       ptr = A.template ptr<L>(f, qb, qb);
     }
+    // a wall link: the value was put in the node's own slot q
+    if (PAR == 1 && BND) ptr = pick((mask >> qb) & 1u, A.template ptr<L>(f, q, -1), ptr);
     T v = S::ld(ptr);
-    // a wall link: the value was put in the node's own slot q (the neighbour
-    // slot read above lies across the wall and is not used)
-    if (PAR == 1 && BND && ((mask >> qb) & 1u)) v = S::ld(A.template ptr<L>(f, q, -1));
     if (P == S_F16 || P == S_BF16) v *= (T)p.inv_scale[q];
     d[q] = v;
   }
@@ -246,6 +255,25 @@ __device__ __forceinline__ void write_f(typename Stor<P>::E* __restrict__ f, con
   }
 }
 
+// One direction of write_f.
+template <class L, int P, int PAR, bool BND, class AD>
+__device__ __forceinline__ void write_f1(typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask, const Phys& p,
+                                         int q, typename Stor<P>::T v) {
+  using S = Stor<P>;
+  using T = typename S::T;
+  const int qb = opp(q);
+  T s = v;
+  if (P == S_F16 || P == S_BF16) s *= (T)p.scale[q];
+  if (PAR == 0) {
+    S::st(A.template ptr<L>(f, qb, -1), s);
+  } else if (BND) {
+    // wall link: back into the node's own slot
+    S::st(pick((mask >> q) & 1u, A.template ptr<L>(f, qb, -1), A.template ptr<L>(f, q, q)), s);
+  } else {
+    S::st(A.template ptr<L>(f, q, q), s);
+  }
+}
+
 // Same pattern for the 21 induction planes (7 directions x 3 components).
 template <int P, int PAR, bool BND, class AD>
 __device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g, const AD& A, uint32_t mask,
@@ -262,8 +290,8 @@ __device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g
       } else {
         ptr = A.template ptr<D3Q19>(g, 3 * kb + i, kb);
       }
+      if (PAR == 1 && BND) ptr = pick((mask >> kb) & 1u, A.template ptr<D3Q19>(g, 3 * k + i, -1), ptr);
       h[k][i] = S::ld(ptr);
-      if (PAR == 1 && BND && ((mask >> kb) & 1u)) h[k][i] = S::ld(A.template ptr<D3Q19>(g, 3 * k + i, -1));
     }
   }
 }
@@ -283,10 +311,8 @@ __device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, con
       } else {
         ptr = A.template ptr<D3Q19>(g, 3 * k + i, k);
       }
-      if (PAR == 1 && BND && ((mask >> k) & 1u))
-        S::st(A.template ptr<D3Q19>(g, 3 * kb + i, -1), h[k][i]);
-      else
-        S::st(ptr, h[k][i]);
+      if (PAR == 1 && BND) ptr = pick((mask >> k) & 1u, A.template ptr<D3Q19>(g, 3 * kb + i, -1), ptr);
+      S::st(ptr, h[k][i]);
     }
   }
 }
@@ -429,8 +455,11 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
 // so that small quantities are never rounded at the scale of large ones.  The
 // weights 1/9, 1/18, 1/36 are applied as hi + lo parts so that the large
 // part's moments are not scaled by the weights' own rounding.
-template <class L, class T, bool MHD>
-__device__ __forceinline__ void collide(T (&d)[L::Q], const Macro<T>& m, const T (&db)[3], const Phys& p) {
+// sink(q, value) receives each post-collision value as soon as it is formed,
+// so that it can be stored at once and its register freed.
+template <class L, class T, bool MHD, class Sink>
+__device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, const T (&db)[3], const Phys& p,
+                                        Sink&& sink) {
   const T rho = m.rho;
   const T lEq = (T)p.lEq;
   const T usq = T(1.5) * (m.U[0] * m.U[0] + m.U[1] * m.U[1] + m.U[2] * m.U[2]);
@@ -468,7 +497,7 @@ __device__ __forceinline__ void collide(T (&d)[L::Q], const Macro<T>& m, const T
     }
     const T euf = edot<L>(q, m.UF[0], m.UF[1], m.UF[2]);
     const T F = cr * w * (T(3) * (ea - ufa) + T(9) * euf * ea);
-    d[q] = d[q] + (neq + w * Rs) * itau + F;
+    sink(q, d[q] + (neq + w * Rs) * itau + F);
   }
 }
 
@@ -566,36 +595,33 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
     bal[5] += m.rho * m.A[1];
     bal[6] += m.rho * m.A[2];
   }
-  collide<L, T, MHD>(d, m, db, a.p);
-  if (BND) {
-    // halfway bounce-back links: the returning population is d_rel plus
-    // the moving-wall term 6 w rho (e_opp . u_w) / c^2; Eq. (25) momentum
-    // exchange per link is proportional to e_q (2 d_rel + ladd) beyond the
-    // constant rest-state part, which the host adds from link counts.
+  typename S::E* fo = (typename S::E*)a.f;
+  collide<L, T, MHD>(d, m, db, a.p, [&](int q, T v) __attribute__((always_inline)) {
+    if (BND && q > 0 && ((mask >> q) & 1u)) {
+      // halfway bounce-back link: the returning population is d_rel plus the
+      // moving-wall term 6 w rho (e_opp . u_w) / c^2; the Eq. (25) momentum
+      // exchange per link is proportional to e_q (2 d_rel + ladd) beyond the
+      // constant rest-state part, which the host adds from link counts.
+      const uint32_t gr = nibble(rec, q);
+      const T ux = (T)a.uw[3 * gr], uy = (T)a.uw[3 * gr + 1], uz = (T)a.uw[3 * gr + 2];  // u_w / c
+      const T ladd = T(-6) * (T)L::w(q) * m.rho * edot<L>(q, ux, uy, uz);
+      const T out = v;
+      v = out + ladd;
+      if (DIAG) {
+        const T cq = out + v;
 #pragma unroll
-    for (int q = 1; q < L::Q; ++q) {
-      if ((mask >> q) & 1u) {
-        const uint32_t gr = nibble(rec, q);
-        const T ux = (T)a.uw[3 * gr], uy = (T)a.uw[3 * gr + 1], uz = (T)a.uw[3 * gr + 2];  // u_w / c
-        const T ladd = T(-6) * (T)L::w(q) * m.rho * edot<L>(q, ux, uy, uz);
-        const T out = d[q];
-        d[q] = out + ladd;
-        if (DIAG) {
-          const T cq = out + d[q];
-#pragma unroll
-          for (int s = 0; s < MAXBG; ++s) {
-            if (((bgrp >> (4 * s)) & 15u) == gr) {
-              wacc[s][0] += (T)L::ex(q) * cq;
-              wacc[s][1] += (T)L::ey(q) * cq;
-              wacc[s][2] += (T)L::ez(q) * cq;
-              wacc[s][3] += ladd;
-            }
+        for (int s = 0; s < MAXBG; ++s) {
+          if (((bgrp >> (4 * s)) & 15u) == gr) {
+            wacc[s][0] += (T)L::ex(q) * cq;
+            wacc[s][1] += (T)L::ey(q) * cq;
+            wacc[s][2] += (T)L::ez(q) * cq;
+            wacc[s][3] += ladd;
           }
         }
       }
     }
-  }
-  write_f<L, P, PAR, BND>((typename S::E*)a.f, Af, mask, a.p, d);
+    write_f1<L, P, PAR, BND>(fo, Af, mask, a.p, q, v);
+  });
   if (MHD) {
     collide_g<T>(h, m, a.p);
     if (BND) {
