@@ -1,21 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the fused LBM step on one MI355X.
 
-Workload: D3Q19 square duct 256x128x128, periodic x, halfway bounce-back
-walls on y and z, tau0 = 0.52 with Smagorinsky closure (C_s = 0.1), Guo
-forcing a_x = 1e-5, seeded +-1e-3 initial velocity, FP32 storage and
-arithmetic.  A step is one call-level pass of the whole hot path: the
-fused relax-propagate kernel (moments, equilibrium, force term, LES,
+Headline workload: D3Q19 square duct 256x128x128, periodic x, halfway
+bounce-back walls on y and z, tau0 = 0.52 with Smagorinsky closure
+(C_s = 0.1), Guo forcing a_x = 1e-5, seeded +-1e-3 initial velocity, FP32
+storage and arithmetic.  A step is one call-level pass of the whole hot path:
+the fused relax-propagate kernel (moments, equilibrium, force term, LES
 relaxation, in-place A-A streaming with bounce-back) every step, plus the
 wall-force and balance reductions of the last step of the call.
 
-Prints ONE JSON line (rank 0).  ``value`` = MLUPS (lattice updates per
-second / 1e6) with the state resident in HBM.  ``roofline`` relates the
-algorithmic bytes of the step kernel (2 Q s bytes per node: each of Q
-distributions read and written once, s = bytes per stored value) to its
-average launch time measured with HIP events on the stream the kernel runs
-on.  ``cpu_baseline`` times the FP64 CPU oracle on a bounded sample of the
-same workload on this host.
+Prints ONE JSON line.  ``value`` = MLUPS of whole lbm_step calls (lattice
+updates per second / 1e6, state resident in HBM, HIP events around the call
+on the library's stream).  ``roofline.achieved`` = algorithmic bytes of one
+step launch (2 Q s bytes per node: each of Q distributions read and written
+once, s bytes per stored value) / the step kernel's mean launch duration,
+measured with HIP events recorded between consecutive launches on that
+stream.  ``cpu_baseline`` times the FP64 CPU reference on a bounded sample
+of the same workload on this host.
 """
 import argparse
 import json
@@ -29,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BYTES = {0: 8, 1: 4, 2: 2, 3: 2}  # storage -> bytes per value
 
 
 def parse():
@@ -36,17 +38,23 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-variants", action="store_true", help="skip the other storage precisions")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
+    ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and workloads")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run one 1 GiB device-to-device copy (a plain copy kernel of known size, "
+                         "used to scale hardware byte counters)")
     return ap.parse_args()
 
 
-def timed_steps(lat, torch, steps):
-    """Run `steps` steps in one lbm_step call bracketed by HIP events on the
-    library's stream (torch's current stream); returns seconds."""
+def timed_run(lbm, torch, w, steps, warmup, storage=None):
+    """Warm up, then time one lbm_step(steps) call; returns a result dict."""
+    lat = lbm.from_workload(w, storage=storage)
     stream = torch.cuda.current_stream()
     lat.set_stream(stream.cuda_stream)
+    if warmup:
+        lat.step(warmup)
+    lat.set_timing(True)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -54,28 +62,25 @@ def timed_steps(lat, torch, steps):
     lat.step(steps)
     e1.record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) * 1e-3
-
-
-def run_variant(W, lbm, torch, storage, steps, warmup):
-    w = W.duct_les(storage=storage)
-    lat = lbm.from_workload(w)
-    lat.set_stream(torch.cuda.current_stream().cuda_stream)
-    if warmup:
-        lat.step(warmup)
-    t = timed_steps(lat, torch, steps)
+    t = e0.elapsed_time(e1) * 1e-3
+    tim = lat.step_timings()
     bal = lat.force_balance()
     fw = lat.wall_force()
     lat.close()
-    bytes_per_node = 2 * w.Q * {W.F64: 8, W.F32: 4, W.F16: 2, W.BF16: 2}[storage]
-    mlups = w.N * steps / t / 1e6
+    st = w.storage if storage is None else storage
+    bpn = 2 * w.Q * BYTES[st] + (2 * 21 * BYTES[st] if w.mhd is not None else 0)
+    n_even = (steps - 1 + 1) // 2
+    launch = (tim["even"] * n_even + tim["odd"] * (steps - 1 - n_even)) / max(steps - 1, 1)
     return {
-        "mlups": mlups,
+        "mlups": w.N * steps / t / 1e6,
         "ms_per_step": t * 1e3 / steps,
-        "gbs": bytes_per_node * w.N * steps / t / 1e9,
-        "frac": bytes_per_node * w.N * steps / t / 1e9 / HBM_PEAK_GBS,
+        "launch_us": {"even": tim["even"] * 1e6, "odd": tim["odd"] * 1e6, "mean": launch * 1e6,
+                      "diagnostic_last_step": tim["diag"] * 1e6, "reduce_and_copy": tim["tail"] * 1e6},
+        "bytes_per_launch": bpn * w.N,
+        "achieved_gbs": bpn * w.N / launch / 1e9,
+        "frac": bpn * w.N / launch / 1e9 / HBM_PEAK_GBS,
         "balance_residual_rel": float(np.abs(bal[9:12]).max() / max(abs(bal[3]), 1e-300)),
-        "wall_drag_x": float(fw[:, 0, 0].sum()),
+        "wall_force_x_total": float(fw[:, 0, 0].sum()),
     }
 
 
@@ -118,33 +123,25 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     lbm.lib()
+    if args.calibrate:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
-    # headline: FP32 storage
     w = W.duct_les()
-    lat = lbm.from_workload(w)
-    lat.set_stream(torch.cuda.current_stream().cuda_stream)
-    print("bench: warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
-    if args.warmup:
-        lat.step(args.warmup)
-    torch.cuda.synchronize()
-    print("bench: timing %d steps" % args.steps, file=sys.stderr, flush=True)
-    t = timed_steps(lat, torch, args.steps)
-    bal = lat.force_balance()
-    lat.close()
-    N = w.N
-    mlups = N * args.steps / t / 1e6
-    bytes_per_launch = 2 * w.Q * 4 * N  # 152 B per node for FP32 D3Q19
-    launch_s = t / args.steps
-    achieved = bytes_per_launch / launch_s / 1e9
-
+    print("bench: headline FP32 duct, warmup %d, timed %d steps" % (args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    r = timed_run(lbm, torch, w, args.steps, args.warmup)
     out = {
         "metric": "MLUPS + % HBM roofline (FP32/16-bit vs FP64 at stated err); adjoint MLUPS",
-        "value": round(mlups, 1),
+        "value": round(r["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t * 1e3 / args.steps, 5),
+        "ms_per_step": round(r["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -155,28 +152,41 @@ def main():
             "lattice": "D3Q19", "nx": w.nx, "ny": w.ny, "nz": w.nz,
             "storage": "f32", "force_model": "guo", "tau0": w.tau, "les_cs": w.les_cs,
             "a_x": w.body_force[0], "u0": "uniform +-1e-3, seed 2512",
-            "streaming": "in-place A-A", "diagnostics": "wall force + balance on the last step of the call",
+            "streaming": "in-place A-A, row-blocked layout",
+            "diagnostics": "wall force + balance on the last step of each call",
         },
         "roofline": {
             "bound": "hbm",
-            "achieved": round(achieved, 1),
+            "achieved": round(r["achieved_gbs"], 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "frac": round(r["frac"], 4),
             "traffic": None,
-            "kernel": "k_step<D3Q19, F32> (even/odd A-A parities alternate; average over both)",
-            "bytes_per_launch": bytes_per_launch,
+            "kernel": "lbm::k_step<D3Q19, F32, no MHD, parity, no diagnostics, row-uniform>",
+            "bytes_per_launch": r["bytes_per_launch"],
+            "launch_us": {k: round(v, 2) for k, v in r["launch_us"].items()},
         },
-        "balance_residual_rel": float(np.abs(bal[9:12]).max() / max(abs(bal[3]), 1e-300)),
+        "balance_residual_rel": r["balance_residual_rel"],
     }
     if not args.no_variants:
         variants = {}
-        for name, st in (("f16", W.F16), ("bf16", W.BF16), ("f64", W.F64)):
+        half = max(args.steps // 2, 10)
+        for name, st in (("duct_f16", W.F16), ("duct_bf16", W.BF16), ("duct_f64", W.F64)):
             print("bench: variant %s" % name, file=sys.stderr, flush=True)
-            variants[name] = run_variant(W, lbm, torch, st, max(args.steps // 2, 10), min(args.warmup, 10))
+            variants[name] = timed_run(lbm, torch, w, half, min(args.warmup, 10), storage=st)
+        print("bench: variant hartmann duct", file=sys.stderr, flush=True)
+        variants["hartmann_duct_f32_192x96x96"] = timed_run(lbm, torch, W.hartmann_duct(), half, 10)
+        print("bench: variant couette cylinder", file=sys.stderr, flush=True)
+        variants["couette_cylinder_f32_512x128"] = timed_run(lbm, torch, W.couette_cylinder(), 2000, 100)
+        print("bench: variant poiseuille", file=sys.stderr, flush=True)
+        variants["poiseuille_f64_64x32"] = timed_run(lbm, torch, W.poiseuille(), 5000, 100)
+        for v in variants.values():
+            for k in ("mlups", "ms_per_step", "achieved_gbs", "frac"):
+                v[k] = round(v[k], 4 if k == "frac" else 2)
+            v["launch_us"] = {k: round(x, 2) for k, x in v["launch_us"].items()}
         out["variants"] = variants
     if not args.no_cpu:
-        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        print("bench: CPU reference baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

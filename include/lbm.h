@@ -52,7 +52,7 @@ enum { LBM_MAX_GROUPS = 16, LBM_NREC = 24 };
 /* Create a lattice.  Section 2: uniform grid with spacing dx, time step dt,
  * relaxation time tau (tau > 1/2), D2Q9 (nz must be 1) or D3Q19.  All axes
  * are periodic until walls are added.  Storage defaults to LBM_F32, rho0 to 1.
- * Limits: every axis <= 65536 nodes; a distribution plane must fit in 4 GiB.
+ * Limits: every axis <= 65536 nodes and fewer than 2^31 nodes in total.
  * Returns NULL on error (lbm_last_error() explains). */
 lbm_ctx* lbm_create(int lattice, int nx, int ny, int nz, double tau, double dx, double dt, int force_model);
 
@@ -185,6 +185,16 @@ long lbm_link_count(lbm_ctx* ctx, int group);
 
 /* Steps taken since the last initialisation. */
 long lbm_steps_taken(lbm_ctx* ctx);
+
+/* Per-launch timing of lbm_step with HIP events recorded on the context's
+ * stream between consecutive launches (on = 1; adds one event per launch).
+ * lbm_step_timings fills out[6] for the most recent timed call, in seconds:
+ * 0 mean duration of an even-parity step launch, 1 of an odd-parity one
+ * (both excluding the call's last, diagnostic, step), 2 the diagnostic step,
+ * 3 the reduction and 568-byte copy that follow it, 4 launches in the call,
+ * 5 the whole call from the first launch to the end of the copy. */
+int lbm_set_timing(lbm_ctx* ctx, int on);
+int lbm_step_timings(lbm_ctx* ctx, double* out);
 
 #ifdef __cplusplus
 }

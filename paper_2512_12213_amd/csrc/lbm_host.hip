@@ -116,6 +116,10 @@ struct lbm_ctx {
   bool have_step = false;
   double last[NBAL + MAXG * NWALL] = {};
   double last_uw[MAXG][3] = {};
+  // optional per-launch timing of lbm_step (HIP events on the context stream)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  double tim[6] = {};  // mean even-parity step, mean odd-parity step, diagnostic step, reduce+copy, launches, call
 };
 
 namespace {
@@ -392,6 +396,7 @@ lbm_ctx* lbm_create(int lattice, int nx, int ny, int nz, double tau, double dx, 
 void lbm_destroy(lbm_ctx* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   if (h->hred) (void)hipHostFree(h->hred);
   if (h->own) (void)hipStreamDestroy(h->own);
   delete h;
@@ -605,15 +610,51 @@ int lbm_step(lbm_ctx* h, int n) {
     h->uw_dirty = false;
   }
   StepArgs a = step_args(h);
+  if (h->timing) {
+    while (h->ev.size() < (size_t)n + 2) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      h->ev.push_back(e);
+    }
+  }
+  const int par0 = h->parity;
+  if (h->timing) HIPCHK(hipEventRecord(h->ev[0], h->stream));
   for (int i = 0; i < n; ++i) {
     const bool diag = i == n - 1;
     HIPCHK(launch_step(h->lattice, h->prec, h->mhd, a, h->parity, diag, h->stream));
+    if (h->timing) HIPCHK(hipEventRecord(h->ev[i + 1], h->stream));
     h->parity ^= 1;
   }
   HIPCHK(launch_reduce((const double*)h->part.p, (const uint32_t*)h->blkgrp.p, h->ntiles, 0, NBAL + MAXG * NWALL,
                        (double*)h->red.p, h->stream));
   HIPCHK(hipMemcpyAsync(h->hred, h->red.p, (NBAL + MAXG * NWALL) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (h->timing) HIPCHK(hipEventRecord(h->ev[n + 1], h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
+  if (h->timing) {
+    double se = 0, so = 0;
+    int ne = 0, no = 0;
+    for (int i = 0; i < n; ++i) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
+      if (i == n - 1) {
+        h->tim[2] = ms * 1e-3;
+      } else if (((par0 + i) & 1) == 0) {
+        se += ms * 1e-3;
+        ++ne;
+      } else {
+        so += ms * 1e-3;
+        ++no;
+      }
+    }
+    float ms = 0, tot = 0;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev[n], h->ev[n + 1]));
+    HIPCHK(hipEventElapsedTime(&tot, h->ev[0], h->ev[n + 1]));
+    h->tim[0] = ne ? se / ne : 0;
+    h->tim[1] = no ? so / no : 0;
+    h->tim[3] = ms * 1e-3;
+    h->tim[4] = n;
+    h->tim[5] = tot * 1e-3;
+  }
   std::memcpy(h->last, h->hred, sizeof(h->last));
   std::memcpy(h->last_uw, h->uw, sizeof(h->last_uw));
   h->steps += n;
@@ -793,6 +834,19 @@ long lbm_link_count(lbm_ctx* h, int group) {
     for (int q = 0; q < h->Q; ++q) s += h->nlink[(size_t)gr * h->Q + q];
   }
   return s;
+}
+
+int lbm_set_timing(lbm_ctx* h, int on) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  h->timing = on != 0;
+  return LBM_OK;
+}
+
+int lbm_step_timings(lbm_ctx* h, double* out) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (!out) return fail(LBM_EINVAL, "null buffer");
+  for (int k = 0; k < 6; ++k) out[k] = h->tim[k];
+  return LBM_OK;
 }
 
 long lbm_steps_taken(lbm_ctx* h) {

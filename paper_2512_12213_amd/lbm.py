@@ -50,6 +50,8 @@ _SIGS = [
     ("lbm_num_groups", C.c_int, [_P]),
     ("lbm_link_count", C.c_long, [_P, C.c_int]),
     ("lbm_steps_taken", C.c_long, [_P]),
+    ("lbm_set_timing", C.c_int, [_P, C.c_int]),
+    ("lbm_step_timings", C.c_int, [_P, _D]),
 ]
 EXPORTED = [s[0] for s in _SIGS]
 
@@ -228,6 +230,15 @@ class Lattice:
 
     def steps_taken(self):
         return self.L.lbm_steps_taken(self.h)
+
+    def set_timing(self, on=True):
+        _chk(self.L.lbm_set_timing(self.h, int(on)))
+
+    def step_timings(self):
+        """dict of seconds: even, odd (mean step launches), diag, tail, launches, call"""
+        out = np.empty(6)
+        _chk(self.L.lbm_step_timings(self.h, _dp(out)))
+        return dict(zip(("even", "odd", "diag", "tail", "launches", "call"), out.tolist()))
 
 
 def from_workload(w, storage=None, u0=None, init=True):
