@@ -19,6 +19,7 @@ stream.  ``cpu_baseline`` times the FP64 CPU reference on a bounded sample
 of the same workload on this host.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -31,6 +32,33 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES = {0: 8, 1: 4, 2: 2, 3: 2}  # storage -> bytes per value
+KERNEL_SOURCES = ("paper_2512_12213_amd/csrc/kernels.hip", "paper_2512_12213_amd/csrc/kernels.hpp",
+                  "paper_2512_12213_amd/csrc/lattice.hpp", "paper_2512_12213_amd/build.py")
+TRAFFIC_RECORD = "profiles/k_step_d3q19_f32_duct_les_256x128x128.md"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per step launch from the committed hardware-counter record,
+    or None when the kernel sources changed since the counters were taken."""
+    try:
+        rec = {}
+        with open(os.path.join(ROOT, TRAFFIC_RECORD)) as f:
+            for line in f:
+                k, _, v = line.strip().partition(": ")
+                rec[k] = v
+        if rec.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        return int(rec["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -161,7 +189,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(r["frac"], 4),
-            "traffic": None,
+            "traffic": measured_traffic(),
             "kernel": "lbm::k_step<D3Q19, F32, no MHD, parity, no diagnostics, row-uniform>",
             "bytes_per_launch": r["bytes_per_launch"],
             "launch_us": {k: round(v, 2) for k, v in r["launch_us"].items()},
