@@ -57,6 +57,7 @@ def _lib(complex_step: bool):
         lib.orc_force_balance.argtypes = [P, dp]
         lib.orc_link_count.restype = C.c_long
         lib.orc_link_count.argtypes = [P, C.c_int]
+        lib.orc_adjoint.argtypes = [P, C.c_int, C.c_int, C.c_int, dp, dp, dp]
         _libs[name] = lib
     return _libs[name]
 
@@ -196,3 +197,16 @@ class Oracle:
 
     def link_count(self, group=-1):
         return self.lib.orc_link_count(self.h, group)
+
+    def adjoint(self, T, group, axis):
+        """Reverse-mode gradient of J = component `axis` of the raw wall force
+        on `group` during the last of T steps from the current state (complex
+        build only).  Returns (J, grad_a [3, nz, ny, nx], grad_uw [G, 3]) in
+        physical units; the state is left at step T."""
+        if not self.cs:
+            raise ValueError("the adjoint needs the complex-step build")
+        J = np.zeros(1)
+        ga = np.zeros((3, self.nz, self.ny, self.nx))
+        gu = np.zeros((max(self.groups, 1), 3))
+        self._chk(self.lib.orc_adjoint(self.h, T, group, axis, _dp(J), _dp(ga), _dp(gu)))
+        return float(J[0]), ga, gu

@@ -297,8 +297,10 @@ typedef struct {
   real E[3][3];  /* artefact term E_ij of Eq. (9) */
 } node_t;
 
-/* Moments, model velocities, Pi^neq, Smagorinsky tau, force term. */
-static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, node_t* s) {
+/* Moments, model velocities, Pi^neq, Smagorinsky tau, force term.  a_node,
+ * when not NULL, replaces the node's body force (used to differentiate with
+ * respect to it). */
+static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, const real* a_node, node_t* s) {
   const int D = o->D, Q = o->Q;
   const double c = o->c, c2 = c * c, dt = o->dt;
   memset(s, 0, sizeof(*s));
@@ -314,7 +316,7 @@ static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, n
   s->drho = drho;
   for (int k = 0; k < 3; ++k) {
     s->u[k] = k < D ? j[k] / rho : 0;
-    s->a[k] = k < D ? body_force(o, idx, k) : 0;
+    s->a[k] = k < D ? (a_node ? a_node[k] : body_force(o, idx, k)) : 0;
     s->v[k] = s->u[k] + 0.5 * dt * s->a[k]; /* v = u + dt a / 2 for all models */
     s->B[k] = Bn ? Bn[k] : 0;
   }
@@ -484,6 +486,25 @@ int orc_get_induction(const orc* o, double* g) {
 /* per-row partial sums: [G][3][3] wall force, then M, P[3], rho_a[3] */
 static int part_size(const orc* o) { return o->G * 9 + 7; }
 
+/* Everything of one node's update before propagation: node_setup, then the
+ * relaxation of Eq. (2), drel = d + (d^eq - d)/tau + F, with the equilibrium
+ * of Eq. (1) (+ the magnetic term of Eq. 10). */
+static void node_relax(const orc* o, const real* dl, long idx, const real* Bn, const real* a_node, node_t* s,
+                       real* drel) {
+  node_setup(o, dl, idx, Bn, a_node, s);
+  for (int q = 0; q < o->Q; ++q) {
+    real deq = feq_dev(o, q, s->rho, s->drho, s->ueq);
+    if (o->mhd) deq += phi_mhd(o, q, s->B);
+    drel[q] = dl[q] + (deq - dl[q]) / s->tau + s->F[q];
+  }
+}
+
+/* Moving wall (halfway bounce-back, Ladd): the population returning along
+ * opp(q) gains 6 w_q rho (e_opp(q) . u_w) / c^2. */
+static real moving_wall_term(const orc* o, int q, real rho, const real* uw) {
+  return 6.0 * o->w[q] * rho * edot(o, o->opp[q], uw) / (o->c * o->c);
+}
+
 static void update_node(orc* o, int x, int y, int z, real* part) {
   const int D = o->D, Q = o->Q;
   const long N = o->N;
@@ -502,7 +523,7 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
       }
   }
   node_t s;
-  node_setup(o, dl, idx, o->mhd ? Bn : NULL, &s);
+  node_relax(o, dl, idx, o->mhd ? Bn : NULL, NULL, &s, drel);
 
   /* balance partials at time t (Eq. 32): mass, momentum, body force */
   real* pb = part + o->G * 9;
@@ -510,13 +531,6 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
   for (int k = 0; k < 3; ++k) {
     pb[1 + k] += vol * s.rho * s.u[k];
     pb[4 + k] += vol * s.rho * s.a[k];
-  }
-
-  /* relaxation, Eq. (2): f_rel = f + (f^eq - f)/tau + F */
-  for (int q = 0; q < Q; ++q) {
-    real deq = feq_dev(o, q, s.rho, s.drho, s.ueq);
-    if (o->mhd) deq += phi_mhd(o, q, s.B);
-    drel[q] = dl[q] + (deq - dl[q]) / s.tau + s.F[q];
   }
 
   /* propagation with halfway bounce-back and momentum exchange */
@@ -528,8 +542,7 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
       continue;
     }
     const int qb = o->opp[q];
-    /* moving wall: the returning population gains 6 w rho (e_qb . u_w) / c^2 */
-    real ladd = 6.0 * o->w[q] * s.rho * edot(o, qb, o->uw[grp]) / c2;
+    real ladd = moving_wall_term(o, q, s.rho, o->uw[grp]);
     o->dn[(long)qb * N + idx] = drel[q] + ladd;
     /* Eq. (25): outgoing f_bar = f_rel(x_f, t), incoming f_bar = f(x_f, t + dt) */
     real fout = drel[q] + o->w[q] * o->rho0;
@@ -645,7 +658,7 @@ int orc_get_macro(const orc* o, double* rho, double* v, double* B) {
     load_node(o, i, dl);
     node_B(o, i, Bn);
     node_t s;
-    node_setup(o, dl, i, Bn, &s);
+    node_setup(o, dl, i, Bn, NULL, &s);
     rho[i] = RE(s.rho);
     for (int k = 0; k < o->D; ++k) v[(long)k * o->N + i] = RE(s.v[k]);
     if (B)
@@ -681,7 +694,7 @@ int orc_stress(const orc* o, double* sigma, double* strain) {
       load_node(o, i, dl);
       node_B(o, i, Bn);
       node_t s;
-      node_setup(o, dl, i, Bn, &s);
+      node_setup(o, dl, i, Bn, NULL, &s);
       node_stress(o, &s, sig, S);
     }
     for (int m = 0; m < nc; ++m) {
@@ -756,7 +769,7 @@ static void stress_integral(const orc* o, real* F) {
               load_node(o, ids[l], dl);
               node_B(o, ids[l], Bn);
               node_t s;
-              node_setup(o, dl, ids[l], Bn, &s);
+              node_setup(o, dl, ids[l], Bn, NULL, &s);
               memset(sig, 0, sizeof(sig));
               node_stress(o, &s, sig, S);
               for (int i = 0; i < 3; ++i)
@@ -807,3 +820,144 @@ int orc_force_balance(const orc* o, double* out) {
   out[23] = (double)o->step;
   return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Reverse-mode gradient of a wall-force objective (complex-step build only)
+ * ---------------------------------------------------------------------------
+ * J = component `axis` of the raw momentum-exchange force (Eq. 25) on the
+ * links of wall group `group` during the last of T steps.  The map from the
+ * state at step n to the state at step n + 1 is relaxation (node-local) then
+ * propagation with bounce-back (a permutation of the relaxed values plus the
+ * moving-wall term).  Its transpose is applied backwards in time:
+ *   - propagation: the cotangent of a relaxed value is the cotangent of the
+ *     slot it was written to (and the same for the moving-wall term added to a
+ *     bounce-back slot);
+ *   - relaxation: the node's Jacobian with respect to its Q distributions, its
+ *     body force and (through the moving-wall term) the wall velocity, each
+ *     column taken by a complex step of node_relax itself (exact to rounding,
+ *     no hand-derived formula), multiplied by the cotangents.
+ * All T pre-step states are kept (no checkpointing).  MHD is not supported. */
+#ifdef ORC_COMPLEX
+int orc_adjoint(orc* o, int T, int group, int axis, double* J, double* grad_a, double* grad_uw) {
+  if (T < 1 || o->mhd || group < 0 || group >= o->G || axis < 0 || axis >= o->D) return -1;
+  const int Q = o->Q, D = o->D, G = o->G;
+  const long N = o->N;
+  const long QN = (long)Q * N;
+  const double c = o->c, dt = o->dt;
+  const double vol = o->lat == 0 ? o->dx * o->dx : o->dx * o->dx * o->dx;
+  const double h = 1e-30; /* complex step */
+  double* states = (double*)malloc(sizeof(double) * QN * T);
+  double* lam = (double*)calloc(QN, sizeof(double));
+  double* lamn = (double*)calloc(QN, sizeof(double));
+  const long rows = (long)o->ny * o->nz;
+  double* uwpart = (double*)calloc((size_t)rows * G * 3, sizeof(double));
+  if (!states || !lam || !lamn || !uwpart) {
+    free(states);
+    free(lam);
+    free(lamn);
+    free(uwpart);
+    return -2;
+  }
+  /* forward, keeping the state before each step */
+  for (int n = 0; n < T; ++n) {
+    for (long i = 0; i < QN; ++i) states[(long)n * QN + i] = RE(o->d[i]);
+    orc_step(o, 1);
+  }
+  *J = RE(o->wf[group][0][axis]);
+  memset(grad_a, 0, sizeof(double) * 3 * N);
+  /* backward */
+  for (int n = T - 1; n >= 0; --n) {
+    const double* sn = states + (long)n * QN;
+    memset(lamn, 0, sizeof(double) * QN);
+#pragma omp parallel for schedule(static)
+    for (long r = 0; r < rows; ++r) {
+      const int y = (int)(r % o->ny), z = (int)(r / o->ny);
+      double* pu = uwpart + r * G * 3;
+      for (int x = 0; x < o->nx; ++x) {
+        const long idx = ((long)z * o->ny + y) * o->nx + x;
+        if (o->solid[idx]) continue;
+        /* cotangents of the relaxed values (muR) and of the moving-wall terms (muL) */
+        double muR[19], muL[19];
+        int wall[19], grp[19];
+        for (int q = 0; q < Q; ++q) {
+          long t;
+          int g;
+          wall[q] = link_target(o, x, y, z, o->e[q], &t, &g);
+          grp[q] = wall[q] ? g : -1;
+          if (!wall[q]) {
+            muR[q] = lam[(long)q * N + t];
+            muL[q] = 0;
+          } else {
+            muR[q] = muL[q] = lam[(long)o->opp[q] * N + idx];
+          }
+        }
+        if (n == T - 1) {
+          /* J = sum over the group's links of (dx^D/dt)(e_q f_out - e_opp f_in)_axis,
+           * f_out = drel + w rho0, f_in = f_out + moving-wall term */
+          for (int q = 0; q < Q; ++q)
+            if (wall[q] && grp[q] == group) {
+              const double ek = c * o->e[q][axis];
+              muR[q] += 2.0 * vol / dt * ek;
+              muL[q] += vol / dt * ek;
+            }
+        }
+        real dl[19], drel[19];
+        node_t s;
+        for (int q = 0; q < Q; ++q) dl[q] = sn[(long)q * N + idx];
+        /* distributions */
+        for (int p = 0; p < Q; ++p) {
+          const real keep = dl[p];
+          dl[p] = keep + MK(0.0, h);
+          node_relax(o, dl, idx, NULL, NULL, &s, drel);
+          double acc = 0;
+          for (int q = 0; q < Q; ++q) {
+            acc += muR[q] * (IM(drel[q]) / h);
+            if (wall[q]) {
+              real uw[3] = {RE(o->uw[grp[q]][0]), RE(o->uw[grp[q]][1]), RE(o->uw[grp[q]][2])};
+              acc += muL[q] * (IM(moving_wall_term(o, q, s.rho, uw)) / h);
+            }
+          }
+          lamn[(long)p * N + idx] = acc;
+          dl[p] = keep;
+        }
+        /* body force of this node */
+        for (int k = 0; k < D; ++k) {
+          real an[3] = {0, 0, 0};
+          for (int m = 0; m < D; ++m) an[m] = RE(body_force(o, idx, m));
+          an[k] += MK(0.0, h);
+          node_relax(o, dl, idx, NULL, an, &s, drel);
+          double acc = 0;
+          for (int q = 0; q < Q; ++q) acc += muR[q] * (IM(drel[q]) / h);
+          grad_a[(long)k * N + idx] += acc;
+        }
+        /* wall velocities (through the moving-wall term only) */
+        node_relax(o, dl, idx, NULL, NULL, &s, drel);
+        for (int q = 0; q < Q; ++q) {
+          if (!wall[q]) continue;
+          for (int k = 0; k < D; ++k) {
+            real uw[3] = {RE(o->uw[grp[q]][0]), RE(o->uw[grp[q]][1]), RE(o->uw[grp[q]][2])};
+            uw[k] += MK(0.0, h);
+            pu[grp[q] * 3 + k] += muL[q] * (IM(moving_wall_term(o, q, s.rho, uw)) / h);
+          }
+        }
+      }
+    }
+    double* t = lam;
+    lam = lamn;
+    lamn = t;
+  }
+  memset(grad_uw, 0, sizeof(double) * G * 3);
+  for (long r = 0; r < rows; ++r)
+    for (int k = 0; k < G * 3; ++k) grad_uw[k] += uwpart[r * G * 3 + k];
+  free(states);
+  free(lam);
+  free(lamn);
+  free(uwpart);
+  return 0;
+}
+#else
+int orc_adjoint(orc* o, int T, int group, int axis, double* J, double* grad_a, double* grad_uw) {
+  (void)o, (void)T, (void)group, (void)axis, (void)J, (void)grad_a, (void)grad_uw;
+  return -3; /* needs the complex-step build */
+}
+#endif

@@ -69,6 +69,14 @@ int orc_wall_force(const orc* o, double* out, double* out_im, int G);
 int orc_force_balance(const orc* o, double* out);
 long orc_link_count(const orc* o, int group);
 
+/* Reverse-mode gradient (complex-step build only; -3 from the double build).
+ * From the current state, runs T steps and returns J = component `axis` of
+ * the raw wall force on group `group` during the last step, grad_a [3][N]
+ * = dJ/da per node (physical units; components beyond D are 0) and
+ * grad_uw [G][3] = dJ/du_w per wall group.  Leaves the state at step T.
+ * Parameters must carry no imaginary parts. */
+int orc_adjoint(orc* o, int T, int group, int axis, double* J, double* grad_a, double* grad_uw);
+
 #ifdef __cplusplus
 }
 #endif

@@ -100,3 +100,32 @@ def hartmann(n, nu, eta, mu, rho, a_x, B0):
     u = U * (1 - np.cosh(Ha * y / half) / np.cosh(Ha))
     b = rho * a_x * half * mu / B0 * (np.sinh(Ha * y / half) / np.sinh(Ha) - y / half)
     return u, b, Ha
+
+
+def channel_bottom_force_recurrence(ny, tau, a_rows, steps, uw=0.0):
+    """x-force per column on the bottom wall during the last step of the
+    channel of `channel_recurrence`, with a body force that may vary by row
+    (a_rows: scalar or [ny]).  Momentum exchange at a static halfway wall
+    (Eq. 25): each link leaving row 0 downwards carries e_x (2 f_rel); the
+    rest-state parts of the two diagonal links cancel, so the force is
+    2 m*_-(0).  The map (a_rows, u_w) -> force is linear."""
+    a = np.broadcast_to(np.asarray(a_rows, dtype=float), (ny,)).copy()
+    mp = np.zeros(ny)
+    m0 = np.zeros(ny)
+    mm = np.zeros(ny)
+    C = 1.0 - 1.0 / (2.0 * tau)
+    F = 0.0
+    for _ in range(steps):
+        v = mp + m0 + mm + 0.5 * a
+        sp = (1 - 1 / tau) * mp + v / (6 * tau) + C * a / 6
+        s0 = (1 - 1 / tau) * m0 + 2 * v / (3 * tau) + 2 * C * a / 3
+        sm = (1 - 1 / tau) * mm + v / (6 * tau) + C * a / 6
+        F = 2.0 * sm[0]
+        mp2 = np.empty(ny)
+        mm2 = np.empty(ny)
+        mp2[1:] = sp[:-1]
+        mm2[:-1] = sm[1:]
+        mp2[0] = -sm[0]
+        mm2[-1] = -sp[-1] + uw / 3.0
+        mp, m0, mm = mp2, s0, mm2
+    return F
