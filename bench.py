@@ -112,6 +112,57 @@ def timed_run(lbm, torch, w, steps, warmup, storage=None):
     }
 
 
+def adjoint_run(lbm, torch, W, adj_prec, repeats=3):
+    """Differentiable duct with a sphere (128x64x64, r = 8, tau 0.55, per-node
+    Guo force field, 400 steps, checkpoints every 40, FP32): recorded forward
+    and full checkpointed backward (segment recompute + adjoint steps),
+    timed with events around the calls; best of `repeats`."""
+    w = W.duct_sphere()
+    T, K = w.steps, 40
+    a0 = W.force_field(w.nx, w.ny, w.nz, base=w.body_force, amp=0.3, seed=16)
+    af = torch.from_numpy(a0.astype(np.float32)).cuda()
+    ga = torch.empty_like(af)
+    lat = lbm.from_workload(w)
+    lat.set_adjoint_precision(adj_prec)
+    stream = torch.cuda.current_stream()
+    lat.set_stream(stream.cuda_stream)
+    lat.set_body_force_field(af.data_ptr())
+    u0 = W.initial_velocity(w)
+    best_f = best_b = None
+    for _ in range(repeats):
+        lat.init_equilibrium(u0)
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        J = lat.adjoint_forward(T, K, 4, 0)
+        e1.record(stream)
+        gu = lat.adjoint_backward(1.0, ga.data_ptr(), False)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        tf = e0.elapsed_time(e1) * 1e-3
+        tb = e1.elapsed_time(e2) * 1e-3
+        best_f = tf if best_f is None else min(best_f, tf)
+        best_b = tb if best_b is None else min(best_b, tb)
+    lat.close()
+    lu = w.N * T
+    # reverse bytes per node and step: recompute (2 Q 4 + 4 x 4 rho/U written + 12 field)
+    # + adjoint (2 Q s_adj + 4 x 4 read + 12 field + 2 x 12 gradient read-modify-write)
+    s_adj = 8 if adj_prec == W.F64 else 4
+    rbytes = (2 * 19 * 4 + 16 + 12) + (2 * 19 * s_adj + 16 + 12 + 24)
+    return {
+        "workload": "duct_sphere_d3q19_128x64x64_r8_T400_ckpt40_f32",
+        "adjoint_state": "f64" if adj_prec == W.F64 else "f32",
+        "J": J,
+        "dJ_duw_x": float(gu[1, 0]),
+        "forward_ms": round(best_f * 1e3, 3),
+        "backward_ms": round(best_b * 1e3, 3),
+        "forward_mlups": round(lu / best_f / 1e6, 1),
+        "adjoint_mlups": round(lu / best_b / 1e6, 1),
+        "backward_bytes_per_node_step": rbytes,
+        "backward_achieved_gbs": round(rbytes * lu / best_b / 1e9, 1),
+    }
+
+
 def cpu_baseline(W, budget_s):
     import oracle
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -213,6 +264,10 @@ def main():
                 v[k] = round(v[k], 4 if k == "frac" else 2)
             v["launch_us"] = {k: round(x, 2) for k, x in v["launch_us"].items()}
         out["variants"] = variants
+    if not args.no_variants:
+        print("bench: adjoint (differentiable duct with sphere)", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_run(lbm, torch, W, W.F64)
+        out["adjoint_f32_state"] = adjoint_run(lbm, torch, W, W.F32)
     if not args.no_cpu:
         print("bench: CPU reference baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)

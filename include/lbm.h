@@ -186,6 +186,42 @@ long lbm_link_count(lbm_ctx* ctx, int group);
 /* Steps taken since the last initialisation. */
 long lbm_steps_taken(lbm_ctx* ctx);
 
+/* ---- differentiation (the discrete adjoint of the step; the paper does not
+ * differentiate its method) ---- */
+
+/* Record a differentiable run: from the current state, advance T >= 1 steps
+ * exactly as lbm_step(T) does, keeping a device copy of the state every
+ * ckpt_every >= 1 steps (ceil(T / ckpt_every) copies of Q N values, owned by
+ * the context), and return in *J the objective: component `axis` (0 = x,
+ * 1 = y, 2 = z; < D) of the raw Eq. (25) force on wall group `group` during
+ * the last step, i.e. lbm_wall_force variant 0.  Needs LBM_F32 or LBM_F64
+ * storage, no MHD and no Smagorinsky closure (LBM_EINVAL otherwise).  The run
+ * stays recorded for lbm_adjoint_backward until the next lbm_step,
+ * lbm_adjoint_forward, state upload or change of wall velocities, body force
+ * or closure; the body-force field's device memory must not change meanwhile. */
+int lbm_adjoint_forward(lbm_ctx* ctx, int T, int ckpt_every, int group, int axis, double* J);
+
+/* Gradient of gJ * J for the recorded run, by the adjoint of every step in
+ * reverse order: each checkpoint segment is first recomputed forward (also
+ * recording density and velocity per node and step), then its adjoint steps
+ * run backwards.  grad_a_dev: device buffer [3][nz][ny][nx], float
+ * (grad_f64 = 0) or double (grad_f64 = 1), overwritten with gJ dJ/da per
+ * node in physical units (the z plane is 0 in 2D), or NULL.  grad_uw: host
+ * buffer [G][3], G = lbm_num_groups, overwritten with gJ dJ/du_w per wall
+ * group (physical units), or NULL.  Work buffers (two state copies and
+ * min(ckpt_every, T) x 4 N values) are allocated on first use and kept.  The
+ * context's state is not changed and the run stays recorded.  LBM_ESTATE
+ * without a recorded run.  The recompute runs in the storage precision, the
+ * adjoint steps in the adjoint precision (lbm_set_adjoint_precision). */
+int lbm_adjoint_backward(lbm_ctx* ctx, double gJ, void* grad_a_dev, int grad_f64, double* grad_uw);
+
+/* Precision of the adjoint state and its arithmetic: LBM_F64 (the default;
+ * the only choice for LBM_F64 storage) or LBM_F32 (LBM_F32 storage only:
+ * half the adjoint's memory traffic, but FP32 rounding of the adjoint state
+ * loses the small differences between nearly equal sensitivities, e.g. the
+ * gradient with respect to the velocity of a distant wall).  Any time. */
+int lbm_set_adjoint_precision(lbm_ctx* ctx, int precision);
+
 /* Per-launch timing of lbm_step with HIP events recorded on the context's
  * stream between consecutive launches (on = 1; adds one event per launch).
  * lbm_step_timings fills out[6] for the most recent timed call, in seconds:

@@ -1,0 +1,294 @@
+// Adjoint (reverse-mode) step kernels for gfx950: the transpose of one forward
+// step (relaxation of Eq. 2 with the equilibrium of Eq. 1 and the force term
+// of Section 2 / Eq. 3, then A-A propagation with halfway bounce-back and the
+// moving-wall term), used to differentiate the Eq. (25) wall force with
+// respect to the per-node body force and the wall velocities.  The paper does
+// not differentiate its method; this is the discrete adjoint of the forward
+// kernels' arithmetic.
+//
+// In-place A-A storage of the adjoint state.  A forward step reads a node's
+// populations from a set of slots and writes its relaxed values into the same
+// set of slots (the A-A property, bounce-back links included).  The
+// transposed step therefore reads the cotangents of the relaxed values from
+// the slots the forward step wrote and writes the cotangents of the pre-step
+// populations into the slots the forward step read, one thread per node and
+// race-free in place, with the parity of the forward step it reverses.
+//
+// Per node, with nu = 1/tau, u^eq = U + lEq A, u^F = kF U + lF A and the
+// cotangents mu_q of the relaxed values, everything reduces to the weighted
+// moments m0 = sum w mu, m1 = sum w mu e, m2 = sum w mu e e:
+//   rho-cotangent  M_rho = nu [m0 + 3 m1.ue + 9/2 ue.m2.ue - 3/2 ue.ue m0]
+//                        + C [3 m1.A - 3 (uF.A) m0 + 9 uF.m2.A]
+//                        + sum over wall links of mu_q (-6 w_q e_q.u_w)
+//   G_ue = nu rho (3 m1 + 9 m2 ue - 3 ue m0),  G_uF = C rho (9 m2 A - 3 A m0)
+//   U-cotangent    M_U = G_ue + kF G_uF
+//   A-cotangent    g_A = lEq G_ue + lF G_uF + C rho (3 m1 - 3 uF m0 + 9 m2 uF)
+//   lambda_p = (1 - nu) mu_p + M_rho + M_U.(e_p - U) / rho
+// and the wall velocity of a link's group gets mu_q (-6 w_q rho e_q).  rho
+// and U of the forward state come from the recompute pass (4 values per node
+// instead of Q), in the forward storage precision PS; the adjoint state and
+// its arithmetic use precision PL.  PL = F64 with an FP32 forward keeps the
+// small anisotropic parts of lambda (differences of nearly equal values, e.g.
+// the shear sensitivity at a distant wall) that FP32 storage of lambda rounds
+// away.
+#include "device.hpp"
+
+namespace lbm {
+
+template <class L, int PS, int PL, int PAR, bool SEED, bool BND, class AD>
+__device__ __forceinline__ void adj_node(const AdjArgs& a, uint32_t n, const AD& Al, const uint4& rec,
+                                         typename Stor<PL>::T (&pu)[MAXBG][3], uint32_t bgrp) {
+  using S = Stor<PL>;
+  using T = typename S::T;
+  using E = typename S::E;
+  const Geom& g = a.geo;
+  const Phys& p = a.p;
+  const uint32_t mask = rec.x;
+  E* lam = (E*)a.lam;
+
+  // cotangents of the relaxed values: read where the forward step wrote them
+  T mu[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    if (SEED) {
+      // objective: sum over the links of one group of e_axis (2 d_rel + ladd);
+      // mu holds the cotangent of d_rel here, that of ladd is mu / 2
+      T s = T(0);
+      if (BND && q > 0 && ((mask >> q) & 1u) && (int)nibble(rec, q) == a.seed_group) {
+        const int ek = a.seed_axis == 0 ? L::ex(q) : (a.seed_axis == 1 ? L::ey(q) : L::ez(q));
+        s = T(2 * ek);
+      }
+      mu[q] = s;
+    } else {
+      const int qb = opp(q);
+      const E* ptr;
+      if (PAR == 0) {
+        ptr = Al.template ptr<L>(lam, qb, -1);
+      } else if (BND) {
+        ptr = pick((mask >> q) & 1u, Al.template ptr<L>(lam, qb, -1), Al.template ptr<L>(lam, q, q));
+      } else {
+        ptr = Al.template ptr<L>(lam, q, q);
+      }
+      mu[q] = S::ld(ptr);
+    }
+  }
+
+  // forward state of this node and its body force
+  using M = typename Stor<PS>::T;
+  const M* mac = (const M*)a.mac;
+  const T rho = (T)mac[n];
+  const T U[3] = {(T)mac[g.N + n], (T)mac[2 * (uint64_t)g.N + n], (T)mac[3 * (uint64_t)g.N + n]};
+  T A[3];
+  if (a.afield) {
+    const T sc = (T)p.afield_scale;
+    A[0] = (T)a.afield[n] * sc;
+    A[1] = (T)a.afield[g.N + n] * sc;
+    A[2] = L::D == 3 ? (T)a.afield[2 * (uint64_t)g.N + n] * sc : T(0);
+  } else {
+    A[0] = (T)p.A[0];
+    A[1] = (T)p.A[1];
+    A[2] = (T)p.A[2];
+  }
+  const T nu = (T)p.inv_tau0;
+  const T lEq = (T)p.lEq, kF = (T)p.kF;
+  const T lF = (T)(p.lF0 + p.lF1 * p.tau0);
+  const T C = (T)(1.0 - p.cG * 0.5 * p.inv_tau0);
+  T ue[3], uf[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    ue[k] = U[k] + lEq * A[k];
+    uf[k] = kF * U[k] + lF * A[k];
+  }
+
+  // weighted moments of mu
+  T m0 = T(0), m1[3] = {T(0), T(0), T(0)};
+  T mxx = T(0), myy = T(0), mzz = T(0), mxy = T(0), mxz = T(0), myz = T(0);
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const T wm = (T)L::w(q) * mu[q];
+    const int ex = L::ex(q), ey = L::ey(q), ez = L::ez(q);
+    m0 += wm;
+    if (ex) m1[0] += ex > 0 ? wm : -wm;
+    if (ey) m1[1] += ey > 0 ? wm : -wm;
+    if (ez) m1[2] += ez > 0 ? wm : -wm;
+    if (ex) mxx += wm;
+    if (ey) myy += wm;
+    if (ez) mzz += wm;
+    if (ex * ey) mxy += ex * ey > 0 ? wm : -wm;
+    if (ex * ez) mxz += ex * ez > 0 ? wm : -wm;
+    if (ey * ez) myz += ey * ez > 0 ? wm : -wm;
+  }
+  auto m2v = [&](const T (&v)[3], T (&r)[3]) __attribute__((always_inline)) {
+    r[0] = mxx * v[0] + mxy * v[1] + mxz * v[2];
+    r[1] = mxy * v[0] + myy * v[1] + myz * v[2];
+    r[2] = mxz * v[0] + myz * v[1] + mzz * v[2];
+  };
+  T m2ue[3], m2A[3], m2uf[3];
+  m2v(ue, m2ue);
+  m2v(A, m2A);
+  m2v(uf, m2uf);
+  const T m1ue = m1[0] * ue[0] + m1[1] * ue[1] + m1[2] * ue[2];
+  const T m1A = m1[0] * A[0] + m1[1] * A[1] + m1[2] * A[2];
+  const T uem2ue = ue[0] * m2ue[0] + ue[1] * m2ue[1] + ue[2] * m2ue[2];
+  const T ufm2A = uf[0] * m2A[0] + uf[1] * m2A[1] + uf[2] * m2A[2];
+  const T ueue = ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2];
+  const T ufA = uf[0] * A[0] + uf[1] * A[1] + uf[2] * A[2];
+
+  T Mrho = nu * (m0 + T(3) * m1ue + T(4.5) * uem2ue - T(1.5) * ueue * m0) +
+           C * (T(3) * m1A - T(3) * ufA * m0 + T(9) * ufm2A);
+  T MU[3], gA[3];
+  const T nr = nu * rho, cr = C * rho;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T Gue = nr * (T(3) * m1[k] + T(9) * m2ue[k] - T(3) * ue[k] * m0);
+    const T Guf = cr * (T(9) * m2A[k] - T(3) * A[k] * m0);
+    MU[k] = Gue + kF * Guf;
+    gA[k] = lEq * Gue + lF * Guf + cr * (T(3) * m1[k] - T(3) * uf[k] * m0 + T(9) * m2uf[k]);
+  }
+
+  // moving-wall terms of the bounce-back links: -6 w_q rho (e_q . u_w)
+  if (BND) {
+#pragma unroll
+    for (int q = 1; q < L::Q; ++q) {
+      if ((mask >> q) & 1u) {
+        const uint32_t gr = nibble(rec, q);
+        const T ux = (T)a.uw[3 * gr], uy = (T)a.uw[3 * gr + 1], uz = (T)a.uw[3 * gr + 2];
+        const T muL = SEED ? T(0.5) * mu[q] : mu[q];
+        const T c6 = T(-6) * (T)L::w(q) * muL;
+        Mrho += c6 * edot<L>(q, ux, uy, uz);
+        const T cr6 = c6 * rho;
+#pragma unroll
+        for (int s = 0; s < MAXBG; ++s) {
+          if (((bgrp >> (4 * s)) & 15u) == gr) {
+            pu[s][0] += cr6 * (T)L::ex(q);
+            pu[s][1] += cr6 * (T)L::ey(q);
+            pu[s][2] += cr6 * (T)L::ez(q);
+          }
+        }
+      }
+    }
+  }
+
+  // cotangents of the pre-step populations: written where the forward step read them
+  const T irho = T(1) / rho;
+  const T MUU = (MU[0] * U[0] + MU[1] * U[1] + MU[2] * U[2]) * irho;
+  const T keep = T(1) - nu;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const int qb = opp(q);
+    const T lq = keep * mu[q] + Mrho + edot<L>(q, MU[0], MU[1], MU[2]) * irho - MUU;
+    E* ptr;
+    if (PAR == 0) {
+      ptr = Al.template ptr<L>(lam, q, -1);
+    } else if (BND) {
+      ptr = pick((mask >> qb) & 1u, Al.template ptr<L>(lam, q, -1), Al.template ptr<L>(lam, qb, qb));
+    } else {
+      ptr = Al.template ptr<L>(lam, qb, qb);
+    }
+    S::st(ptr, lq);
+  }
+
+  // body-force gradient, accumulated over the steps
+  if (a.grad_a) {
+    const double sc = a.ga_scale;
+    if (a.grad_f64) {
+      double* ga = (double*)a.grad_a;
+#pragma unroll
+      for (int k = 0; k < L::D; ++k) ga[(uint64_t)k * g.N + n] += sc * (double)gA[k];
+    } else {
+      float* ga = (float*)a.grad_a;
+#pragma unroll
+      for (int k = 0; k < L::D; ++k) ga[(uint64_t)k * g.N + n] += (float)(sc * (double)gA[k]);
+    }
+  }
+}
+
+template <class L, int PS, int PL, int PAR, bool SEED, bool RU>
+__global__ __launch_bounds__(NTHREADS) void k_adj(const AdjArgs a) {
+  using T = typename Stor<PL>::T;
+  const Geom& g = a.geo;
+  const uint32_t n = blockIdx.x * NTHREADS + threadIdx.x;
+  const uint32_t bgrp = a.blkgrp[blockIdx.x];
+  T pu[MAXBG][3];
+#pragma unroll
+  for (int s = 0; s < MAXBG; ++s) pu[s][0] = pu[s][1] = pu[s][2] = T(0);
+  if (n < g.N) {
+    uint32_t x, y, z, r;
+    coords(g, n, x, y, z, r);
+    if (RU) {
+      r = __builtin_amdgcn_readfirstlane(r);
+      y = __builtin_amdgcn_readfirstlane(y);
+      z = __builtin_amdgcn_readfirstlane(z);
+    }
+    const int rr = a.rowrec[r];
+    const uint4 rec = rr < 0 ? make_uint4(0u, 0u, 0u, 0u) : a.rec[rr + x];
+    if (!(rec.x >> 31)) {
+      if (RU) {
+        const AddrR Al = addr_r(g, x, y, z, L::Q);
+        if (rr < 0)
+          adj_node<L, PS, PL, PAR, SEED, false>(a, n, Al, rec, pu, bgrp);
+        else
+          adj_node<L, PS, PL, PAR, SEED, true>(a, n, Al, rec, pu, bgrp);
+      } else {
+        const AddrG Al = addr_g(g, x, y, z, r, L::Q);
+        if (rr < 0)
+          adj_node<L, PS, PL, PAR, SEED, false>(a, n, Al, rec, pu, bgrp);
+        else
+          adj_node<L, PS, PL, PAR, SEED, true>(a, n, Al, rec, pu, bgrp);
+      }
+    }
+  }
+  // wall-velocity cotangents of this tile, in the wall slots of the tile's
+  // partial-sum record (block-uniform condition: the tile has wall links)
+  if (bgrp >> 28) {
+    double v[MAXBG * NWALL];
+#pragma unroll
+    for (int s = 0; s < MAXBG; ++s) {
+      v[s * NWALL + 0] = (double)pu[s][0];
+      v[s * NWALL + 1] = (double)pu[s][1];
+      v[s * NWALL + 2] = (double)pu[s][2];
+      v[s * NWALL + 3] = 0.0;
+    }
+    tile_sum_store<MAXBG * NWALL, true>(v, a.part + (uint64_t)blockIdx.x * NPART + NBAL);
+  }
+}
+
+template <class L, int PS, int PL, bool RU>
+static void launch_adj_ru(const AdjArgs& a, int parity, bool seed, uint32_t nb, hipStream_t st) {
+  if (parity == 0) {
+    if (seed)
+      k_adj<L, PS, PL, 0, true, RU><<<nb, NTHREADS, 0, st>>>(a);
+    else
+      k_adj<L, PS, PL, 0, false, RU><<<nb, NTHREADS, 0, st>>>(a);
+  } else {
+    if (seed)
+      k_adj<L, PS, PL, 1, true, RU><<<nb, NTHREADS, 0, st>>>(a);
+    else
+      k_adj<L, PS, PL, 1, false, RU><<<nb, NTHREADS, 0, st>>>(a);
+  }
+}
+
+template <class L, int PS, int PL>
+static hipError_t launch_adj_t(const AdjArgs& a, int parity, bool seed, hipStream_t st) {
+  const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
+  if (a.geo.nx % 64 == 0)
+    launch_adj_ru<L, PS, PL, true>(a, parity, seed, nb, st);
+  else
+    launch_adj_ru<L, PS, PL, false>(a, parity, seed, nb, st);
+  return hipGetLastError();
+}
+
+template <class L>
+static hipError_t launch_adj_l(int prec, int adj_prec, const AdjArgs& a, int parity, bool seed, hipStream_t st) {
+  if (prec == S_F64 && adj_prec == S_F64) return launch_adj_t<L, S_F64, S_F64>(a, parity, seed, st);
+  if (prec == S_F32 && adj_prec == S_F64) return launch_adj_t<L, S_F32, S_F64>(a, parity, seed, st);
+  if (prec == S_F32 && adj_prec == S_F32) return launch_adj_t<L, S_F32, S_F32>(a, parity, seed, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj(int lattice, int prec, int adj_prec, const AdjArgs& a, int parity, bool seed, hipStream_t st) {
+  if (lattice == 0) return launch_adj_l<D2Q9>(prec, adj_prec, a, parity, seed, st);
+  return launch_adj_l<D3Q19>(prec, adj_prec, a, parity, seed, st);
+}
+
+}  // namespace lbm

@@ -1,0 +1,339 @@
+// Device-side building blocks shared by the forward step kernels and the
+// adjoint kernels: storage formats, row-blocked A-A addressing with halfway
+// bounce-back, and per-tile FP64 reductions.
+//
+// Distributions live in one in-place array per lattice, blocked by x-row:
+// element (q, row, x) at (row Q + q) nx + x.  All quantities are
+// dimensionless: velocities in units of c = dx/dt, body force as a dt / c.
+#pragma once
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// storage formats
+// ---------------------------------------------------------------------------
+template <int P>
+struct Stor;
+template <>
+struct Stor<S_F64> {
+  using E = double;
+  using T = double;
+  static __device__ __forceinline__ T ld(const E* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ void st(E* p, T v) { __builtin_nontemporal_store(v, p); }
+};
+template <>
+struct Stor<S_F32> {
+  using E = float;
+  using T = float;
+  static __device__ __forceinline__ T ld(const E* p) { return __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ void st(E* p, T v) { __builtin_nontemporal_store(v, p); }
+};
+template <>
+struct Stor<S_F16> {
+  using E = _Float16;
+  using T = float;
+  static __device__ __forceinline__ T ld(const E* p) { return (float)__builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ void st(E* p, T v) { __builtin_nontemporal_store((_Float16)v, p); }
+};
+template <>
+struct Stor<S_BF16> {
+  using E = uint16_t;
+  using T = float;
+  static __device__ __forceinline__ T ld(const E* p) {
+    return __uint_as_float(uint32_t(__builtin_nontemporal_load(p)) << 16);
+  }
+  static __device__ __forceinline__ void st(E* p, T v) {
+    uint32_t u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    __builtin_nontemporal_store(uint16_t(u >> 16), p);
+  }
+};
+
+template <class T>
+__device__ __forceinline__ T rcp(T x) {
+  return T(1) / x;
+}
+template <>
+__device__ __forceinline__ float rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+
+// ---------------------------------------------------------------------------
+// index helpers
+// ---------------------------------------------------------------------------
+// Element offsets to the six axis neighbours (periodic wrap) in a row-blocked
+// array whose rows hold P planes (row stride rs = P nx).
+struct Offs {
+  int xp, xm;
+  int64_t yp, ym, zp, zm;
+};
+
+__device__ __forceinline__ void coords(const Geom& g, uint32_t n, uint32_t& x, uint32_t& y, uint32_t& z, uint32_t& r) {
+  r = g.nx == 1 ? n : (uint32_t)__umul64hi((uint64_t)n, g.mnx);
+  x = n - r * g.nx;
+  z = g.ny == 1 ? r : (uint32_t)__umul64hi((uint64_t)r, g.mny);
+  y = r - z * g.ny;
+}
+
+__device__ __forceinline__ Offs offsets(const Geom& g, uint32_t x, uint32_t y, uint32_t z, uint64_t rs) {
+  Offs o;
+  const int nx = (int)g.nx;
+  const int64_t ry = (int64_t)rs, rz = (int64_t)rs * g.ny;
+  o.xp = (x + 1 == g.nx) ? 1 - nx : 1;
+  o.xm = (x == 0) ? nx - 1 : -1;
+  o.yp = (y + 1 == g.ny) ? (1 - (int64_t)g.ny) * ry : ry;
+  o.ym = (y == 0) ? ((int64_t)g.ny - 1) * ry : -ry;
+  o.zp = (z + 1 == g.nz) ? (1 - (int64_t)g.nz) * rz : rz;
+  o.zm = (z == 0) ? ((int64_t)g.nz - 1) * rz : -rz;
+  return o;
+}
+
+// Offset from a node to its neighbour along e_q.
+template <class L>
+__device__ __forceinline__ int64_t off_of(int q, const Offs& o) {
+  int64_t s = 0;
+  if (L::ex(q) > 0) s += o.xp;
+  if (L::ex(q) < 0) s += o.xm;
+  if (L::ey(q) > 0) s += o.yp;
+  if (L::ey(q) < 0) s += o.ym;
+  if (L::ez(q) > 0) s += o.zp;
+  if (L::ez(q) < 0) s += o.zm;
+  return s;
+}
+
+// Addressing of one node's slots in a row-blocked array with P planes:
+// ptr<L>(f, plane, q) points at `plane` of the neighbour x + e_q (q < 0: the
+// node itself).
+//
+// Generic form: a per-lane element index of the node plus neighbour offsets.
+struct AddrG {
+  uint64_t b;
+  Offs o;
+  uint32_t nx;
+  template <class L, class E>
+  __device__ __forceinline__ E* ptr(E* f, int plane, int q) const {
+    return f + ((q < 0 ? b : b + off_of<L>(q, o)) + (uint32_t)plane * nx);
+  }
+};
+
+// Row-uniform form, used when nx is a multiple of 64: a wavefront then never
+// leaves its x-row, so y, z and every neighbour-row base are wave-uniform
+// (scalar registers) and each lane only adds its 32-bit x byte offset
+// (scalar base + vector offset addressing).  The row bases are recomputed in
+// ptr() rather than kept in an array, so that the compiler never turns a
+// per-lane choice between two slots into a dynamic index of private memory.
+struct AddrR {
+  uint32_t y, z, ny, nz;
+  uint32_t x, xm, xp;  // x, x - 1, x + 1 (periodic), per lane
+  uint32_t nx;
+  uint64_t rs;         // row stride, planes * nx
+  template <class L, class E>
+  __device__ __forceinline__ E* ptr(E* f, int plane, int q) const {
+    const int dx = q < 0 ? 0 : L::ex(q), dy = q < 0 ? 0 : L::ey(q), dz = q < 0 ? 0 : L::ez(q);
+    const uint32_t yy = dy < 0 ? (y == 0 ? ny - 1 : y - 1) : (dy > 0 ? (y + 1 == ny ? 0 : y + 1) : y);
+    const uint32_t zz = dz < 0 ? (z == 0 ? nz - 1 : z - 1) : (dz > 0 ? (z + 1 == nz ? 0 : z + 1) : z);
+    E* base = f + (((uint64_t)zz * ny + yy) * rs + (uint32_t)plane * nx);  // wave-uniform
+    const uint32_t xs = dx < 0 ? xm : (dx > 0 ? xp : x);
+    return (E*)((char*)base + xs * (uint32_t)sizeof(E));  // 32-bit byte offset
+  }
+};
+
+__device__ __forceinline__ AddrG addr_g(const Geom& g, uint32_t x, uint32_t y, uint32_t z, uint32_t r, uint32_t P) {
+  AddrG a;
+  a.b = (uint64_t)r * (P * g.nx) + x;
+  a.o = offsets(g, x, y, z, (uint64_t)P * g.nx);
+  a.nx = g.nx;
+  return a;
+}
+
+// y, z must be wave-uniform.
+__device__ __forceinline__ AddrR addr_r(const Geom& g, uint32_t x, uint32_t y, uint32_t z, uint32_t P) {
+  AddrR a;
+  a.y = y;
+  a.z = z;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.x = x;
+  a.xm = x == 0 ? g.nx - 1 : x - 1;
+  a.xp = x + 1 == g.nx ? 0 : x + 1;
+  a.nx = g.nx;
+  a.rs = (uint64_t)P * g.nx;
+  return a;
+}
+
+// Per-lane choice between two addresses, written as mask arithmetic on the
+// address values so that it is not folded into an indexed access of the
+// address objects' fields.
+template <class E>
+__device__ __forceinline__ E* pick(bool c, E* a, E* b) {
+  const uint64_t m = 0ull - (uint64_t)c;
+  return (E*)(((uint64_t)a & m) | ((uint64_t)b & ~m));
+}
+
+template <class L, class T>
+__device__ __forceinline__ T edot(int q, T vx, T vy, T vz) {
+  T s = T(0);
+  if (L::ex(q) > 0) s += vx;
+  if (L::ex(q) < 0) s -= vx;
+  if (L::ey(q) > 0) s += vy;
+  if (L::ey(q) < 0) s -= vy;
+  if (L::ez(q) > 0) s += vz;
+  if (L::ez(q) < 0) s -= vz;
+  return s;
+}
+
+__device__ __forceinline__ uint32_t nibble(const uint4& r, int q) {
+  const uint32_t w = q < 8 ? r.y : (q < 16 ? r.z : r.w);
+  return (w >> (4 * (q & 7))) & 15u;
+}
+
+// ---------------------------------------------------------------------------
+// A-A reads and writes of one node's distributions
+// ---------------------------------------------------------------------------
+// Reading the state f_q(x, t):
+//   even parity (natural layout): slot q of x;
+//   odd parity: slot opp(q) of x - e_q, or, when the link from x along
+//   -e_q ends in a wall, slot q of x (where the bounce-back value was put).
+template <class L, int P, int PAR, bool BND, class AD>
+__device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask,
+                                       const Phys& p, typename Stor<P>::T (&d)[L::Q]) {
+  using S = Stor<P>;
+  using T = typename S::T;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const int qb = opp(q);
+    const typename S::E* ptr;
+    if (PAR == 0) {
+      ptr = A.template ptr<L>(f, q, -1);
+    } else {
+      ptr = A.template ptr<L>(f, qb, qb);
+    }
+    // a wall link: the value was put in the node's own slot q
+    if (PAR == 1 && BND) ptr = pick((mask >> qb) & 1u, A.template ptr<L>(f, q, -1), ptr);
+    T v = S::ld(ptr);
+    if (P == S_F16 || P == S_BF16) v *= (T)p.inv_scale[q];
+    d[q] = v;
+  }
+}
+
+// Writing the post-collision value v_q of node x (v_q already holds the
+// bounce-back value, including the moving-wall term, for wall links):
+//   even parity: slot opp(q) of x;
+//   odd parity: slot q of x + e_q, or slot opp(q) of x for a wall link.
+template <class L, int P, int PAR, bool BND, class AD>
+__device__ __forceinline__ void write_f(typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask, const Phys& p,
+                                        const typename Stor<P>::T (&v)[L::Q]) {
+  using S = Stor<P>;
+  using T = typename S::T;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const int qb = opp(q);
+    typename S::E* ptr;
+    if (PAR == 0) {
+      ptr = A.template ptr<L>(f, qb, -1);
+    } else {
+      ptr = A.template ptr<L>(f, q, q);
+    }
+    T s = v[q];
+    if (P == S_F16 || P == S_BF16) s *= (T)p.scale[q];
+    if (PAR == 1 && BND && ((mask >> q) & 1u))
+      S::st(A.template ptr<L>(f, qb, -1), s);  // wall link: back into the node's own slot
+    else
+      S::st(ptr, s);
+  }
+}
+
+// One direction of write_f.
+template <class L, int P, int PAR, bool BND, class AD>
+__device__ __forceinline__ void write_f1(typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask, const Phys& p,
+                                         int q, typename Stor<P>::T v) {
+  using S = Stor<P>;
+  using T = typename S::T;
+  const int qb = opp(q);
+  T s = v;
+  if (P == S_F16 || P == S_BF16) s *= (T)p.scale[q];
+  if (PAR == 0) {
+    S::st(A.template ptr<L>(f, qb, -1), s);
+  } else if (BND) {
+    // wall link: back into the node's own slot
+    S::st(pick((mask >> q) & 1u, A.template ptr<L>(f, qb, -1), A.template ptr<L>(f, q, q)), s);
+  } else {
+    S::st(A.template ptr<L>(f, q, q), s);
+  }
+}
+
+// Same pattern for the 21 induction planes (7 directions x 3 components).
+template <int P, int PAR, bool BND, class AD>
+__device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g, const AD& A, uint32_t mask,
+                                       typename Stor<P>::T (&h)[7][3]) {
+  using S = Stor<P>;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const int kb = opp(k);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const typename S::E* ptr;
+      if (PAR == 0) {
+        ptr = A.template ptr<D3Q19>(g, 3 * k + i, -1);
+      } else {
+        ptr = A.template ptr<D3Q19>(g, 3 * kb + i, kb);
+      }
+      if (PAR == 1 && BND) ptr = pick((mask >> kb) & 1u, A.template ptr<D3Q19>(g, 3 * k + i, -1), ptr);
+      h[k][i] = S::ld(ptr);
+    }
+  }
+}
+
+template <int P, int PAR, bool BND, class AD>
+__device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, const AD& A, uint32_t mask,
+                                        const typename Stor<P>::T (&h)[7][3]) {
+  using S = Stor<P>;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const int kb = opp(k);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      typename S::E* ptr;
+      if (PAR == 0) {
+        ptr = A.template ptr<D3Q19>(g, 3 * kb + i, -1);
+      } else {
+        ptr = A.template ptr<D3Q19>(g, 3 * k + i, k);
+      }
+      if (PAR == 1 && BND) ptr = pick((mask >> k) & 1u, A.template ptr<D3Q19>(g, 3 * kb + i, -1), ptr);
+      S::st(ptr, h[k][i]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+// Sum of v over the 256-thread tile (deterministic order) into out[0..NV),
+// stored (ADD = false) or added to what is there (ADD = true).  Every thread
+// of the tile must call it.
+template <int NV, bool ADD = false>
+__device__ __forceinline__ void tile_sum_store(double (&v)[NV], double* __restrict__ out) {
+  __shared__ double sh[NTHREADS / 64][NV];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s = v[k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    v[k] = s;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[wave][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int k = threadIdx.x;
+    const double t = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
+    out[k] = ADD ? out[k] + t : t;
+  }
+}
+
+}  // namespace lbm

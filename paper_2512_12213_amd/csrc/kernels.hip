@@ -16,306 +16,9 @@
 //
 // All quantities inside the kernels are dimensionless: velocities in units of
 // c = dx/dt, body force as a dt / c, magnetic field as B / (c sqrt(mu)).
-#include "kernels.hpp"
-#include "lattice.hpp"
+#include "device.hpp"
 
 namespace lbm {
-
-// ---------------------------------------------------------------------------
-// storage formats
-// ---------------------------------------------------------------------------
-template <int P>
-struct Stor;
-template <>
-struct Stor<S_F64> {
-  using E = double;
-  using T = double;
-  static __device__ __forceinline__ T ld(const E* p) { return __builtin_nontemporal_load(p); }
-  static __device__ __forceinline__ void st(E* p, T v) { __builtin_nontemporal_store(v, p); }
-};
-template <>
-struct Stor<S_F32> {
-  using E = float;
-  using T = float;
-  static __device__ __forceinline__ T ld(const E* p) { return __builtin_nontemporal_load(p); }
-  static __device__ __forceinline__ void st(E* p, T v) { __builtin_nontemporal_store(v, p); }
-};
-template <>
-struct Stor<S_F16> {
-  using E = _Float16;
-  using T = float;
-  static __device__ __forceinline__ T ld(const E* p) { return (float)__builtin_nontemporal_load(p); }
-  static __device__ __forceinline__ void st(E* p, T v) { __builtin_nontemporal_store((_Float16)v, p); }
-};
-template <>
-struct Stor<S_BF16> {
-  using E = uint16_t;
-  using T = float;
-  static __device__ __forceinline__ T ld(const E* p) {
-    return __uint_as_float(uint32_t(__builtin_nontemporal_load(p)) << 16);
-  }
-  static __device__ __forceinline__ void st(E* p, T v) {
-    uint32_t u = __float_as_uint(v);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    __builtin_nontemporal_store(uint16_t(u >> 16), p);
-  }
-};
-
-template <class T>
-__device__ __forceinline__ T rcp(T x) {
-  return T(1) / x;
-}
-template <>
-__device__ __forceinline__ float rcp<float>(float x) {
-  return __builtin_amdgcn_rcpf(x);
-}
-
-// ---------------------------------------------------------------------------
-// index helpers
-// ---------------------------------------------------------------------------
-// Element offsets to the six axis neighbours (periodic wrap) in a row-blocked
-// array whose rows hold P planes (row stride rs = P nx).
-struct Offs {
-  int xp, xm;
-  int64_t yp, ym, zp, zm;
-};
-
-__device__ __forceinline__ void coords(const Geom& g, uint32_t n, uint32_t& x, uint32_t& y, uint32_t& z, uint32_t& r) {
-  r = g.nx == 1 ? n : (uint32_t)__umul64hi((uint64_t)n, g.mnx);
-  x = n - r * g.nx;
-  z = g.ny == 1 ? r : (uint32_t)__umul64hi((uint64_t)r, g.mny);
-  y = r - z * g.ny;
-}
-
-__device__ __forceinline__ Offs offsets(const Geom& g, uint32_t x, uint32_t y, uint32_t z, uint64_t rs) {
-  Offs o;
-  const int nx = (int)g.nx;
-  const int64_t ry = (int64_t)rs, rz = (int64_t)rs * g.ny;
-  o.xp = (x + 1 == g.nx) ? 1 - nx : 1;
-  o.xm = (x == 0) ? nx - 1 : -1;
-  o.yp = (y + 1 == g.ny) ? (1 - (int64_t)g.ny) * ry : ry;
-  o.ym = (y == 0) ? ((int64_t)g.ny - 1) * ry : -ry;
-  o.zp = (z + 1 == g.nz) ? (1 - (int64_t)g.nz) * rz : rz;
-  o.zm = (z == 0) ? ((int64_t)g.nz - 1) * rz : -rz;
-  return o;
-}
-
-// Offset from a node to its neighbour along e_q.
-template <class L>
-__device__ __forceinline__ int64_t off_of(int q, const Offs& o) {
-  int64_t s = 0;
-  if (L::ex(q) > 0) s += o.xp;
-  if (L::ex(q) < 0) s += o.xm;
-  if (L::ey(q) > 0) s += o.yp;
-  if (L::ey(q) < 0) s += o.ym;
-  if (L::ez(q) > 0) s += o.zp;
-  if (L::ez(q) < 0) s += o.zm;
-  return s;
-}
-
-// Addressing of one node's slots in a row-blocked array with P planes:
-// ptr<L>(f, plane, q) points at `plane` of the neighbour x + e_q (q < 0: the
-// node itself).
-//
-// Generic form: a per-lane element index of the node plus neighbour offsets.
-struct AddrG {
-  uint64_t b;
-  Offs o;
-  uint32_t nx;
-  template <class L, class E>
-  __device__ __forceinline__ E* ptr(E* f, int plane, int q) const {
-    return f + ((q < 0 ? b : b + off_of<L>(q, o)) + (uint32_t)plane * nx);
-  }
-};
-
-// Row-uniform form, used when nx is a multiple of 64: a wavefront then never
-// leaves its x-row, so y, z and every neighbour-row base are wave-uniform
-// (scalar registers) and each lane only adds its 32-bit x byte offset
-// (scalar base + vector offset addressing).  The row bases are recomputed in
-// ptr() rather than kept in an array, so that the compiler never turns a
-// per-lane choice between two slots into a dynamic index of private memory.
-struct AddrR {
-  uint32_t y, z, ny, nz;
-  uint32_t x, xm, xp;  // x, x - 1, x + 1 (periodic), per lane
-  uint32_t nx;
-  uint64_t rs;         // row stride, planes * nx
-  template <class L, class E>
-  __device__ __forceinline__ E* ptr(E* f, int plane, int q) const {
-    const int dx = q < 0 ? 0 : L::ex(q), dy = q < 0 ? 0 : L::ey(q), dz = q < 0 ? 0 : L::ez(q);
-    const uint32_t yy = dy < 0 ? (y == 0 ? ny - 1 : y - 1) : (dy > 0 ? (y + 1 == ny ? 0 : y + 1) : y);
-    const uint32_t zz = dz < 0 ? (z == 0 ? nz - 1 : z - 1) : (dz > 0 ? (z + 1 == nz ? 0 : z + 1) : z);
-    E* base = f + (((uint64_t)zz * ny + yy) * rs + (uint32_t)plane * nx);  // wave-uniform
-    const uint32_t xs = dx < 0 ? xm : (dx > 0 ? xp : x);
-    return (E*)((char*)base + xs * (uint32_t)sizeof(E));  // 32-bit byte offset
-  }
-};
-
-__device__ __forceinline__ AddrG addr_g(const Geom& g, uint32_t x, uint32_t y, uint32_t z, uint32_t r, uint32_t P) {
-  AddrG a;
-  a.b = (uint64_t)r * (P * g.nx) + x;
-  a.o = offsets(g, x, y, z, (uint64_t)P * g.nx);
-  a.nx = g.nx;
-  return a;
-}
-
-// y, z must be wave-uniform.
-__device__ __forceinline__ AddrR addr_r(const Geom& g, uint32_t x, uint32_t y, uint32_t z, uint32_t P) {
-  AddrR a;
-  a.y = y;
-  a.z = z;
-  a.ny = g.ny;
-  a.nz = g.nz;
-  a.x = x;
-  a.xm = x == 0 ? g.nx - 1 : x - 1;
-  a.xp = x + 1 == g.nx ? 0 : x + 1;
-  a.nx = g.nx;
-  a.rs = (uint64_t)P * g.nx;
-  return a;
-}
-
-// Per-lane choice between two addresses, written as mask arithmetic on the
-// address values so that it is not folded into an indexed access of the
-// address objects' fields.
-template <class E>
-__device__ __forceinline__ E* pick(bool c, E* a, E* b) {
-  const uint64_t m = 0ull - (uint64_t)c;
-  return (E*)(((uint64_t)a & m) | ((uint64_t)b & ~m));
-}
-
-template <class L, class T>
-__device__ __forceinline__ T edot(int q, T vx, T vy, T vz) {
-  T s = T(0);
-  if (L::ex(q) > 0) s += vx;
-  if (L::ex(q) < 0) s -= vx;
-  if (L::ey(q) > 0) s += vy;
-  if (L::ey(q) < 0) s -= vy;
-  if (L::ez(q) > 0) s += vz;
-  if (L::ez(q) < 0) s -= vz;
-  return s;
-}
-
-__device__ __forceinline__ uint32_t nibble(const uint4& r, int q) {
-  const uint32_t w = q < 8 ? r.y : (q < 16 ? r.z : r.w);
-  return (w >> (4 * (q & 7))) & 15u;
-}
-
-// ---------------------------------------------------------------------------
-// A-A reads and writes of one node's distributions
-// ---------------------------------------------------------------------------
-// Reading the state f_q(x, t):
-//   even parity (natural layout): slot q of x;
-//   odd parity: slot opp(q) of x - e_q, or, when the link from x along
-//   -e_q ends in a wall, slot q of x (where the bounce-back value was put).
-template <class L, int P, int PAR, bool BND, class AD>
-__device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask,
-                                       const Phys& p, typename Stor<P>::T (&d)[L::Q]) {
-  using S = Stor<P>;
-  using T = typename S::T;
-#pragma unroll
-  for (int q = 0; q < L::Q; ++q) {
-    const int qb = opp(q);
-    const typename S::E* ptr;
-    if (PAR == 0) {
-      ptr = A.template ptr<L>(f, q, -1);
-    } else {
-      ptr = A.template ptr<L>(f, qb, qb);
-    }
-    // a wall link: the value was put in the node's own slot q
-    if (PAR == 1 && BND) ptr = pick((mask >> qb) & 1u, A.template ptr<L>(f, q, -1), ptr);
-    T v = S::ld(ptr);
-    if (P == S_F16 || P == S_BF16) v *= (T)p.inv_scale[q];
-    d[q] = v;
-  }
-}
-
-// Writing the post-collision value v_q of node x (v_q already holds the
-// bounce-back value, including the moving-wall term, for wall links):
-//   even parity: slot opp(q) of x;
-//   odd parity: slot q of x + e_q, or slot opp(q) of x for a wall link.
-template <class L, int P, int PAR, bool BND, class AD>
-__device__ __forceinline__ void write_f(typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask, const Phys& p,
-                                        const typename Stor<P>::T (&v)[L::Q]) {
-  using S = Stor<P>;
-  using T = typename S::T;
-#pragma unroll
-  for (int q = 0; q < L::Q; ++q) {
-    const int qb = opp(q);
-    typename S::E* ptr;
-    if (PAR == 0) {
-      ptr = A.template ptr<L>(f, qb, -1);
-    } else {
-      ptr = A.template ptr<L>(f, q, q);
-    }
-    T s = v[q];
-    if (P == S_F16 || P == S_BF16) s *= (T)p.scale[q];
-    if (PAR == 1 && BND && ((mask >> q) & 1u))
-      S::st(A.template ptr<L>(f, qb, -1), s);  // wall link: back into the node's own slot
-    else
-      S::st(ptr, s);
-  }
-}
-
-// One direction of write_f.
-template <class L, int P, int PAR, bool BND, class AD>
-__device__ __forceinline__ void write_f1(typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask, const Phys& p,
-                                         int q, typename Stor<P>::T v) {
-  using S = Stor<P>;
-  using T = typename S::T;
-  const int qb = opp(q);
-  T s = v;
-  if (P == S_F16 || P == S_BF16) s *= (T)p.scale[q];
-  if (PAR == 0) {
-    S::st(A.template ptr<L>(f, qb, -1), s);
-  } else if (BND) {
-    // wall link: back into the node's own slot
-    S::st(pick((mask >> q) & 1u, A.template ptr<L>(f, qb, -1), A.template ptr<L>(f, q, q)), s);
-  } else {
-    S::st(A.template ptr<L>(f, q, q), s);
-  }
-}
-
-// Same pattern for the 21 induction planes (7 directions x 3 components).
-template <int P, int PAR, bool BND, class AD>
-__device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g, const AD& A, uint32_t mask,
-                                       typename Stor<P>::T (&h)[7][3]) {
-  using S = Stor<P>;
-#pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    const int kb = opp(k);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const typename S::E* ptr;
-      if (PAR == 0) {
-        ptr = A.template ptr<D3Q19>(g, 3 * k + i, -1);
-      } else {
-        ptr = A.template ptr<D3Q19>(g, 3 * kb + i, kb);
-      }
-      if (PAR == 1 && BND) ptr = pick((mask >> kb) & 1u, A.template ptr<D3Q19>(g, 3 * k + i, -1), ptr);
-      h[k][i] = S::ld(ptr);
-    }
-  }
-}
-
-template <int P, int PAR, bool BND, class AD>
-__device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, const AD& A, uint32_t mask,
-                                        const typename Stor<P>::T (&h)[7][3]) {
-  using S = Stor<P>;
-#pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    const int kb = opp(k);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      typename S::E* ptr;
-      if (PAR == 0) {
-        ptr = A.template ptr<D3Q19>(g, 3 * kb + i, -1);
-      } else {
-        ptr = A.template ptr<D3Q19>(g, 3 * k + i, k);
-      }
-      if (PAR == 1 && BND) ptr = pick((mask >> k) & 1u, A.template ptr<D3Q19>(g, 3 * kb + i, -1), ptr);
-      S::st(ptr, h[k][i]);
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // local physics
@@ -524,34 +227,9 @@ __device__ __forceinline__ void collide_g(T (&h)[7][3], const Macro<T>& m, const
 }
 
 // ---------------------------------------------------------------------------
-// reductions
-// ---------------------------------------------------------------------------
-template <int NV>
-__device__ __forceinline__ void tile_sum_store(double (&v)[NV], double* __restrict__ out) {
-  __shared__ double sh[NTHREADS / 64][NV];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = v[k];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    v[k] = s;
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) sh[wave][k] = v[k];
-  }
-  __syncthreads();
-  if (threadIdx.x < NV) {
-    const int k = threadIdx.x;
-    out[k] = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // the fused step
 // ---------------------------------------------------------------------------
-template <class L, int P, bool MHD, int PAR, bool DIAG, bool BND, class AD>
+template <class L, int P, bool MHD, int PAR, bool DIAG, bool MAC, bool BND, class AD>
 __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const AD& Af, const AD& Ag, const uint4& rec,
                                             typename Stor<P>::T (&bal)[NBAL],
                                             typename Stor<P>::T (&wacc)[MAXBG][NWALL], uint32_t bgrp) {
@@ -586,6 +264,14 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
   }
   Macro<T> m;
   macro<L, T, MHD, false>(d, a.p, Ax, Ay, Az, db, m);
+  if (MAC) {
+    // density and velocity of the pre-step state, for the adjoint
+    T* mo = (T*)a.mac;
+    mo[n] = m.rho;
+    mo[g.N + n] = m.U[0];
+    mo[2 * (uint64_t)g.N + n] = m.U[1];
+    mo[3 * (uint64_t)g.N + n] = m.U[2];
+  }
   if (DIAG) {
     bal[0] += m.drho;
     bal[1] += m.rho * m.U[0];
@@ -637,7 +323,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
   }
 }
 
-template <class L, int P, bool MHD, int PAR, bool DIAG, bool RU>
+template <class L, int P, bool MHD, int PAR, bool DIAG, bool RU, bool MAC = false>
 __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   using T = typename Stor<P>::T;
   const Geom& g = a.geo;
@@ -670,16 +356,16 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
         const AddrR Af = addr_r(g, x, y, z, L::Q);
         const AddrR Ag = addr_r(g, x, y, z, MHD ? 21 : L::Q);
         if (rr < 0)
-          node_update<L, P, MHD, PAR, DIAG, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
         else
-          node_update<L, P, MHD, PAR, DIAG, true>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          node_update<L, P, MHD, PAR, DIAG, MAC, true>(a, n, Af, Ag, rec, bal, wacc, bgrp);
       } else {
         const AddrG Af = addr_g(g, x, y, z, r, L::Q);
         const AddrG Ag = addr_g(g, x, y, z, r, MHD ? 21 : L::Q);
         if (rr < 0)
-          node_update<L, P, MHD, PAR, DIAG, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
         else
-          node_update<L, P, MHD, PAR, DIAG, true>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          node_update<L, P, MHD, PAR, DIAG, MAC, true>(a, n, Af, Ag, rec, bal, wacc, bgrp);
       }
     }
   }
@@ -978,6 +664,25 @@ static hipError_t launch_step_t(const StepArgs& a, int parity, bool diag, hipStr
   return hipGetLastError();
 }
 
+// Forward step that also records rho and U of the pre-step state (adjoint
+// recompute): F32 / F64 storage, no MHD, no diagnostics.
+template <class L, int P>
+static hipError_t launch_step_mac_t(const StepArgs& a, int parity, hipStream_t st) {
+  const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
+  if (a.geo.nx % 64 == 0) {
+    if (parity == 0)
+      k_step<L, P, false, 0, false, true, true><<<nb, NTHREADS, 0, st>>>(a);
+    else
+      k_step<L, P, false, 1, false, true, true><<<nb, NTHREADS, 0, st>>>(a);
+  } else {
+    if (parity == 0)
+      k_step<L, P, false, 0, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
+    else
+      k_step<L, P, false, 1, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
+  }
+  return hipGetLastError();
+}
+
 template <class L, int P, bool MHD>
 static hipError_t launch_diag_t(const DiagArgs& a, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
@@ -1019,6 +724,13 @@ static hipError_t launch_init_t(const InitArgs& a, hipStream_t st) {
 
 hipError_t launch_step(int lattice, int prec, bool mhd, const StepArgs& a, int parity, bool diag, hipStream_t st) {
   LBM_DISPATCH(launch_step_t, lattice, prec, mhd, a, parity, diag, st);
+}
+
+hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, hipStream_t st) {
+  if (prec != S_F32 && prec != S_F64) return hipErrorInvalidValue;
+  if (lattice == 0)
+    return prec == S_F64 ? launch_step_mac_t<D2Q9, S_F64>(a, parity, st) : launch_step_mac_t<D2Q9, S_F32>(a, parity, st);
+  return prec == S_F64 ? launch_step_mac_t<D3Q19, S_F64>(a, parity, st) : launch_step_mac_t<D3Q19, S_F32>(a, parity, st);
 }
 
 hipError_t launch_diag(int lattice, int prec, bool mhd, const DiagArgs& a, hipStream_t st) {

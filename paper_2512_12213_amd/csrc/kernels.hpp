@@ -44,6 +44,25 @@ struct StepArgs {
   const uint32_t* blkgrp;  // per tile: up to MAXBG group labels, 4 bits each, + count in bits 28..31
   const double* uw;        // [MAXG][3] wall velocity / c
   double* part;            // [ntiles][NPART] on diagnostic steps
+  void* mac;               // [4][N] rho, U of the pre-step state (adjoint recompute), or null
+  Geom geo;
+  Phys p;
+};
+
+// Arguments of the adjoint step kernel (reverse of one forward step).
+struct AdjArgs {
+  void* lam;               // adjoint state, same type and layout as the distributions
+  const void* mac;         // [4][N] rho, U of the forward state before this step
+  const float* afield;     // [3][N] or null
+  const uint4* rec;
+  const int* rowrec;
+  const uint32_t* blkgrp;
+  const double* uw;        // [MAXG][3] wall velocity / c
+  void* grad_a;            // [3][N] float or double (grad_f64), accumulated; or null
+  double* part;            // [ntiles][NPART], wall-velocity cotangents accumulated in the wall slots
+  double ga_scale;         // factor from the node's force cotangent to grad_a
+  int grad_f64;
+  int seed_group, seed_axis;  // objective (last forward step only)
   Geom geo;
   Phys p;
 };

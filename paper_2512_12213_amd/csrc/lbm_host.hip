@@ -20,6 +20,8 @@ hipError_t launch_diag(int lattice, int prec, bool mhd, const DiagArgs& a, hipSt
 hipError_t launch_init(int lattice, int prec, bool mhd, const InitArgs& a, hipStream_t st);
 hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t ntiles, int mode, int nout, double* out,
                          hipStream_t st);
+hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, hipStream_t st);
+hipError_t launch_adj(int lattice, int prec, int adj_prec, const AdjArgs& a, int parity, bool seed, hipStream_t st);
 }  // namespace lbm
 
 using namespace lbm;
@@ -116,6 +118,12 @@ struct lbm_ctx {
   bool have_step = false;
   double last[NBAL + MAXG * NWALL] = {};
   double last_uw[MAXG][3] = {};
+  // adjoint: the recorded forward run (checkpoints every tape_K steps) and
+  // the buffers of the backward pass
+  DevBuf ckpt, replay, lam, mac, adjpart, adjred;
+  bool tape = false;
+  int adj_prec = S_F64;  // precision of the adjoint state and arithmetic
+  int tape_T = 0, tape_K = 0, tape_group = 0, tape_axis = 0, tape_par0 = 0;
   // optional per-launch timing of lbm_step (HIP events on the context stream)
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -384,7 +392,7 @@ lbm_ctx* lbm_create(int lattice, int nx, int ny, int nz, double tau, double dx, 
     return nullptr;
   }
   h->stream = h->own;
-  if (hipHostMalloc((void**)&h->hred, (NBAL + MAXG * NWALL + NDIAGPART) * sizeof(double)) != hipSuccess) {
+  if (hipHostMalloc((void**)&h->hred, (2 * (NBAL + MAXG * NWALL) + NDIAGPART) * sizeof(double)) != hipSuccess) {
     fail(LBM_ENOMEM, "pinned host buffer");
     (void)hipStreamDestroy(h->own);
     delete h;
@@ -446,6 +454,7 @@ int lbm_add_solid_mask(lbm_ctx* h, const unsigned char* mask, int group) {
 
 int lbm_set_wall_velocity(lbm_ctx* h, int group, double ux, double uy, double uz) {
   if (!h) return fail(LBM_EINVAL, "null context");
+  h->tape = false;
   if (group < 0 || group >= MAXG) return fail(LBM_EINVAL, "group out of range");
   if (!std::isfinite(ux) || !std::isfinite(uy) || !std::isfinite(uz)) return fail(LBM_EINVAL, "non-finite velocity");
   h->uw[group][0] = ux;
@@ -457,6 +466,7 @@ int lbm_set_wall_velocity(lbm_ctx* h, int group, double ux, double uy, double uz
 
 int lbm_set_body_force(lbm_ctx* h, double ax, double ay, double az) {
   if (!h) return fail(LBM_EINVAL, "null context");
+  h->tape = false;
   if (!std::isfinite(ax) || !std::isfinite(ay) || !std::isfinite(az)) return fail(LBM_EINVAL, "non-finite force");
   h->a[0] = ax;
   h->a[1] = ay;
@@ -466,12 +476,14 @@ int lbm_set_body_force(lbm_ctx* h, double ax, double ay, double az) {
 
 int lbm_set_body_force_field(lbm_ctx* h, const void* dev_ptr) {
   if (!h) return fail(LBM_EINVAL, "null context");
+  h->tape = false;
   h->afield = (const float*)dev_ptr;
   return LBM_OK;
 }
 
 int lbm_set_les(lbm_ctx* h, double cs) {
   if (!h) return fail(LBM_EINVAL, "null context");
+  h->tape = false;
   if (!(cs >= 0) || !std::isfinite(cs)) return fail(LBM_EINVAL, "C_s must be >= 0");
   h->cs = cs;
   return LBM_OK;
@@ -506,6 +518,7 @@ int lbm_set_stream(lbm_ctx* h, void* s) {
 
 int lbm_init_equilibrium(lbm_ctx* h, const double* u0) {
   if (!h) return fail(LBM_EINVAL, "null context");
+  h->tape = false;
   int rc = build_geometry(h);
   if (rc) return rc;
   rc = alloc_state(h);
@@ -534,6 +547,7 @@ int lbm_init_equilibrium(lbm_ctx* h, const double* u0) {
 
 int lbm_set_state(lbm_ctx* h, const double* d) {
   if (!h) return fail(LBM_EINVAL, "null context");
+  h->tape = false;
   if (!d) return fail(LBM_EINVAL, "null state");
   int rc = build_geometry(h);
   if (rc) return rc;
@@ -597,11 +611,7 @@ int lbm_get_induction(lbm_ctx* h, double* gout) {
   return LBM_OK;
 }
 
-int lbm_step(lbm_ctx* h, int n) {
-  int rc = check_ready(h);
-  if (rc) return rc;
-  if (n < 0) return fail(LBM_EINVAL, "negative step count");
-  if (n == 0) return LBM_OK;
+static int upload_uw(lbm_ctx* h) {
   if (h->uw_dirty) {
     double t[MAXG * 3];
     for (int gr = 0; gr < MAXG; ++gr)
@@ -609,7 +619,17 @@ int lbm_step(lbm_ctx* h, int n) {
     HIPCHK(hipMemcpy(h->uwdev.p, t, sizeof(t), hipMemcpyHostToDevice));
     h->uw_dirty = false;
   }
+  return LBM_OK;
+}
+
+// n >= 1 steps; the last one with diagnostics.  With ckpt_every > 0 the state
+// before step i is copied to checkpoint i / ckpt_every whenever
+// i % ckpt_every == 0.
+static int step_loop(lbm_ctx* h, int n, int ckpt_every) {
+  int rc = upload_uw(h);
+  if (rc) return rc;
   StepArgs a = step_args(h);
+  const size_t sbytes = (size_t)h->Q * h->N * elem_bytes(h->prec);
   if (h->timing) {
     while (h->ev.size() < (size_t)n + 2) {
       hipEvent_t e;
@@ -620,6 +640,9 @@ int lbm_step(lbm_ctx* h, int n) {
   const int par0 = h->parity;
   if (h->timing) HIPCHK(hipEventRecord(h->ev[0], h->stream));
   for (int i = 0; i < n; ++i) {
+    if (ckpt_every > 0 && i % ckpt_every == 0)
+      HIPCHK(hipMemcpyAsync((char*)h->ckpt.p + (size_t)(i / ckpt_every) * sbytes, h->f.p, sbytes,
+                            hipMemcpyDeviceToDevice, h->stream));
     const bool diag = i == n - 1;
     HIPCHK(launch_step(h->lattice, h->prec, h->mhd, a, h->parity, diag, h->stream));
     if (h->timing) HIPCHK(hipEventRecord(h->ev[i + 1], h->stream));
@@ -661,6 +684,15 @@ int lbm_step(lbm_ctx* h, int n) {
   h->have_step = true;
   if (!std::isfinite(h->last[0])) return fail(LBM_EUNSTABLE, "total mass is not finite after step %ld", h->steps);
   return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* h, int n) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (n < 0) return fail(LBM_EINVAL, "negative step count");
+  if (n == 0) return LBM_OK;
+  h->tape = false;
+  return step_loop(h, n, 0);
 }
 
 int lbm_get_macro(lbm_ctx* h, double* rho, double* v) {
@@ -834,6 +866,117 @@ long lbm_link_count(lbm_ctx* h, int group) {
     for (int q = 0; q < h->Q; ++q) s += h->nlink[(size_t)gr * h->Q + q];
   }
   return s;
+}
+
+static int adjoint_supported(lbm_ctx* h) {
+  if (h->prec != S_F32 && h->prec != S_F64) return fail(LBM_EINVAL, "the adjoint needs F32 or F64 storage");
+  if (h->mhd) return fail(LBM_EINVAL, "the adjoint does not cover the MHD equilibrium");
+  if (h->cs > 0) return fail(LBM_EINVAL, "the adjoint does not cover the Smagorinsky closure");
+  return LBM_OK;
+}
+
+int lbm_adjoint_forward(lbm_ctx* h, int T, int ckpt_every, int group, int axis, double* J) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  rc = adjoint_supported(h);
+  if (rc) return rc;
+  if (T < 1) return fail(LBM_EINVAL, "T must be >= 1");
+  if (ckpt_every < 1) return fail(LBM_EINVAL, "ckpt_every must be >= 1");
+  if (group < 0 || group >= h->G) return fail(LBM_EINVAL, "group %d is not a wall group in use", group);
+  if (axis < 0 || axis >= h->D) return fail(LBM_EINVAL, "axis %d out of range", axis);
+  if (!J) return fail(LBM_EINVAL, "null J");
+  const int nseg = (T + ckpt_every - 1) / ckpt_every;
+  const size_t sbytes = (size_t)h->Q * h->N * elem_bytes(h->prec);
+  HIPCHK(h->ckpt.ensure((size_t)nseg * sbytes));
+  h->tape = false;
+  const int par0 = h->parity;
+  rc = step_loop(h, T, ckpt_every);
+  if (rc) return rc;
+  double v[4][3];
+  wall_variants(h, group, v);
+  *J = v[0][axis];
+  h->tape = true;
+  h->tape_T = T;
+  h->tape_K = ckpt_every;
+  h->tape_group = group;
+  h->tape_axis = axis;
+  h->tape_par0 = par0;
+  return LBM_OK;
+}
+
+int lbm_adjoint_backward(lbm_ctx* h, double gJ, void* grad_a_dev, int grad_f64, double* grad_uw) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!h->tape) return fail(LBM_ESTATE, "no recorded run: call lbm_adjoint_forward first (set-up changes and steps discard it)");
+  if (!std::isfinite(gJ)) return fail(LBM_EINVAL, "non-finite gJ");
+  const int T = h->tape_T, K = h->tape_K;
+  const int nseg = (T + K - 1) / K;
+  const size_t eb = elem_bytes(h->prec);
+  const size_t sbytes = (size_t)h->Q * h->N * eb;
+  const size_t mbytes = (size_t)4 * h->N * eb;
+  const int ap = h->prec == S_F64 ? S_F64 : h->adj_prec;
+  HIPCHK(h->replay.ensure(sbytes));
+  HIPCHK(h->lam.ensure((size_t)h->Q * h->N * elem_bytes(ap)));
+  HIPCHK(h->mac.ensure((size_t)std::min(K, T) * mbytes));
+  HIPCHK(h->adjpart.ensure((size_t)h->ntiles * NPART * sizeof(double)));
+  HIPCHK(h->adjred.ensure((NBAL + MAXG * NWALL) * sizeof(double)));
+  rc = upload_uw(h);
+  if (rc) return rc;
+  const size_t gbytes = (size_t)3 * h->N * (grad_f64 ? sizeof(double) : sizeof(float));
+  if (grad_a_dev) HIPCHK(hipMemsetAsync(grad_a_dev, 0, gbytes, h->stream));
+  HIPCHK(hipMemsetAsync(h->adjpart.p, 0, (size_t)h->ntiles * NPART * sizeof(double), h->stream));
+  const double fscale = vol(h) * h->c / h->dt;  // force units of the unit-seed objective
+  StepArgs sa = step_args(h);
+  sa.f = h->replay.p;
+  AdjArgs aa = {};
+  aa.lam = h->lam.p;
+  aa.afield = h->afield;
+  aa.rec = (const uint4*)h->rec.p;
+  aa.rowrec = (const int*)h->rowrec.p;
+  aa.blkgrp = (const uint32_t*)h->blkgrp.p;
+  aa.uw = (const double*)h->uwdev.p;
+  aa.grad_a = grad_a_dev;
+  aa.grad_f64 = grad_f64 ? 1 : 0;
+  aa.part = (double*)h->adjpart.p;
+  aa.ga_scale = gJ * fscale * h->dt / h->c;
+  aa.seed_group = h->tape_group;
+  aa.seed_axis = h->tape_axis;
+  aa.geo = sa.geo;
+  aa.p = sa.p;
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int t0 = seg * K, t1 = std::min(T, t0 + K);
+    // recompute the segment from its checkpoint, recording rho and U
+    HIPCHK(hipMemcpyAsync(h->replay.p, (char*)h->ckpt.p + (size_t)seg * sbytes, sbytes, hipMemcpyDeviceToDevice,
+                          h->stream));
+    for (int t = t0; t < t1; ++t) {
+      sa.mac = (char*)h->mac.p + (size_t)(t - t0) * mbytes;
+      HIPCHK(launch_step_mac(h->lattice, h->prec, sa, (h->tape_par0 + t) & 1, h->stream));
+    }
+    // then reverse its steps
+    for (int t = t1 - 1; t >= t0; --t) {
+      aa.mac = (const char*)h->mac.p + (size_t)(t - t0) * mbytes;
+      HIPCHK(launch_adj(h->lattice, h->prec, ap, aa, (h->tape_par0 + t) & 1, t == T - 1, h->stream));
+    }
+  }
+  double* hr = h->hred + NBAL + MAXG * NWALL + NDIAGPART;
+  HIPCHK(launch_reduce((const double*)h->adjpart.p, (const uint32_t*)h->blkgrp.p, h->ntiles, 0, NBAL + MAXG * NWALL,
+                       (double*)h->adjred.p, h->stream));
+  HIPCHK(hipMemcpyAsync(hr, h->adjred.p, (NBAL + MAXG * NWALL) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (grad_uw) {
+    const double su = gJ * fscale / h->c;
+    for (int gr = 0; gr < h->G; ++gr)
+      for (int k = 0; k < 3; ++k) grad_uw[3 * gr + k] = k < h->D ? su * hr[NBAL + gr * NWALL + k] : 0.0;
+  }
+  return LBM_OK;
+}
+
+int lbm_set_adjoint_precision(lbm_ctx* h, int precision) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (precision != LBM_F64 && precision != LBM_F32) return fail(LBM_EINVAL, "adjoint precision must be LBM_F64 or LBM_F32");
+  if (precision == LBM_F32 && h->prec == S_F64) return fail(LBM_EINVAL, "an FP64 lattice keeps an FP64 adjoint");
+  h->adj_prec = precision;
+  return LBM_OK;
 }
 
 int lbm_set_timing(lbm_ctx* h, int on) {

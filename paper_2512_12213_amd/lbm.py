@@ -50,6 +50,9 @@ _SIGS = [
     ("lbm_num_groups", C.c_int, [_P]),
     ("lbm_link_count", C.c_long, [_P, C.c_int]),
     ("lbm_steps_taken", C.c_long, [_P]),
+    ("lbm_adjoint_forward", C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.c_int, _D]),
+    ("lbm_adjoint_backward", C.c_int, [_P, C.c_double, C.c_void_p, C.c_int, _D]),
+    ("lbm_set_adjoint_precision", C.c_int, [_P, C.c_int]),
     ("lbm_set_timing", C.c_int, [_P, C.c_int]),
     ("lbm_step_timings", C.c_int, [_P, _D]),
 ]
@@ -230,6 +233,25 @@ class Lattice:
 
     def steps_taken(self):
         return self.L.lbm_steps_taken(self.h)
+
+    # differentiation
+    def adjoint_forward(self, T, ckpt_every, group, axis):
+        """Record T steps (checkpoint every ckpt_every) and return J, the raw
+        wall force of `group` along `axis` during the last step."""
+        J = np.zeros(1)
+        _chk(self.L.lbm_adjoint_forward(self.h, T, ckpt_every, group, axis, _dp(J)))
+        return float(J[0])
+
+    def adjoint_backward(self, gJ=1.0, grad_a_ptr=None, grad_f64=False):
+        """gJ dJ/du_w as [G, 3]; gJ dJ/da into the device buffer at
+        grad_a_ptr ([3, nz, ny, nx], float32 or float64) when given."""
+        G = self.num_groups()
+        gu = np.zeros((G, 3))
+        _chk(self.L.lbm_adjoint_backward(self.h, gJ, grad_a_ptr, int(grad_f64), _dp(gu)))
+        return gu
+
+    def set_adjoint_precision(self, precision):
+        _chk(self.L.lbm_set_adjoint_precision(self.h, precision))
 
     def set_timing(self, on=True):
         _chk(self.L.lbm_set_timing(self.h, int(on)))
