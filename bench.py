@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BYTES = {0: 8, 1: 4, 2: 2, 3: 2}  # storage -> bytes per value
 KERNEL_SOURCES = ("paper_2512_12213_amd/csrc/kernels.hip", "paper_2512_12213_amd/csrc/kernels.hpp",
-                  "paper_2512_12213_amd/csrc/lattice.hpp", "paper_2512_12213_amd/build.py")
+                  "paper_2512_12213_amd/csrc/device.hpp", "paper_2512_12213_amd/csrc/lattice.hpp",
+                  "paper_2512_12213_amd/build.py")
 TRAFFIC_RECORD = "profiles/k_step_d3q19_f32_duct_les_256x128x128.md"
 
 

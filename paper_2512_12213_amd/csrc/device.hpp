@@ -14,6 +14,12 @@ namespace lbm {
 // ---------------------------------------------------------------------------
 // storage formats
 // ---------------------------------------------------------------------------
+// Cache hints (measured on MI355X, D3Q19 duct 256x128x128): 4- and 2-byte
+// stores are plain (temporal), so that the partial 128-byte lines of the
+// x-shifted A-A writes are merged in L2 before they are written back
+// (non-temporal stores cost 4 % in FP32, 7 % on odd steps); 8-byte stores stay
+// non-temporal (plain ones cost FP64 5 %).  4- and 8-byte loads are
+// non-temporal, 2-byte loads plain (7 % faster for the 16-bit formats).
 template <int P>
 struct Stor;
 template <>
@@ -28,26 +34,26 @@ struct Stor<S_F32> {
   using E = float;
   using T = float;
   static __device__ __forceinline__ T ld(const E* p) { return __builtin_nontemporal_load(p); }
-  static __device__ __forceinline__ void st(E* p, T v) { __builtin_nontemporal_store(v, p); }
+  static __device__ __forceinline__ void st(E* p, T v) { *p = v; }
 };
 template <>
 struct Stor<S_F16> {
   using E = _Float16;
   using T = float;
-  static __device__ __forceinline__ T ld(const E* p) { return (float)__builtin_nontemporal_load(p); }
-  static __device__ __forceinline__ void st(E* p, T v) { __builtin_nontemporal_store((_Float16)v, p); }
+  static __device__ __forceinline__ T ld(const E* p) { return (float)*p; }
+  static __device__ __forceinline__ void st(E* p, T v) { *p = (_Float16)v; }
 };
 template <>
 struct Stor<S_BF16> {
   using E = uint16_t;
   using T = float;
   static __device__ __forceinline__ T ld(const E* p) {
-    return __uint_as_float(uint32_t(__builtin_nontemporal_load(p)) << 16);
+    return __uint_as_float(uint32_t(*p) << 16);
   }
   static __device__ __forceinline__ void st(E* p, T v) {
     uint32_t u = __float_as_uint(v);
     u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    __builtin_nontemporal_store(uint16_t(u >> 16), p);
+    *p = uint16_t(u >> 16);
   }
 };
 
