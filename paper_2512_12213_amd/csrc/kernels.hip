@@ -200,7 +200,11 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
     }
     const T euf = edot<L>(q, m.UF[0], m.UF[1], m.UF[2]);
     const T F = cr * w * (T(3) * (ea - ufa) + T(9) * euf * ea);
-    sink(q, d[q] + (neq + w * Rs) * itau + F);
+    // the increment is formed first and added to d once: adding the small
+    // force term F to an already rounded d + (neq + w Rs) / tau would round it
+    // away in the same direction at every step (a drift of momentum and mass
+    // in slowly varying flows)
+    sink(q, d[q] + ((neq + w * Rs) * itau + F));
   }
 }
 

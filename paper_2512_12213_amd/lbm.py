@@ -68,11 +68,21 @@ class LBMError(RuntimeError):
 
 
 def lib():
-    """Load liblbm.so (raises if it has not been built)."""
+    """Load liblbm.so (raises if it has not been built).
+
+    PyTorch for ROCm ships its own HIP runtime.  If the library were loaded
+    first, a later ``import torch`` would bring a second HIP runtime into the
+    process and torch would find no device; importing torch first (when it is
+    installed) makes the library bind to torch's runtime, so that both share
+    one runtime, one device context and interoperable streams."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("liblbm.so is not built; run paper_2512_12213_amd.build.build() first")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, res, args in _SIGS:
             fn = getattr(L, name)
