@@ -96,11 +96,22 @@ def test_couette_cylinder_full_20000_steps(lbm, storage):
     assert e["wall"] <= (1e-12 if storage == W.F64 else 1e-4)
     # tangentially moving lid and static walls: no momentum-flux correction
     assert np.abs(fw[:3, 1] - fw[:3, 0]).max() <= 1e-6 * np.abs(fw[:3, 0]).max()
-    # Eq. (32) per step, relative to the largest of its terms (sums over 64k
-    # nodes: FP64 rounding of the sums is about 1e-12 of them)
+    # Eq. (32) per step.  FP64: relative to the largest of its terms (sums over
+    # 64k nodes round at about 1e-12 of them).  FP32: the momentum change is
+    # taken from states rounded to FP32, so the residual is bounded by the
+    # storage rounding of the momentum, half an FP32 unit of the largest stored
+    # value times the 6 (2D: 6 of 9 directions carry x momentum) per node and
+    # the fluid nodes (dx = dt = 1); measured 9.9e-6 against that bound of 4e-4
     rec = g.force_balance()
-    scale = np.abs(rec[0:9]).max()
-    assert np.abs(rec[9:12]).max() <= (1e-11 if storage == W.F64 else 1e-5) * scale
+    res = np.abs(rec[9:12]).max()
+    if storage == W.F64:
+        assert res <= 1e-11 * np.abs(rec[0:9]).max()
+    else:
+        dmax = np.abs(g.get_state()).max()
+        nfluid = int((W.obstacle_mask(w) == 0).sum())
+        bound = 0.5 * float(np.spacing(np.float32(dmax))) * 6 * nfluid
+        say("balance residual %.2e, FP32 storage-rounding bound %.2e" % (res, bound))
+        assert res <= bound
 
 
 def test_duct_les_full_size_1000_steps_every_format(lbm):
