@@ -76,6 +76,31 @@ def parse():
     return ap.parse_args()
 
 
+def W_obstacle_mask(w):
+    from paper_2512_12213_amd import workloads as W
+    return W.obstacle_mask(w)
+
+
+def copy_ceiling(torch, nbytes, repeats=20):
+    """Device-to-device copy of nbytes / 2 bytes (nbytes moved: read + write),
+    the practical bandwidth ceiling for the step's traffic."""
+    n = nbytes // 2 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(repeats):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / repeats
+    del src, dst
+    return 2 * n * 4 / t / 1e9
+
+
 def timed_run(lbm, torch, w, steps, warmup, storage=None):
     """Warm up, then time one lbm_step(steps) call; returns a result dict."""
     lat = lbm.from_workload(w, storage=storage)
@@ -97,11 +122,14 @@ def timed_run(lbm, torch, w, steps, warmup, storage=None):
     fw = lat.wall_force()
     lat.close()
     st = w.storage if storage is None else storage
+    mask = W_obstacle_mask(w)
+    nfluid = w.N if mask is None else int((mask == 0).sum())
     bpn = 2 * w.Q * BYTES[st] + (2 * 21 * BYTES[st] if w.mhd is not None else 0)
     n_even = (steps - 1 + 1) // 2
     launch = (tim["even"] * n_even + tim["odd"] * (steps - 1 - n_even)) / max(steps - 1, 1)
     return {
         "mlups": w.N * steps / t / 1e6,
+        "fluid_mlups": nfluid * steps / t / 1e6,
         "ms_per_step": t * 1e3 / steps,
         "launch_us": {"even": tim["even"] * 1e6, "odd": tim["odd"] * 1e6, "mean": launch * 1e6,
                       "diagnostic_last_step": tim["diag"] * 1e6, "reduce_and_copy": tim["tail"] * 1e6},
@@ -165,6 +193,9 @@ def adjoint_run(lbm, torch, W, adj_prec, repeats=3):
 
 
 def cpu_baseline(W, budget_s):
+    """The CPU oracle as it stands on this host: all threads on the full duct
+    (about budget_s of work), one thread on a few steps of the same, and the
+    oracle's reverse pass on two steps of the differentiable duct."""
     import oracle
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from helpers import make_oracle
@@ -178,6 +209,20 @@ def cpu_baseline(W, budget_s):
     t0 = time.perf_counter()
     o.step(n)
     t = time.perf_counter() - t0
+    oracle.threads(1)
+    t0 = time.perf_counter()
+    o.step(2)
+    t_one = time.perf_counter() - t0
+    oracle.threads(threads)
+    o.close()
+    wa = W.duct_sphere()
+    oracle.threads(threads, complex_step=True)
+    a0 = W.force_field(wa.nx, wa.ny, wa.nz, base=wa.body_force, amp=0.3, seed=16)
+    oa = make_oracle(wa, complex_step=True)
+    oa.set_body_force_field(a0)
+    t0 = time.perf_counter()
+    oa.adjoint(2, 4, 0)
+    t_adj = time.perf_counter() - t0
     return {
         "value": w.N * n / t / 1e6,
         "unit": "MLUPS",
@@ -185,6 +230,10 @@ def cpu_baseline(W, budget_s):
         "kind": "oracle",
         "sample": "%d steps of the full %dx%dx%d duct (FP64, LES, walls) after 1 untimed step, %.1f s"
                   % (n, w.nx, w.ny, w.nz, t),
+        "single_thread_mlups": w.N * 2 / t_one / 1e6,
+        "adjoint_mlups": wa.N * 2 / t_adj / 1e6,
+        "adjoint_sample": "forward and reverse pass (complex-step node Jacobians) of 2 steps of the "
+                          "128x64x64 duct with a sphere, %d threads, %.1f s" % (threads, t_adj),
     }
 
 
@@ -214,6 +263,7 @@ def main():
     print("bench: headline FP32 duct, warmup %d, timed %d steps" % (args.warmup, args.steps),
           file=sys.stderr, flush=True)
     r = timed_run(lbm, torch, w, args.steps, args.warmup)
+    copy_gbs = copy_ceiling(torch, r["bytes_per_launch"])
     out = {
         "metric": "MLUPS + % HBM roofline (FP32/16-bit vs FP64 at stated err); adjoint MLUPS",
         "value": round(r["mlups"], 1),
@@ -245,6 +295,8 @@ def main():
             "kernel": "lbm::k_step<D3Q19, F32, no MHD, parity, no diagnostics, row-uniform>",
             "bytes_per_launch": r["bytes_per_launch"],
             "launch_us": {k: round(v, 2) for k, v in r["launch_us"].items()},
+            "copy_ceiling_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(r["achieved_gbs"] / copy_gbs, 4),
         },
         "balance_residual_rel": r["balance_residual_rel"],
     }
@@ -261,7 +313,7 @@ def main():
         print("bench: variant poiseuille", file=sys.stderr, flush=True)
         variants["poiseuille_f64_64x32"] = timed_run(lbm, torch, W.poiseuille(), 5000, 100)
         for v in variants.values():
-            for k in ("mlups", "ms_per_step", "achieved_gbs", "frac"):
+            for k in ("mlups", "fluid_mlups", "ms_per_step", "achieved_gbs", "frac"):
                 v[k] = round(v[k], 4 if k == "frac" else 2)
             v["launch_us"] = {k: round(x, 2) for k, x in v["launch_us"].items()}
         out["variants"] = variants
