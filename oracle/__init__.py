@@ -58,6 +58,7 @@ def _lib(complex_step: bool):
         lib.orc_link_count.restype = C.c_long
         lib.orc_link_count.argtypes = [P, C.c_int]
         lib.orc_adjoint.argtypes = [P, C.c_int, C.c_int, C.c_int, dp, dp, dp]
+        lib.orc_halfstep.argtypes = [P, dp, dp, dp, dp]
         _libs[name] = lib
     return _libs[name]
 
@@ -197,6 +198,18 @@ class Oracle:
 
     def link_count(self, group=-1):
         return self.lib.orc_link_count(self.h, group)
+
+    def halfstep(self):
+        """Half-step distribution of the last step (Eq. 27) and its moments:
+        (fbar [Q, ...] deviations, rho_bar, u_bar [D, ...], sigma_bar [ncomp, ...])."""
+        nc = 3 if self.D == 2 else 6
+        sh = (self.nz, self.ny, self.nx)
+        fb = np.empty((self.Q,) + sh)
+        rb = np.empty(sh)
+        ub = np.empty((self.D,) + sh)
+        sb = np.empty((nc,) + sh)
+        self._chk(self.lib.orc_halfstep(self.h, _dp(fb), _dp(rb), _dp(ub), _dp(sb)))
+        return fb, rb, ub, sb
 
     def adjoint(self, T, group, axis):
         """Reverse-mode gradient of J = component `axis` of the raw wall force

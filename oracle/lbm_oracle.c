@@ -71,6 +71,8 @@ struct orc {
   double B0[3], mu, tau_m;
   real *g, *gn; /* induction distributions [7][3][N] */
   real *d, *dn; /* [Q][N] deviations */
+  real* rel;     /* [Q][N] relaxed values f_rel(x, t) of the last step, before propagation */
+  real* Bt;      /* [3][N] B(x, t) before the last step (MHD) */
   /* records of the last executed step */
   real wf[MAXG][3][3]; /* per group: raw, momentum-flux correction, Maxwell correction */
   real M_t, P_t[3], rho_a[3];
@@ -146,6 +148,8 @@ orc* orc_create(int lattice, int nx, int ny, int nz, double tau, double dx, doub
   o->solid = (unsigned char*)calloc(o->N, 1);
   o->d = (real*)calloc((size_t)o->Q * o->N, sizeof(real));
   o->dn = (real*)calloc((size_t)o->Q * o->N, sizeof(real));
+  o->rel = (real*)calloc((size_t)o->Q * o->N, sizeof(real));
+  o->Bt = (real*)calloc((size_t)3 * o->N, sizeof(real));
   return o;
 }
 
@@ -154,6 +158,8 @@ void orc_destroy(orc* o) {
   free(o->solid);
   free(o->d);
   free(o->dn);
+  free(o->rel);
+  free(o->Bt);
   free(o->afield);
   free(o->g);
   free(o->gn);
@@ -524,6 +530,9 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
   }
   node_t s;
   node_relax(o, dl, idx, o->mhd ? Bn : NULL, NULL, &s, drel);
+  /* kept for the half-step distribution of Eq. (27) */
+  for (int q = 0; q < Q; ++q) o->rel[(long)q * N + idx] = drel[q];
+  for (int k = 0; k < 3; ++k) o->Bt[(long)k * N + idx] = s.B[k];
 
   /* balance partials at time t (Eq. 32): mass, momentum, body force */
   real* pb = part + o->G * 9;
@@ -818,6 +827,69 @@ int orc_force_balance(const orc* o, double* out) {
   out[21] = RE(M1);
   out[22] = o->have_step ? RE(M1 - o->M_t) : 0;
   out[23] = (double)o->step;
+  return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Half-step distribution (Section 4, Eqs. 27-28)
+ * ---------------------------------------------------------------------------
+ * fbar = (f_rel(x, t) + f(x, t + dt)) / 2 of the last step (Eq. 27), as a
+ * deviation from w rho0; its density, velocity and the stress of Eq. (28):
+ *   sigma_bar_ij = -sum_a e_ai e_aj fbar_a + Mbar^eq_ij,
+ *   Mbar^eq_ij = pbar delta_ij + rhobar ubar_i ubar_j (+ L_ij(Bbar) under MHD),
+ * pbar = rhobar c^2 / 3, Bbar = (B(t) + B(t + dt)) / 2 (the induction
+ * distributions interpolated the same way; relaxation conserves B).
+ * Any output may be NULL; solid nodes read 0.  -1 before the first step. */
+int orc_halfstep(const orc* o, double* fbar, double* rho_bar, double* u_bar, double* sigma_bar) {
+  if (!o->have_step) return -1;
+  const int D = o->D, Q = o->Q;
+  const long N = o->N;
+  const double c = o->c, c2 = c * c;
+  const int nc = D == 2 ? 3 : 6;
+  const int (*comp)[2] = D == 2 ? comp2 : comp3;
+  for (long i = 0; i < N; ++i) {
+    real db[19];
+    for (int q = 0; q < Q; ++q) db[q] = o->solid[i] ? 0 : 0.5 * (o->rel[(long)q * N + i] + o->d[(long)q * N + i]);
+    if (fbar)
+      for (int q = 0; q < Q; ++q) fbar[(long)q * N + i] = RE(db[q]);
+    if (o->solid[i]) {
+      if (rho_bar) rho_bar[i] = 0;
+      if (u_bar)
+        for (int k = 0; k < D; ++k) u_bar[(long)k * N + i] = 0;
+      if (sigma_bar)
+        for (int m = 0; m < nc; ++m) sigma_bar[(long)m * N + i] = 0;
+      continue;
+    }
+    real drho = 0, j[3] = {0, 0, 0};
+    for (int q = 0; q < Q; ++q) {
+      drho += db[q];
+      for (int k = 0; k < D; ++k) j[k] += (real)(c * o->e[q][k]) * db[q];
+    }
+    real rho = o->rho0 + drho, u[3] = {0, 0, 0};
+    for (int k = 0; k < D; ++k) u[k] = j[k] / rho;
+    if (rho_bar) rho_bar[i] = RE(rho);
+    if (u_bar)
+      for (int k = 0; k < D; ++k) u_bar[(long)k * N + i] = RE(u[k]);
+    if (sigma_bar) {
+      real B[3] = {0, 0, 0};
+      if (o->mhd) {
+        real Bn[3];
+        node_B(o, i, Bn);
+        for (int k = 0; k < 3; ++k) B[k] = 0.5 * (o->Bt[(long)k * N + i] + Bn[k]);
+      }
+      for (int m = 0; m < nc; ++m) {
+        const int a = comp[m][0], b = comp[m][1];
+        /* -sum e_a e_b fbar with fbar = d_bar + w rho0: the w rho0 part gives
+         * -rho0 c^2/3 delta_ab */
+        real mom = 0;
+        for (int q = 0; q < Q; ++q) mom += (real)(c2 * o->e[q][a] * o->e[q][b]) * db[q];
+        real meq = (a == b ? rho * c2 / 3.0 : 0.0) + rho * u[a] * u[b];
+        if (o->mhd) meq += maxwell(o, a, b, B);
+        real val = -(mom + (a == b ? o->rho0 * c2 / 3.0 : 0.0)) + meq;
+        sigma_bar[(long)m * N + i] = RE(val);
+      }
+    }
+  }
   return 0;
 }
 
