@@ -156,6 +156,22 @@ int lbm_get_field_B(lbm_ctx* ctx, double* B);
  * buffers [ncomp][nz][ny][nx]; either may be NULL.  Solid nodes read 0. */
 int lbm_stress(lbm_ctx* ctx, double* sigma, double* strain);
 
+/* Half-step distribution of the last step (Section 4, Eq. 27):
+ * f_bar = (f_rel(x, t) + f(x, t + dt)) / 2, the relaxed value before
+ * propagation averaged with the propagated one, and its moments: density
+ * rho_bar = sum f_bar, velocity u_bar = sum e f_bar / rho_bar, and the stress
+ * of Eq. (28), sigma_bar = -sum e e f_bar + Mbar^eq with
+ * Mbar^eq = p_bar I + rho_bar u_bar u_bar (+ the Maxwell stress of
+ * B_bar = (B(t) + B(t + dt)) / 2 under MHD), p_bar = rho_bar c^2 / 3.  At a
+ * steady state sigma_bar equals the Eq. (9) stress up to the force term's
+ * second moment (Eq. 30).  Caller-owned host buffers: fbar [Q][nz][ny][nx] as
+ * f_bar - w rho0, rho_bar [nz][ny][nx], u_bar [D][nz][ny][nx] (physical),
+ * sigma_bar [ncomp][nz][ny][nx] (physical, component order of lbm_stress); any
+ * may be NULL; solid nodes read 0.  LBM_ESTATE unless a step has been taken
+ * since the state was last set.  The wall velocities of the last step are
+ * used, even if they have been changed since. */
+int lbm_halfstep(lbm_ctx* ctx, double* fbar, double* rho_bar, double* u_bar, double* sigma_bar);
+
 /* Momentum-exchange force on the walls of each group during the last step
  * (Eq. 25, the populations leaving at t and returning at t + dt, per link
  * (dx^D / dt)(e_out f_out - e_in f_in)).  out [G][4][3], G = lbm_num_groups:

@@ -565,6 +565,141 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
 // ---------------------------------------------------------------------------
 // initial state / upload
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// half-step distribution of the last step (Section 4, Eqs. 27-28)
+// ---------------------------------------------------------------------------
+// f_bar = (f_rel(x, t) + f(x, t + dt)) / 2.  f(t + dt) is the current state.
+// f_rel(x, t) is read back from where the last step put it: in a node's own
+// opposite slot after an even step (next parity odd), at the neighbour
+// x + e after an odd step; a bounce-back link's value came back to the node
+// with the moving-wall term added, which is removed again.  That term needs
+// rho(x, t), recovered from mass conservation of the relaxation:
+// rho = rho0 + sum_a f_rel_a = rho0 + sum_a V_a + rho K, with V the values as
+// read and K = sum over wall links of 6 w (e.u_w).  Induction distributions
+// likewise (anti-bounce-back: the stored value is the negated relaxed one).
+template <class L, int P, bool MHD, int PAR>
+__global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
+  using S = Stor<P>;
+  using E = typename S::E;
+  using TS = typename S::T;
+  const Geom& g = a.geo;
+  const uint32_t n = blockIdx.x * NTHREADS + threadIdx.x;
+  if (n >= g.N) return;
+  uint32_t x, y, z, r;
+  coords(g, n, x, y, z, r);
+  const AddrG Af = addr_g(g, x, y, z, r, L::Q);
+  const AddrG Ag = addr_g(g, x, y, z, r, 21);
+  const int rr = a.rowrec[r];
+  const uint4 rec = rr >= 0 ? a.rec[rr + x] : make_uint4(0u, 0u, 0u, 0u);
+  const uint32_t mask = rec.x;
+  const bool solid = mask >> 31;
+  double db[L::Q];
+  double Bh[3] = {0.0, 0.0, 0.0};  // (B(t) + B(t + dt)) / 2 - B0
+  if (!solid) {
+    TS d1[L::Q];
+    read_f<L, P, PAR, true>((const E*)a.f, Af, mask, a.p, d1);
+    double V[L::Q];
+    double sV = 0.0, K = 0.0;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const bool wall = q > 0 && ((mask >> q) & 1u);
+      const E* ptr = (PAR == 1 || wall) ? Af.template ptr<L>((const E*)a.f, opp(q), -1)
+                                        : Af.template ptr<L>((const E*)a.f, q, q);
+      double v = (double)S::ld(ptr);
+      if (P == S_F16 || P == S_BF16) v *= (double)a.p.inv_scale[q];
+      V[q] = v;
+      sV += v;
+      if (wall) {
+        const uint32_t gr = nibble(rec, q);
+        K += 6.0 * L::w(q) * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
+      }
+    }
+    const double rho_t = (a.p.rho0 + sV) / (1.0 - K);
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      double rel = V[q];
+      if (q > 0 && ((mask >> q) & 1u)) {
+        const uint32_t gr = nibble(rec, q);
+        rel += 6.0 * L::w(q) * rho_t * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
+      }
+      db[q] = 0.5 * (rel + (double)d1[q]);
+    }
+    if (MHD) {
+      TS h1[7][3];
+      read_g<P, PAR, true>((const E*)a.g, Ag, mask, h1);
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const bool wall = k > 0 && ((mask >> k) & 1u);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const E* ptr = (PAR == 1 || wall) ? Ag.template ptr<D3Q19>((const E*)a.g, 3 * opp(k) + i, -1)
+                                            : Ag.template ptr<D3Q19>((const E*)a.g, 3 * k + i, k);
+          double hr = (double)S::ld(ptr);
+          if (wall) hr = -hr;
+          Bh[i] += 0.5 * (hr + (double)h1[k][i]);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) db[q] = 0.0;
+  }
+  if (a.fbar) {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      double v = db[q];
+      if (MHD && !solid) v += mhd_phi0<L>(q, a.p);  // back to f - w rho0
+      a.fbar[(uint64_t)q * g.N + n] = v;
+    }
+  }
+  double srho = 0.0, j[3] = {0.0, 0.0, 0.0};
+  double m2[6] = {0, 0, 0, 0, 0, 0};  // sum e e d_bar: xx, yy, zz, xy, xz, yz
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const double v = db[q];
+    const int ex = L::ex(q), ey = L::ey(q), ez = L::ez(q);
+    srho += v;
+    j[0] += ex * v;
+    j[1] += ey * v;
+    j[2] += ez * v;
+    m2[0] += ex * ex * v;
+    m2[1] += ey * ey * v;
+    m2[2] += ez * ez * v;
+    m2[3] += ex * ey * v;
+    m2[4] += ex * ez * v;
+    m2[5] += ey * ez * v;
+  }
+  const double rho = a.p.rho0 + srho;
+  const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+  if (a.rho) a.rho[n] = solid ? 0.0 : rho;
+  if (a.vel) {
+#pragma unroll
+    for (int k = 0; k < L::D; ++k) a.vel[(uint64_t)k * g.N + n] = solid ? 0.0 : u[k] * a.c;
+  }
+  if (a.sigma) {
+    // -sum e e f_bar + p_bar delta + rho_bar u u (+ L(B_bar)); the stored
+    // deviations exclude w rho0 (and phi(B0), whose second moment is L(B0))
+    const int ci[6] = {0, 1, 2, 0, 0, 1}, cj[6] = {0, 1, 2, 1, 2, 2};
+    double sg[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int i = ci[c], k = cj[c];
+      double v = -m2[c] + (i == k ? srho / 3.0 : 0.0) + rho * u[i] * u[k];
+      if (MHD) {
+        // L(b) - L(b0) with b = b0 + Bh, L_ij = b^2 delta_ij / 2 - b_i b_j
+        const double* b0 = a.p.b0;
+        const double bs[3] = {2.0 * b0[0] + Bh[0], 2.0 * b0[1] + Bh[1], 2.0 * b0[2] + Bh[2]};  // b + b0
+        const double b2h = 0.5 * (Bh[0] * bs[0] + Bh[1] * bs[1] + Bh[2] * bs[2]);
+        v += (i == k ? b2h : 0.0) - 0.5 * (Bh[i] * bs[k] + bs[i] * Bh[k]);
+      }
+      sg[c] = solid ? 0.0 : v * a.c * a.c;
+    }
+    const int map2[3] = {0, 3, 1};
+#pragma unroll
+    for (int c = 0; c < L::NC; ++c) a.sigma[(uint64_t)c * g.N + n] = sg[L::D == 2 ? map2[c] : c];
+  }
+}
+
 template <class L, int P, bool MHD>
 __global__ __launch_bounds__(NTHREADS) void k_init(const InitArgs a) {
   using S = Stor<P>;
@@ -698,6 +833,16 @@ static hipError_t launch_diag_t(const DiagArgs& a, hipStream_t st) {
 }
 
 template <class L, int P, bool MHD>
+static hipError_t launch_half_t(const HalfArgs& a, hipStream_t st) {
+  const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
+  if (a.parity == 0)
+    k_half<L, P, MHD, 0><<<nb, NTHREADS, 0, st>>>(a);
+  else
+    k_half<L, P, MHD, 1><<<nb, NTHREADS, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+template <class L, int P, bool MHD>
 static hipError_t launch_init_t(const InitArgs& a, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
   k_init<L, P, MHD><<<nb, NTHREADS, 0, st>>>(a);
@@ -739,6 +884,10 @@ hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity,
 
 hipError_t launch_diag(int lattice, int prec, bool mhd, const DiagArgs& a, hipStream_t st) {
   LBM_DISPATCH(launch_diag_t, lattice, prec, mhd, a, st);
+}
+
+hipError_t launch_half(int lattice, int prec, bool mhd, const HalfArgs& a, hipStream_t st) {
+  LBM_DISPATCH(launch_half_t, lattice, prec, mhd, a, st);
 }
 
 hipError_t launch_init(int lattice, int prec, bool mhd, const InitArgs& a, hipStream_t st) {

@@ -91,6 +91,23 @@ struct DiagArgs {
   double area;                 // dx^(D-1)
 };
 
+// Half-step distribution of the last step (Section 4, Eq. 27).
+struct HalfArgs {
+  const void* f;        // state at t + dt, in the layout the next step reads
+  const void* g;
+  const uint4* rec;
+  const int* rowrec;
+  double* fbar;         // [Q][N] f_bar - w rho0, or null
+  double* rho;          // [N] or null
+  double* vel;          // [D][N] u_bar (physical), or null
+  double* sigma;        // [NC][N] -sum e e f_bar + Mbar^eq (physical), or null
+  double uw[MAXG][3];   // wall velocities / c of the last step
+  Geom geo;
+  Phys p;
+  int parity;           // parity of the next step
+  double c;
+};
+
 // Initial-state / upload kernel arguments.
 struct InitArgs {
   void* f;

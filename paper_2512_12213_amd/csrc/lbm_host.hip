@@ -21,6 +21,7 @@ hipError_t launch_init(int lattice, int prec, bool mhd, const InitArgs& a, hipSt
 hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t ntiles, int mode, int nout, double* out,
                          hipStream_t st);
 hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, hipStream_t st);
+hipError_t launch_half(int lattice, int prec, bool mhd, const HalfArgs& a, hipStream_t st);
 hipError_t launch_adj(int lattice, int prec, int adj_prec, const AdjArgs& a, int parity, bool seed, hipStream_t st);
 }  // namespace lbm
 
@@ -742,6 +743,40 @@ int lbm_stress(lbm_ctx* h, double* sigma, double* strain) {
   if (rc) return rc;
   if (sigma) HIPCHK(hipMemcpyAsync(sigma, base, nc * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   if (strain) HIPCHK(hipMemcpyAsync(strain, base + nc * N, nc * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_halfstep(lbm_ctx* h, double* fbar, double* rho_bar, double* u_bar, double* sigma_bar) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!h->have_step) return fail(LBM_ESTATE, "no step taken since the state was set");
+  const size_t N = h->N, Q = h->Q, D = h->D, nc = h->NC;
+  const size_t total = (fbar ? Q : 0) + (rho_bar ? 1 : 0) + (u_bar ? D : 0) + (sigma_bar ? nc : 0);
+  if (!total) return LBM_OK;
+  HIPCHK(h->tmp.ensure(total * N * sizeof(double)));
+  HalfArgs a = {};
+  a.f = h->f.p;
+  a.g = h->mhd ? h->g.p : nullptr;
+  a.rec = (const uint4*)h->rec.p;
+  a.rowrec = (const int*)h->rowrec.p;
+  double* base = (double*)h->tmp.p;
+  size_t off = 0;
+  if (fbar) { a.fbar = base + off; off += Q * N; }
+  if (rho_bar) { a.rho = base + off; off += N; }
+  if (u_bar) { a.vel = base + off; off += D * N; }
+  if (sigma_bar) { a.sigma = base + off; off += nc * N; }
+  for (int gr = 0; gr < MAXG; ++gr)
+    for (int k = 0; k < 3; ++k) a.uw[gr][k] = h->last_uw[gr][k] / h->c;
+  a.geo = make_geom(h);
+  a.p = make_phys(h);
+  a.parity = h->parity;
+  a.c = h->c;
+  HIPCHK(launch_half(h->lattice, h->prec, h->mhd, a, h->stream));
+  if (fbar) HIPCHK(hipMemcpyAsync(fbar, a.fbar, Q * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (rho_bar) HIPCHK(hipMemcpyAsync(rho_bar, a.rho, N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (u_bar) HIPCHK(hipMemcpyAsync(u_bar, a.vel, D * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (sigma_bar) HIPCHK(hipMemcpyAsync(sigma_bar, a.sigma, nc * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return LBM_OK;
 }

@@ -45,6 +45,7 @@ _SIGS = [
     ("lbm_get_macro", C.c_int, [_P, _D, _D]),
     ("lbm_get_field_B", C.c_int, [_P, _D]),
     ("lbm_stress", C.c_int, [_P, _D, _D]),
+    ("lbm_halfstep", C.c_int, [_P, _D, _D, _D, _D]),
     ("lbm_wall_force", C.c_int, [_P, _D]),
     ("lbm_force_balance", C.c_int, [_P, _D]),
     ("lbm_num_groups", C.c_int, [_P]),
@@ -223,6 +224,17 @@ class Lattice:
         S = np.empty_like(sig)
         _chk(self.L.lbm_stress(self.h, _dp(sig), _dp(S)))
         return sig, S
+
+    def halfstep(self):
+        """Half-step distribution of the last step (Eq. 27) and its moments:
+        (fbar [Q, ...] deviations, rho_bar, u_bar [D, ...], sigma_bar [ncomp, ...])."""
+        sh = (self.nz, self.ny, self.nx)
+        fb = np.empty((self.Q,) + sh)
+        rb = np.empty(sh)
+        ub = np.empty((self.D,) + sh)
+        sb = np.empty((self.NC,) + sh)
+        _chk(self.L.lbm_halfstep(self.h, _dp(fb), _dp(rb), _dp(ub), _dp(sb)))
+        return fb, rb, ub, sb
 
     def num_groups(self):
         return _chk(self.L.lbm_num_groups(self.h))
