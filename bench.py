@@ -141,13 +141,13 @@ def timed_run(lbm, torch, w, steps, warmup, storage=None):
     }
 
 
-def adjoint_run(lbm, torch, W, adj_prec, repeats=3):
+def adjoint_run(lbm, torch, W, adj_prec, K=40, repeats=3):
     """Differentiable duct with a sphere (128x64x64, r = 8, tau 0.55, per-node
     Guo force field, 400 steps, checkpoints every 40, FP32): recorded forward
     and full checkpointed backward (segment recompute + adjoint steps),
     timed with events around the calls; best of `repeats`."""
     w = W.duct_sphere()
-    T, K = w.steps, 40
+    T = w.steps
     a0 = W.force_field(w.nx, w.ny, w.nz, base=w.body_force, amp=0.3, seed=16)
     af = torch.from_numpy(a0.astype(np.float32)).cuda()
     ga = torch.empty_like(af)
@@ -177,9 +177,9 @@ def adjoint_run(lbm, torch, W, adj_prec, repeats=3):
     # reverse bytes per node and step: recompute (2 Q 4 + 4 x 4 rho/U written + 12 field)
     # + adjoint (2 Q s_adj + 4 x 4 read + 12 field + 2 x 12 gradient read-modify-write)
     s_adj = 8 if adj_prec == W.F64 else 4
-    rbytes = (2 * 19 * 4 + 16 + 12) + (2 * 19 * s_adj + 16 + 12 + 24)
+    rbytes = (2 * 19 * 4 + 16 + 12 if K else 0) + (2 * 19 * s_adj + 16 + 12 + 24)
     return {
-        "workload": "duct_sphere_d3q19_128x64x64_r8_T400_ckpt40_f32",
+        "workload": "duct_sphere_d3q19_128x64x64_r8_T400_%s_f32" % ("ckpt%d" % K if K else "tape"),
         "adjoint_state": "f64" if adj_prec == W.F64 else "f32",
         "J": J,
         "dJ_duw_x": float(gu[1, 0]),
@@ -321,6 +321,7 @@ def main():
         print("bench: adjoint (differentiable duct with sphere)", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_run(lbm, torch, W, W.F64)
         out["adjoint_f32_state"] = adjoint_run(lbm, torch, W, W.F32)
+        out["adjoint_tape"] = adjoint_run(lbm, torch, W, W.F64, K=0)
     if not args.no_cpu:
         print("bench: CPU reference baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)

@@ -208,7 +208,10 @@ long lbm_steps_taken(lbm_ctx* ctx);
 /* Record a differentiable run: from the current state, advance T >= 1 steps
  * exactly as lbm_step(T) does, keeping a device copy of the state every
  * ckpt_every >= 1 steps (ceil(T / ckpt_every) copies of Q N values, owned by
- * the context), and return in *J the objective: component `axis` (0 = x,
+ * the context; the backward pass recomputes each segment), or, with
+ * ckpt_every = 0, recording density and velocity of every step instead
+ * (T x 4 N values; no recompute in the backward pass), and return in *J the
+ * objective: component `axis` (0 = x,
  * 1 = y, 2 = z; < D) of the raw Eq. (25) force on wall group `group` during
  * the last step, i.e. lbm_wall_force variant 0.  Needs LBM_F32 or LBM_F64
  * storage, no MHD and no Smagorinsky closure (LBM_EINVAL otherwise).  The run
@@ -220,12 +223,14 @@ int lbm_adjoint_forward(lbm_ctx* ctx, int T, int ckpt_every, int group, int axis
 /* Gradient of gJ * J for the recorded run, by the adjoint of every step in
  * reverse order: each checkpoint segment is first recomputed forward (also
  * recording density and velocity per node and step), then its adjoint steps
- * run backwards.  grad_a_dev: device buffer [3][nz][ny][nx], float
+ * run backwards (with ckpt_every = 0 the recorded densities and velocities
+ * are used directly).  grad_a_dev: device buffer [3][nz][ny][nx], float
  * (grad_f64 = 0) or double (grad_f64 = 1), overwritten with gJ dJ/da per
  * node in physical units (the z plane is 0 in 2D), or NULL.  grad_uw: host
  * buffer [G][3], G = lbm_num_groups, overwritten with gJ dJ/du_w per wall
- * group (physical units), or NULL.  Work buffers (two state copies and
- * min(ckpt_every, T) x 4 N values) are allocated on first use and kept.  The
+ * group (physical units), or NULL.  Work buffers (with checkpoints: two
+ * state copies and min(ckpt_every, T) x 4 N values; one state copy without)
+ * are allocated on first use and kept.  The
  * context's state is not changed and the run stays recorded.  LBM_ESTATE
  * without a recorded run.  The recompute runs in the storage precision, the
  * adjoint steps in the adjoint precision (lbm_set_adjoint_precision). */

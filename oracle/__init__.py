@@ -43,6 +43,8 @@ def _lib(complex_step: bool):
         lib.orc_set_body_force.argtypes = [P, dp, dp]
         lib.orc_set_body_force_field.argtypes = [P, dp, dp]
         lib.orc_set_les.argtypes = [P, C.c_double]
+        lib.orc_set_equilibrium.argtypes = [P, C.c_int]
+        lib.orc_set_darcy.argtypes = [P, C.c_double]
         lib.orc_set_artefact.argtypes = [P, C.c_int]
         lib.orc_set_mhd.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
         lib.orc_init_equilibrium.argtypes = [P, dp]
@@ -136,6 +138,12 @@ class Oracle:
 
     def set_les(self, cs):
         self._chk(self.lib.orc_set_les(self.h, cs))
+
+    def set_equilibrium(self, stokes):
+        self._chk(self.lib.orc_set_equilibrium(self.h, int(stokes)))
+
+    def set_darcy(self, sigma):
+        self._chk(self.lib.orc_set_darcy(self.h, sigma))
 
     def set_artefact(self, on):
         self._chk(self.lib.orc_set_artefact(self.h, int(on)))

@@ -66,6 +66,8 @@ struct orc {
   real a[3];
   real* afield; /* [3][N] or NULL */
   double cs;
+  int stokes;   /* 1: equilibrium without the quadratic velocity terms (text after Eq. 11) */
+  double darcy; /* porous resistance sigma: body force -sigma v added to a (Brinkman) */
   int artefact;
   int mhd;
   double B0[3], mu, tau_m;
@@ -232,6 +234,17 @@ int orc_set_les(orc* o, double cs) {
   return 0;
 }
 
+int orc_set_equilibrium(orc* o, int stokes) {
+  o->stokes = stokes ? 1 : 0;
+  return 0;
+}
+
+int orc_set_darcy(orc* o, double sigma) {
+  if (!(sigma >= 0)) return -1;
+  o->darcy = sigma;
+  return 0;
+}
+
 int orc_set_artefact(orc* o, int on) {
   o->artefact = on ? 1 : 0;
   return 0;
@@ -261,10 +274,13 @@ static real edot(const orc* o, int q, const real* v) {
   return s;
 }
 
-/* Equilibrium of Eq. (1), as a deviation from w*rho0; drho = rho - rho0. */
+/* Equilibrium of Eq. (1), as a deviation from w*rho0; drho = rho - rho0.
+ * The Stokes form (text after Eq. 11) keeps only the linear term
+ * rho w [1 + 3 e.u / c^2]. */
 static real feq_dev(const orc* o, int q, real rho, real drho, const real* u) {
   const double c2 = o->c * o->c;
   real eu = edot(o, q, u);
+  if (o->stokes) return o->w[q] * (drho + rho * 3.0 * eu / c2);
   real uu = 0;
   for (int k = 0; k < o->D; ++k) uu += u[k] * u[k];
   return o->w[q] * (drho + rho * (3.0 * eu / c2 + 4.5 * eu * eu / (c2 * c2) - 1.5 * uu / c2));
@@ -323,6 +339,9 @@ static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, c
   for (int k = 0; k < 3; ++k) {
     s->u[k] = k < D ? j[k] / rho : 0;
     s->a[k] = k < D ? (a_node ? a_node[k] : body_force(o, idx, k)) : 0;
+    /* porous resistance -sigma v with v = u + dt a / 2, a including it:
+     * a = (a_ext - sigma u) / (1 + sigma dt / 2) */
+    if (o->darcy > 0) s->a[k] = (s->a[k] - o->darcy * s->u[k]) / (1.0 + 0.5 * o->darcy * dt);
     s->v[k] = s->u[k] + 0.5 * dt * s->a[k]; /* v = u + dt a / 2 for all models */
     s->B[k] = Bn ? Bn[k] : 0;
   }
@@ -342,7 +361,7 @@ static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, c
     for (int k = 0; k < D; ++k) {
       real m = 0;
       for (int q = 0; q < Q; ++q) m += (real)(c2 * o->e[q][i] * o->e[q][k]) * dl[q];
-      real eqm = (i == k ? drho * c2 / 3.0 : 0.0) + rho * s->ueq[i] * s->ueq[k];
+      real eqm = (i == k ? drho * c2 / 3.0 : 0.0) + (o->stokes ? 0.0 : rho * s->ueq[i] * s->ueq[k]);
       if (o->mhd) eqm += maxwell(o, i, k, s->B);
       s->Pi[i][k] = m - eqm;
     }
@@ -399,7 +418,10 @@ static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, c
     for (int k = 0; k < D; ++k) {
       real th = 0;
       for (int q = 0; q < Q; ++q) th += (real)(c2 * o->e[q][i] * o->e[q][k]) * s->F[q];
-      s->E[i][k] = s->tau * dt * (s->ueq[i] * rho * s->a[k] + s->ueq[k] * rho * s->a[i]) - s->tau * th;
+      /* with the Stokes equilibrium M^eq has no rho u u part, whose time
+       * derivative gives the u^eq a terms */
+      real ua = o->stokes ? 0.0 : s->tau * dt * (s->ueq[i] * rho * s->a[k] + s->ueq[k] * rho * s->a[i]);
+      s->E[i][k] = ua - s->tau * th;
     }
 }
 
@@ -883,7 +905,7 @@ int orc_halfstep(const orc* o, double* fbar, double* rho_bar, double* u_bar, dou
          * -rho0 c^2/3 delta_ab */
         real mom = 0;
         for (int q = 0; q < Q; ++q) mom += (real)(c2 * o->e[q][a] * o->e[q][b]) * db[q];
-        real meq = (a == b ? rho * c2 / 3.0 : 0.0) + rho * u[a] * u[b];
+        real meq = (a == b ? rho * c2 / 3.0 : 0.0) + (o->stokes ? 0.0 : rho * u[a] * u[b]);
         if (o->mhd) meq += maxwell(o, a, b, B);
         real val = -(mom + (a == b ? o->rho0 * c2 / 3.0 : 0.0)) + meq;
         sigma_bar[(long)m * N + i] = RE(val);

@@ -804,21 +804,26 @@ static hipError_t launch_step_t(const StepArgs& a, int parity, bool diag, hipStr
 }
 
 // Forward step that also records rho and U of the pre-step state (adjoint
-// recompute): F32 / F64 storage, no MHD, no diagnostics.
+// recompute, or the recorded run's tape): F32 / F64 storage, no MHD.
 template <class L, int P>
-static hipError_t launch_step_mac_t(const StepArgs& a, int parity, hipStream_t st) {
+static hipError_t launch_step_mac_t(const StepArgs& a, int parity, bool diag, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
-  if (a.geo.nx % 64 == 0) {
-    if (parity == 0)
-      k_step<L, P, false, 0, false, true, true><<<nb, NTHREADS, 0, st>>>(a);
-    else
-      k_step<L, P, false, 1, false, true, true><<<nb, NTHREADS, 0, st>>>(a);
+  const bool ru = a.geo.nx % 64 == 0;
+#define LBM_MAC(PAR, DG, RU) k_step<L, P, false, PAR, DG, RU, true><<<nb, NTHREADS, 0, st>>>(a)
+  if (ru) {
+    if (parity == 0) {
+      if (diag) LBM_MAC(0, true, true); else LBM_MAC(0, false, true);
+    } else {
+      if (diag) LBM_MAC(1, true, true); else LBM_MAC(1, false, true);
+    }
   } else {
-    if (parity == 0)
-      k_step<L, P, false, 0, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
-    else
-      k_step<L, P, false, 1, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
+    if (parity == 0) {
+      if (diag) LBM_MAC(0, true, false); else LBM_MAC(0, false, false);
+    } else {
+      if (diag) LBM_MAC(1, true, false); else LBM_MAC(1, false, false);
+    }
   }
+#undef LBM_MAC
   return hipGetLastError();
 }
 
@@ -875,11 +880,13 @@ hipError_t launch_step(int lattice, int prec, bool mhd, const StepArgs& a, int p
   LBM_DISPATCH(launch_step_t, lattice, prec, mhd, a, parity, diag, st);
 }
 
-hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, hipStream_t st) {
+hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, bool diag, hipStream_t st) {
   if (prec != S_F32 && prec != S_F64) return hipErrorInvalidValue;
   if (lattice == 0)
-    return prec == S_F64 ? launch_step_mac_t<D2Q9, S_F64>(a, parity, st) : launch_step_mac_t<D2Q9, S_F32>(a, parity, st);
-  return prec == S_F64 ? launch_step_mac_t<D3Q19, S_F64>(a, parity, st) : launch_step_mac_t<D3Q19, S_F32>(a, parity, st);
+    return prec == S_F64 ? launch_step_mac_t<D2Q9, S_F64>(a, parity, diag, st)
+                         : launch_step_mac_t<D2Q9, S_F32>(a, parity, diag, st);
+  return prec == S_F64 ? launch_step_mac_t<D3Q19, S_F64>(a, parity, diag, st)
+                       : launch_step_mac_t<D3Q19, S_F32>(a, parity, diag, st);
 }
 
 hipError_t launch_diag(int lattice, int prec, bool mhd, const DiagArgs& a, hipStream_t st) {

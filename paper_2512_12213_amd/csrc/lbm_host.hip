@@ -20,7 +20,7 @@ hipError_t launch_diag(int lattice, int prec, bool mhd, const DiagArgs& a, hipSt
 hipError_t launch_init(int lattice, int prec, bool mhd, const InitArgs& a, hipStream_t st);
 hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t ntiles, int mode, int nout, double* out,
                          hipStream_t st);
-hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, hipStream_t st);
+hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, bool diag, hipStream_t st);
 hipError_t launch_half(int lattice, int prec, bool mhd, const HalfArgs& a, hipStream_t st);
 hipError_t launch_adj(int lattice, int prec, int adj_prec, const AdjArgs& a, int parity, bool seed, hipStream_t st);
 }  // namespace lbm
@@ -625,11 +625,13 @@ static int upload_uw(lbm_ctx* h) {
 
 // n >= 1 steps; the last one with diagnostics.  With ckpt_every > 0 the state
 // before step i is copied to checkpoint i / ckpt_every whenever
-// i % ckpt_every == 0.
-static int step_loop(lbm_ctx* h, int n, int ckpt_every) {
+// i % ckpt_every == 0; with a tape, every step also records rho and U of its
+// pre-step state at tape + i * 4 N values.
+static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
   int rc = upload_uw(h);
   if (rc) return rc;
   StepArgs a = step_args(h);
+  const size_t mbytes = (size_t)4 * h->N * elem_bytes(h->prec);
   const size_t sbytes = (size_t)h->Q * h->N * elem_bytes(h->prec);
   if (h->timing) {
     while (h->ev.size() < (size_t)n + 2) {
@@ -645,7 +647,12 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every) {
       HIPCHK(hipMemcpyAsync((char*)h->ckpt.p + (size_t)(i / ckpt_every) * sbytes, h->f.p, sbytes,
                             hipMemcpyDeviceToDevice, h->stream));
     const bool diag = i == n - 1;
-    HIPCHK(launch_step(h->lattice, h->prec, h->mhd, a, h->parity, diag, h->stream));
+    if (tape) {
+      a.mac = (char*)tape + (size_t)i * mbytes;
+      HIPCHK(launch_step_mac(h->lattice, h->prec, a, h->parity, diag, h->stream));
+    } else {
+      HIPCHK(launch_step(h->lattice, h->prec, h->mhd, a, h->parity, diag, h->stream));
+    }
     if (h->timing) HIPCHK(hipEventRecord(h->ev[i + 1], h->stream));
     h->parity ^= 1;
   }
@@ -916,16 +923,21 @@ int lbm_adjoint_forward(lbm_ctx* h, int T, int ckpt_every, int group, int axis, 
   rc = adjoint_supported(h);
   if (rc) return rc;
   if (T < 1) return fail(LBM_EINVAL, "T must be >= 1");
-  if (ckpt_every < 1) return fail(LBM_EINVAL, "ckpt_every must be >= 1");
+  if (ckpt_every < 0) return fail(LBM_EINVAL, "ckpt_every must be >= 0");
   if (group < 0 || group >= h->G) return fail(LBM_EINVAL, "group %d is not a wall group in use", group);
   if (axis < 0 || axis >= h->D) return fail(LBM_EINVAL, "axis %d out of range", axis);
   if (!J) return fail(LBM_EINVAL, "null J");
-  const int nseg = (T + ckpt_every - 1) / ckpt_every;
-  const size_t sbytes = (size_t)h->Q * h->N * elem_bytes(h->prec);
-  HIPCHK(h->ckpt.ensure((size_t)nseg * sbytes));
   h->tape = false;
   const int par0 = h->parity;
-  rc = step_loop(h, T, ckpt_every);
+  if (ckpt_every > 0) {
+    const int nseg = (T + ckpt_every - 1) / ckpt_every;
+    const size_t sbytes = (size_t)h->Q * h->N * elem_bytes(h->prec);
+    HIPCHK(h->ckpt.ensure((size_t)nseg * sbytes));
+    rc = step_loop(h, T, ckpt_every);
+  } else {
+    HIPCHK(h->mac.ensure((size_t)T * 4 * h->N * elem_bytes(h->prec)));
+    rc = step_loop(h, T, 0, h->mac.p);
+  }
   if (rc) return rc;
   double v[4][3];
   wall_variants(h, group, v);
@@ -945,14 +957,16 @@ int lbm_adjoint_backward(lbm_ctx* h, double gJ, void* grad_a_dev, int grad_f64, 
   if (!h->tape) return fail(LBM_ESTATE, "no recorded run: call lbm_adjoint_forward first (set-up changes and steps discard it)");
   if (!std::isfinite(gJ)) return fail(LBM_EINVAL, "non-finite gJ");
   const int T = h->tape_T, K = h->tape_K;
-  const int nseg = (T + K - 1) / K;
+  const int nseg = K > 0 ? (T + K - 1) / K : 1;
   const size_t eb = elem_bytes(h->prec);
   const size_t sbytes = (size_t)h->Q * h->N * eb;
   const size_t mbytes = (size_t)4 * h->N * eb;
   const int ap = h->prec == S_F64 ? S_F64 : h->adj_prec;
-  HIPCHK(h->replay.ensure(sbytes));
+  if (K > 0) {
+    HIPCHK(h->replay.ensure(sbytes));
+    HIPCHK(h->mac.ensure((size_t)std::min(K, T) * mbytes));
+  }
   HIPCHK(h->lam.ensure((size_t)h->Q * h->N * elem_bytes(ap)));
-  HIPCHK(h->mac.ensure((size_t)std::min(K, T) * mbytes));
   HIPCHK(h->adjpart.ensure((size_t)h->ntiles * NPART * sizeof(double)));
   HIPCHK(h->adjred.ensure((NBAL + MAXG * NWALL) * sizeof(double)));
   rc = upload_uw(h);
@@ -979,13 +993,15 @@ int lbm_adjoint_backward(lbm_ctx* h, double gJ, void* grad_a_dev, int grad_f64, 
   aa.geo = sa.geo;
   aa.p = sa.p;
   for (int seg = nseg - 1; seg >= 0; --seg) {
-    const int t0 = seg * K, t1 = std::min(T, t0 + K);
-    // recompute the segment from its checkpoint, recording rho and U
-    HIPCHK(hipMemcpyAsync(h->replay.p, (char*)h->ckpt.p + (size_t)seg * sbytes, sbytes, hipMemcpyDeviceToDevice,
-                          h->stream));
-    for (int t = t0; t < t1; ++t) {
-      sa.mac = (char*)h->mac.p + (size_t)(t - t0) * mbytes;
-      HIPCHK(launch_step_mac(h->lattice, h->prec, sa, (h->tape_par0 + t) & 1, h->stream));
+    const int t0 = K > 0 ? seg * K : 0, t1 = K > 0 ? std::min(T, t0 + K) : T;
+    if (K > 0) {
+      // recompute the segment from its checkpoint, recording rho and U
+      HIPCHK(hipMemcpyAsync(h->replay.p, (char*)h->ckpt.p + (size_t)seg * sbytes, sbytes, hipMemcpyDeviceToDevice,
+                            h->stream));
+      for (int t = t0; t < t1; ++t) {
+        sa.mac = (char*)h->mac.p + (size_t)(t - t0) * mbytes;
+        HIPCHK(launch_step_mac(h->lattice, h->prec, sa, (h->tape_par0 + t) & 1, false, h->stream));
+      }
     }
     // then reverse its steps
     for (int t = t1 - 1; t >= t0; --t) {

@@ -26,12 +26,14 @@ def lattice(name):
     return np.array(es), np.array(ws)
 
 
-def channel_recurrence(ny, tau, a, steps, uw=0.0):
+def channel_recurrence(ny, tau, a, steps, uw=0.0, darcy=0.0):
     """Exact evolution of a body-force-driven D2Q9 channel (lattice units,
     halfway bounce-back walls across y, periodic x, start from rest).
 
     For a flow that is uniform along x with rho = 1, only the class sums
-    m_s = sum_{e_y = s} e_x f (s = +1, 0, -1) matter and v = m_+ + m_0 + m_- + a/2.
+    m_s = sum_{e_y = s} e_x f (s = +1, 0, -1) matter; u = m_+ + m_0 + m_-.
+    The body force may include a porous resistance -darcy v with
+    v = u + a/2, which gives a = (a_ext - darcy u) / (1 + darcy / 2).
     BGK collision with any of the five force models gives, written in v,
         m*_(+-1) = (1 - 1/tau) m_(+-1) + v / (6 tau) + C a / 6,
         m*_0     = (1 - 1/tau) m_0     + 2 v / (3 tau) + 2 C a / 3,
@@ -45,10 +47,12 @@ def channel_recurrence(ny, tau, a, steps, uw=0.0):
     mm = np.zeros(ny)
     C = 1.0 - 1.0 / (2.0 * tau)
     for _ in range(steps):
-        v = mp + m0 + mm + 0.5 * a
-        sp = (1 - 1 / tau) * mp + v / (6 * tau) + C * a / 6
-        s0 = (1 - 1 / tau) * m0 + 2 * v / (3 * tau) + 2 * C * a / 3
-        sm = (1 - 1 / tau) * mm + v / (6 * tau) + C * a / 6
+        u = mp + m0 + mm
+        ae = (a - darcy * u) / (1.0 + 0.5 * darcy)
+        v = u + 0.5 * ae
+        sp = (1 - 1 / tau) * mp + v / (6 * tau) + C * ae / 6
+        s0 = (1 - 1 / tau) * m0 + 2 * v / (3 * tau) + 2 * C * ae / 3
+        sm = (1 - 1 / tau) * mm + v / (6 * tau) + C * ae / 6
         mp2 = np.empty(ny)
         mm2 = np.empty(ny)
         mp2[1:] = sp[:-1]
@@ -56,7 +60,9 @@ def channel_recurrence(ny, tau, a, steps, uw=0.0):
         mp2[0] = -sm[0]
         mm2[-1] = -sp[-1] + uw / 3.0
         mp, m0, mm = mp2, s0, mm2
-    return mp + m0 + mm + 0.5 * a
+    u = mp + m0 + mm
+    ae = (a - darcy * u) / (1.0 + 0.5 * darcy)
+    return u + 0.5 * ae
 
 
 def node_positions(n, dx):
@@ -129,3 +135,12 @@ def channel_bottom_force_recurrence(ny, tau, a_rows, steps, uw=0.0):
         mm2[-1] = -sp[-1] + uw / 3.0
         mp, m0, mm = mp2, s0, mm2
     return F
+
+
+def brinkman_channel(n, nu, sigma, a):
+    """Steady channel of width n (lattice units) with walls at y = +-n/2 and a
+    uniform porous resistance sigma: nu u'' - sigma u + a = 0, u(+-n/2) = 0,
+    u = (a / sigma) [1 - cosh(y / L) / cosh(n / (2 L))], L = sqrt(nu / sigma)."""
+    y = node_positions(n, 1.0)
+    L = np.sqrt(nu / sigma)
+    return a / sigma * (1.0 - np.cosh(y / L) / np.cosh(0.5 * n / L))

@@ -110,8 +110,10 @@ def test_couette_cylinder_adjoint_vs_oracle_all_models(env, model):
     check(J, ga, gu, Jo, gao, guo, W.F64, 3, "couette m%d" % model)
 
 
-@pytest.mark.parametrize("K", [1, 5, 17])
+@pytest.mark.parametrize("K", [0, 1, 5, 17])
 def test_checkpoint_interval_does_not_change_the_gradient(env, K):
+    """K = 0 records density and velocity of every step instead of
+    checkpoints (no recompute)."""
     w = W.duct_sphere(nx=64, ny=16, nz=16, r=3.0, uw=0.01, a=1e-4)
     a0 = W.force_field(w.nx, w.ny, w.nz, base=w.body_force, amp=0.3, seed=13)
     say("case checkpoint interval", K)
