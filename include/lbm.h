@@ -46,6 +46,9 @@ enum { LBM_FORCE_HE = 0, LBM_FORCE_LUO = 1, LBM_FORCE_SHANCHEN = 2, LBM_FORCE_ED
 /* Storage precision of the distributions (arithmetic is FP32 for the
  * reduced formats, FP64 for LBM_F64). */
 enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3 };
+/* Equilibrium form: Eq. (1), or the Stokes form rho w [1 + 3 e.u^eq / c^2]
+ * (text after Eq. 11: M^eq = c^2 rho I / 3, no convection term). */
+enum { LBM_EQ_NS = 0, LBM_EQ_STOKES = 1 };
 enum { LBM_OK = 0, LBM_EINVAL = -1, LBM_ENOMEM = -2, LBM_EHIP = -3, LBM_ESTATE = -4, LBM_EUNSTABLE = -5 };
 enum { LBM_MAX_GROUPS = 16, LBM_NREC = 24 };
 
@@ -99,6 +102,18 @@ int lbm_set_body_force_field(lbm_ctx* ctx, const void* dev_ptr);
 /* Smagorinsky constant C_s >= 0 for the eddy viscosity built from the
  * strain rate of Eq. (9); 0 disables it. */
 int lbm_set_les(lbm_ctx* ctx, double cs);
+
+/* Equilibrium form, LBM_EQ_NS (default) or LBM_EQ_STOKES.  Set-up only.
+ * With the Stokes form the stress of Eq. (9) and the half-step stress use
+ * M^eq = p I, and the artefact term loses its u^eq a part. */
+int lbm_set_equilibrium(lbm_ctx* ctx, int kind);
+
+/* Porous resistance (Brinkman; text after Eq. 11): the body force becomes
+ * a - sigma v with v = u + dt a / 2 the velocity of Section 2, i.e. each node
+ * applies (a - sigma u) / (1 + sigma dt / 2).  sigma >= 0 in 1/time (nu / K
+ * for permeability K); 0 disables it.  May change between steps; wall forces,
+ * the balance record and the adjoint include it. */
+int lbm_set_darcy(lbm_ctx* ctx, double sigma);
 
 /* Include the artefact term E_ij of Eq. (9) in the stress and strain
  * outputs (0 = off, the default).  Any time. */

@@ -23,6 +23,9 @@
 //   G_ue = nu rho (3 m1 + 9 m2 ue - 3 ue m0),  G_uF = C rho (9 m2 A - 3 A m0)
 //   U-cotangent    M_U = G_ue + kF G_uF
 //   A-cotangent    g_A = lEq G_ue + lF G_uF + C rho (3 m1 - 3 uF m0 + 9 m2 uF)
+// (the quadratic terms carry the factor quad, 0 for the Stokes equilibrium; a
+// porous resistance A = (A_ext - s U) / (1 + s/2) adds -s/(1 + s/2) g_A to
+// M_U and scales the external force's cotangent by 1/(1 + s/2))
 //   lambda_p = (1 - nu) mu_p + M_rho + M_U.(e_p - U) / rho
 // and the wall velocity of a link's group gets mu_q (-6 w_q rho e_q).  rho
 // and U of the forward state come from the recompute pass (4 values per node
@@ -89,6 +92,11 @@ __device__ __forceinline__ void adj_node(const AdjArgs& a, uint32_t n, const AD&
     A[1] = (T)p.A[1];
     A[2] = (T)p.A[2];
   }
+  // porous resistance: the force the node applies is A = (A_ext - s U) di
+  const T ds = (T)p.darcy_s, di = (T)p.darcy_inv;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) A[k] = (A[k] - ds * U[k]) * di;
+  const T quad = (T)p.quad;
   const T nu = (T)p.inv_tau0;
   const T lEq = (T)p.lEq, kF = (T)p.kF;
   const T lF = (T)(p.lF0 + p.lF1 * p.tau0);
@@ -134,16 +142,19 @@ __device__ __forceinline__ void adj_node(const AdjArgs& a, uint32_t n, const AD&
   const T ueue = ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2];
   const T ufA = uf[0] * A[0] + uf[1] * A[1] + uf[2] * A[2];
 
-  T Mrho = nu * (m0 + T(3) * m1ue + T(4.5) * uem2ue - T(1.5) * ueue * m0) +
+  T Mrho = nu * (m0 + T(3) * m1ue + quad * (T(4.5) * uem2ue - T(1.5) * ueue * m0)) +
            C * (T(3) * m1A - T(3) * ufA * m0 + T(9) * ufm2A);
   T MU[3], gA[3];
   const T nr = nu * rho, cr = C * rho;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const T Gue = nr * (T(3) * m1[k] + T(9) * m2ue[k] - T(3) * ue[k] * m0);
+    const T Gue = nr * (T(3) * m1[k] + quad * (T(9) * m2ue[k] - T(3) * ue[k] * m0));
     const T Guf = cr * (T(9) * m2A[k] - T(3) * A[k] * m0);
-    MU[k] = Gue + kF * Guf;
-    gA[k] = lEq * Gue + lF * Guf + cr * (T(3) * m1[k] - T(3) * uf[k] * m0 + T(9) * m2uf[k]);
+    // cotangent of the applied force, then through A = (A_ext - s U) di:
+    // to U (-s di) and to the external force (di)
+    const T gAt = lEq * Gue + lF * Guf + cr * (T(3) * m1[k] - T(3) * uf[k] * m0 + T(9) * m2uf[k]);
+    MU[k] = Gue + kF * Guf - ds * di * gAt;
+    gA[k] = di * gAt;
   }
 
   // moving-wall terms of the bounce-back links: -6 w_q rho (e_q . u_w)

@@ -72,9 +72,12 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
   m.U[0] = jx * m.irho;
   m.U[1] = jy * m.irho;
   m.U[2] = jz * m.irho;
-  m.A[0] = Ax;
-  m.A[1] = Ay;
-  m.A[2] = Az;
+  // porous resistance -sigma v, v = U + A / 2 with A including it:
+  // A = (A_ext - sigma dt U) / (1 + sigma dt / 2) (exactly A_ext without it)
+  const T ds = (T)p.darcy_s, di = (T)p.darcy_inv;
+  m.A[0] = (Ax - ds * m.U[0]) * di;
+  m.A[1] = (Ay - ds * m.U[1]) * di;
+  m.A[2] = (Az - ds * m.U[2]) * di;
   const T lEq = (T)p.lEq;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -101,7 +104,7 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
       if (L::ey(q) * L::ez(q) < 0) syz -= ps[k];
     }
     const T third = drho * T(1.0 / 3.0);
-    const T rho = m.rho;
+    const T rho = m.rho * (T)p.quad;  // the Stokes equilibrium has no rho u u part
     m.pi[0] = sxx - third - rho * m.Ue[0] * m.Ue[0];
     m.pi[1] = syy - third - rho * m.Ue[1] * m.Ue[1];
     m.pi[2] = L::D == 3 ? szz - third - rho * m.Ue[2] * m.Ue[2] : T(0);
@@ -172,6 +175,8 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
   const T cr = m.C * rho;
   const T itau = m.itau;
   const T rl = rho * lEq, rl2 = rho * lEq * lEq;
+  const T quad = (T)p.quad;  // 0 for the Stokes equilibrium
+  const T rq = rho * quad, rlq = rl * quad, rl2q = rl2 * quad;
   T bs[3] = {T(0), T(0), T(0)}, db2 = T(0);
   if (MHD) {
 #pragma unroll
@@ -186,12 +191,12 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
     const T ej = edot<L>(q, m.J[0], m.J[1], m.J[2]);
     const T ea = edot<L>(q, m.A[0], m.A[1], m.A[2]);
     // large part: w [drho + 3 e.j + rho (9/2 (e.u)^2 - 3/2 u.u)]
-    const T Rb = m.drho + T(3) * ej + rho * (T(4.5) * eu * eu - usq);
+    const T Rb = m.drho + T(3) * ej + rq * (T(4.5) * eu * eu - usq);
     const T neq = (w * Rb + wlo * Rb) - d[q];
     // small part: the u^eq shift
     //   rho [(e.ue)^2 9/2 - ue.ue 3/2] - (same at u) + 3 e.(rho lEq A),
     // and the magnetic term phi(b) - phi(b0)
-    T Rs = rl * (T(3) * ea + T(9) * eu * ea - T(3) * ua) + rl2 * (T(4.5) * ea * ea - T(1.5) * aa);
+    T Rs = rl * (T(3) * ea) + rlq * (T(9) * eu * ea - T(3) * ua) + rl2q * (T(4.5) * ea * ea - T(1.5) * aa);
     if (MHD) {
       // (e.b)^2 - (e.b0)^2 = (e.db)(e.(b + b0))
       const T edb = edot<L>(q, db[0], db[1], db[2]);
@@ -500,8 +505,9 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
           const int i = ci[c], j = cj[c];
+          // (no u^eq a part with the Stokes equilibrium, whose M^eq has no rho u u)
           Pn[c] += m.tau * m.rho *
-                   ((m.Ue[i] * m.A[j] + m.Ue[j] * m.A[i]) - thc * (m.UF[i] * m.A[j] + m.UF[j] * m.A[i]));
+                   ((T)a.p.quad * (m.Ue[i] * m.A[j] + m.Ue[j] * m.A[i]) - thc * (m.UF[i] * m.A[j] + m.UF[j] * m.A[i]));
         }
       }
       const double cS = -3.0 / (2.0 * (double)m.tau * a.dt * (double)m.rho);
@@ -684,7 +690,7 @@ __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       const int i = ci[c], k = cj[c];
-      double v = -m2[c] + (i == k ? srho / 3.0 : 0.0) + rho * u[i] * u[k];
+      double v = -m2[c] + (i == k ? srho / 3.0 : 0.0) + a.p.quad * rho * u[i] * u[k];
       if (MHD) {
         // L(b) - L(b0) with b = b0 + Bh, L_ij = b^2 delta_ij / 2 - b_i b_j
         const double* b0 = a.p.b0;
@@ -728,7 +734,7 @@ __global__ __launch_bounds__(NTHREADS) void k_init(const InitArgs a) {
         const double w = L::w(q);
         const double eu = edot<L>(q, U[0], U[1], U[2]);
         const double usq = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
-        v = w * a.p.rho0 * (3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+        v = w * a.p.rho0 * (3.0 * eu + a.p.quad * (4.5 * eu * eu - 1.5 * usq));
       }
     }
     T s = (T)v;

@@ -30,6 +30,9 @@ struct Phys {
   double afield_scale; // dt / c, applied to the per-node field a
   double kF, lF0, lF1, lEq, cG, thC;  // force-model table (see host)
   double les_K;        // 18 sqrt(2) C_s^2, 0 = no closure
+  double quad;         // 1: equilibrium of Eq. (1); 0: Stokes form (no quadratic velocity terms)
+  double darcy_s;      // porous resistance sigma dt (0 = none)
+  double darcy_inv;    // 1 / (1 + sigma dt / 2)
   double b0[3];        // MHD B0 / (c sqrt(mu))
   double inv_tau_m;
   float scale[19], inv_scale[19];  // storage scaling per direction

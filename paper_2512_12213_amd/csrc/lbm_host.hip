@@ -97,6 +97,8 @@ struct lbm_ctx {
   double a[3] = {0, 0, 0};
   const float* afield = nullptr;
   double cs = 0;
+  int stokes = 0;
+  double darcy = 0;
   int artefact = 0;
   bool mhd = false;
   double B0[3] = {0, 0, 0}, mu = 1, tau_m = 1;
@@ -150,6 +152,9 @@ Phys make_phys(const lbm_ctx* h) {
     default: p.kF = 1; p.lF0 = 0.5; p.lF1 = 0; p.lEq = 0.5; p.cG = 1; p.thC = 1; break;
   }
   p.les_K = 18.0 * std::sqrt(2.0) * h->cs * h->cs;
+  p.quad = h->stokes ? 0.0 : 1.0;
+  p.darcy_s = h->darcy * h->dt;
+  p.darcy_inv = 1.0 / (1.0 + 0.5 * h->darcy * h->dt);
   const double bs = h->mhd ? 1.0 / (h->c * std::sqrt(h->mu)) : 0.0;
   for (int k = 0; k < 3; ++k) p.b0[k] = h->B0[k] * bs;
   p.inv_tau_m = h->mhd ? 1.0 / h->tau_m : 0.0;
@@ -487,6 +492,22 @@ int lbm_set_les(lbm_ctx* h, double cs) {
   h->tape = false;
   if (!(cs >= 0) || !std::isfinite(cs)) return fail(LBM_EINVAL, "C_s must be >= 0");
   h->cs = cs;
+  return LBM_OK;
+}
+
+int lbm_set_equilibrium(lbm_ctx* h, int kind) {
+  int rc = setup_guard(h);
+  if (rc) return rc;
+  if (kind != LBM_EQ_NS && kind != LBM_EQ_STOKES) return fail(LBM_EINVAL, "unknown equilibrium %d", kind);
+  h->stokes = kind == LBM_EQ_STOKES;
+  return LBM_OK;
+}
+
+int lbm_set_darcy(lbm_ctx* h, double sigma) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (!(sigma >= 0) || !std::isfinite(sigma)) return fail(LBM_EINVAL, "sigma must be >= 0");
+  h->darcy = sigma;
+  h->tape = false;
   return LBM_OK;
 }
 

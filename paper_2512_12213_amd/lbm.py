@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_D2Q9, LBM_D3Q19 = 0, 1
 LBM_FORCE_HE, LBM_FORCE_LUO, LBM_FORCE_SHANCHEN, LBM_FORCE_EDM, LBM_FORCE_GUO = range(5)
 LBM_F64, LBM_F32, LBM_F16, LBM_BF16 = range(4)
+LBM_EQ_NS, LBM_EQ_STOKES = 0, 1
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_EUNSTABLE = 0, -1, -2, -3, -4, -5
 LBM_MAX_GROUPS, LBM_NREC = 16, 24
 
@@ -34,6 +35,8 @@ _SIGS = [
     ("lbm_set_body_force", C.c_int, [_P, C.c_double, C.c_double, C.c_double]),
     ("lbm_set_body_force_field", C.c_int, [_P, C.c_void_p]),
     ("lbm_set_les", C.c_int, [_P, C.c_double]),
+    ("lbm_set_equilibrium", C.c_int, [_P, C.c_int]),
+    ("lbm_set_darcy", C.c_int, [_P, C.c_double]),
     ("lbm_set_artefact", C.c_int, [_P, C.c_int]),
     ("lbm_set_mhd", C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]),
     ("lbm_set_stream", C.c_int, [_P, C.c_void_p]),
@@ -172,6 +175,12 @@ class Lattice:
     def set_les(self, cs):
         _chk(self.L.lbm_set_les(self.h, cs))
 
+    def set_equilibrium(self, kind):
+        _chk(self.L.lbm_set_equilibrium(self.h, kind))
+
+    def set_darcy(self, sigma):
+        _chk(self.L.lbm_set_darcy(self.h, sigma))
+
     def set_artefact(self, on):
         _chk(self.L.lbm_set_artefact(self.h, int(on)))
 
@@ -300,6 +309,10 @@ def from_workload(w, storage=None, u0=None, init=True):
     lat.set_body_force(list(w.body_force))
     if w.les_cs:
         lat.set_les(w.les_cs)
+    if w.stokes:
+        lat.set_equilibrium(LBM_EQ_STOKES)
+    if w.darcy:
+        lat.set_darcy(w.darcy)
     if w.mhd is not None:
         lat.set_mhd(w.mhd[:3], w.mhd[3], w.mhd[4])
     if init:

@@ -37,6 +37,8 @@ class Workload:
     walls: Tuple = ()                   # tuples (axis, group_lo, group_hi)
     wall_velocity: Tuple = ()           # tuples (group, ux, uy, uz)
     les_cs: float = 0.0
+    stokes: bool = False                # Stokes form of the equilibrium
+    darcy: float = 0.0                  # porous resistance sigma (1/time)
     mhd: Optional[Tuple] = None         # (B0x, B0y, B0z, mu, tau_m)
     obstacle: Optional[Tuple] = None    # ("cylinder", cx, cy, r, group) or ("sphere", cx, cy, cz, r, group)
     u0_amp: float = 0.0

@@ -18,6 +18,10 @@ def make_oracle(w: W.Workload, complex_step=False, u0=None, init=True):
     o.set_body_force(list(w.body_force))
     if w.les_cs:
         o.set_les(w.les_cs)
+    if w.stokes:
+        o.set_equilibrium(True)
+    if w.darcy:
+        o.set_darcy(w.darcy)
     if w.mhd is not None:
         o.set_mhd(w.mhd[:3], w.mhd[3], w.mhd[4])
     o.groups = max(o.groups, w.groups)

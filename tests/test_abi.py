@@ -46,7 +46,8 @@ def test_enum_values_match_header(lbm):
     src = open(HEADER).read()
     for name in ("LBM_D2Q9", "LBM_D3Q19", "LBM_FORCE_HE", "LBM_FORCE_LUO", "LBM_FORCE_SHANCHEN", "LBM_FORCE_EDM",
                  "LBM_FORCE_GUO", "LBM_F64", "LBM_F32", "LBM_F16", "LBM_BF16", "LBM_OK", "LBM_EINVAL",
-                 "LBM_ENOMEM", "LBM_EHIP", "LBM_ESTATE", "LBM_EUNSTABLE", "LBM_MAX_GROUPS", "LBM_NREC"):
+                 "LBM_ENOMEM", "LBM_EHIP", "LBM_ESTATE", "LBM_EUNSTABLE", "LBM_MAX_GROUPS", "LBM_NREC",
+                 "LBM_EQ_NS", "LBM_EQ_STOKES"):
         m = re.search(r"\b%s\s*=\s*(-?\d+)" % name, src)
         assert m, name
         assert getattr(lbm, name) == int(m.group(1)), name

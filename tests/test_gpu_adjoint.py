@@ -110,6 +110,17 @@ def test_couette_cylinder_adjoint_vs_oracle_all_models(env, model):
     check(J, ga, gu, Jo, gao, guo, W.F64, 3, "couette m%d" % model)
 
 
+@pytest.mark.parametrize("storage,adj", PRECS, ids=["f64", "f32_adj64", "f32_adj32"])
+def test_adjoint_with_stokes_equilibrium_and_darcy(env, storage, adj):
+    w = W.duct_sphere(nx=64, ny=20, nz=18, r=3.5, uw=0.01, a=1e-4)
+    w.stokes, w.darcy = True, 0.02
+    a0 = W.force_field(w.nx, w.ny, w.nz, base=w.body_force, amp=0.3, seed=18)
+    say("case adjoint stokes+darcy", storage, adj)
+    Jo, gao, guo = oracle_run(w, a0, 11, 4, 0)
+    J, ga, gu = gpu_run(env, w, a0, 11, 3, 4, 0, storage, adj=adj)
+    check(J, ga, gu, Jo, gao, guo, storage, 5, "stokes+darcy")
+
+
 @pytest.mark.parametrize("K", [0, 1, 5, 17])
 def test_checkpoint_interval_does_not_change_the_gradient(env, K):
     """K = 0 records density and velocity of every step instead of
@@ -162,7 +173,7 @@ def test_unsupported_configurations_are_rejected(env):
         lat.adjoint_forward(2, 1, 0, 0)
     lat.close()
     lat = L.from_workload(w)
-    for args in [(0, 1, 4, 0), (2, 0, 4, 0), (2, 1, 9, 0), (2, 1, 4, 3)]:
+    for args in [(0, 1, 4, 0), (2, -1, 4, 0), (2, 1, 9, 0), (2, 1, 4, 3)]:
         with pytest.raises(L.LBMError):
             lat.adjoint_forward(*args)
     with pytest.raises(L.LBMError):

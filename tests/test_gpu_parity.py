@@ -334,3 +334,43 @@ def test_halfstep_needs_a_step(lbm):
     with pytest.raises(lbm.LBMError) as ei:
         g.halfstep()
     assert ei.value.code == lbm.LBM_ESTATE
+
+
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+@pytest.mark.parametrize("model", [0, 2, 4])
+@pytest.mark.parametrize("lattice", [W.D2Q9, W.D3Q19])
+def test_stokes_equilibrium_and_darcy_resistance(lbm, lattice, model, storage):
+    """Two steps with the Stokes form of the equilibrium and a porous
+    resistance (text after Eq. 11), from a seeded state with walls, a moving
+    wall and a solid body; then the half-step stress."""
+    if lattice == W.D2Q9:
+        nx, ny, nz = 64, 19, 1
+        mask = W.cylinder_mask(nx, ny, 12.3, 9.1, 3.2)
+        walls = ((1, 0, 1),)
+    else:
+        nx, ny, nz = 21, 13, 11
+        mask = W.sphere_mask(nx, ny, nz, 9.4, 6.2, 5.1, 2.6)
+        walls = ((1, 0, 1), (2, 2, 3))
+    w = W.Workload("stokes", lattice, nx, ny, nz, 0.65, dx=0.5, dt=0.2, model=model, storage=storage,
+                   body_force=(0.05, -0.02, 0.03), walls=walls, wall_velocity=((1, 0.08, 0.0, 0.03),),
+                   stokes=True, darcy=0.7, groups=5)
+    Q = 9 if lattice == W.D2Q9 else 19
+    say("case stokes+darcy", lattice, model, storage)
+    d0 = W.random_state(Q, nx, ny, nz, 2e-3, seed=31) * (1 - mask[None])
+    g = gpu_from(w, lbm, init=False)
+    g.add_solid_mask(mask, 4)
+    g.set_state(d0)
+    o = make_oracle(w, init=False)
+    o.set_solid(mask, 4)
+    o.groups = 5
+    o.set_state(quantize_state(d0, storage))
+    for k in range(2):
+        g.step(1)
+        o.step(1)
+        assert rel_inf(g.get_state(), o.get_state()) <= TOL_FIELD[storage]
+        compare_all(g, o, storage, 5, "  step %d" % (k + 1))
+    _, _, _, sg = g.halfstep()
+    _, _, _, so = o.halfstep()
+    assert rel_inf(sg, so) <= TOL_STRESS[storage]
+    rg, ro = g.force_balance(), o.force_balance()
+    assert np.abs(rg[3:6] - ro[3:6]).max() <= TOL_WALL[storage] * np.abs(ro[3:6]).max()
