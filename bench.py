@@ -82,8 +82,9 @@ def W_obstacle_mask(w):
 
 
 def copy_ceiling(torch, nbytes, repeats=20):
-    """Device-to-device copy of nbytes / 2 bytes (nbytes moved: read + write),
-    the practical bandwidth ceiling for the step's traffic."""
+    """torch's device-to-device copy of nbytes / 2 bytes (nbytes moved: read +
+    write), for context: it is not a tuned copy (a plain float4 copy kernel
+    reaches about 6.2 TB/s on MI355X)."""
     n = nbytes // 2 // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -295,8 +296,7 @@ def main():
             "kernel": "lbm::k_step<D3Q19, F32, no MHD, parity, no diagnostics, row-uniform>",
             "bytes_per_launch": r["bytes_per_launch"],
             "launch_us": {k: round(v, 2) for k, v in r["launch_us"].items()},
-            "copy_ceiling_gbs": round(copy_gbs, 1),
-            "frac_of_copy": round(r["achieved_gbs"] / copy_gbs, 4),
+            "torch_copy_gbs": round(copy_gbs, 1),
         },
         "balance_residual_rel": r["balance_residual_rel"],
     }
