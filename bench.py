@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and workloads")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--only", choices=["adjoint", "hartmann"], default=None,
+                    help="run only this measurement (for profiling its kernels) and print its record")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a plain copy kernel of known size, "
                          "used to scale hardware byte counters)")
@@ -259,6 +261,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.only == "adjoint":
+        print(json.dumps({"adjoint": adjoint_run(lbm, torch, W, W.F64, repeats=1),
+                          "adjoint_tape": adjoint_run(lbm, torch, W, W.F64, K=0, repeats=1)}), flush=True)
+        return
+    if args.only == "hartmann":
+        rh = timed_run(lbm, torch, W.hartmann_duct(), args.steps, args.warmup)
+        print(json.dumps({"hartmann_duct_f32_192x96x96": rh}), flush=True)
+        return
 
     w = W.duct_les()
     print("bench: headline FP32 duct, warmup %d, timed %d steps" % (args.warmup, args.steps),
