@@ -45,6 +45,7 @@ def _lib(complex_step: bool):
         lib.orc_set_les.argtypes = [P, C.c_double]
         lib.orc_set_equilibrium.argtypes = [P, C.c_int]
         lib.orc_set_darcy.argtypes = [P, C.c_double]
+        lib.orc_set_link_fraction.argtypes = [P, dp]
         lib.orc_set_artefact.argtypes = [P, C.c_int]
         lib.orc_set_mhd.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
         lib.orc_init_equilibrium.argtypes = [P, dp]
@@ -144,6 +145,11 @@ class Oracle:
 
     def set_darcy(self, sigma):
         self._chk(self.lib.orc_set_darcy(self.h, sigma))
+
+    def set_link_fraction(self, q):
+        """q [Q, nz, ny, nx]: wall distance / link length of wall links (1/2 halfway), or None."""
+        q = _f64(q)
+        self._chk(self.lib.orc_set_link_fraction(self.h, _dp(q)))
 
     def set_artefact(self, on):
         self._chk(self.lib.orc_set_artefact(self.h, int(on)))

@@ -74,6 +74,8 @@ struct orc {
   real *g, *gn; /* induction distributions [7][3][N] */
   real *d, *dn; /* [Q][N] deviations */
   real* rel;     /* [Q][N] relaxed values f_rel(x, t) of the last step, before propagation */
+  real* rho_t;   /* [N] density of the last step's pre-step state */
+  double* qlink; /* [Q][N] wall distance / link length for wall links, or NULL (all 1/2) */
   real* Bt;      /* [3][N] B(x, t) before the last step (MHD) */
   /* records of the last executed step */
   real wf[MAXG][3][3]; /* per group: raw, momentum-flux correction, Maxwell correction */
@@ -152,6 +154,7 @@ orc* orc_create(int lattice, int nx, int ny, int nz, double tau, double dx, doub
   o->dn = (real*)calloc((size_t)o->Q * o->N, sizeof(real));
   o->rel = (real*)calloc((size_t)o->Q * o->N, sizeof(real));
   o->Bt = (real*)calloc((size_t)3 * o->N, sizeof(real));
+  o->rho_t = (real*)calloc((size_t)o->N, sizeof(real));
   return o;
 }
 
@@ -162,6 +165,8 @@ void orc_destroy(orc* o) {
   free(o->dn);
   free(o->rel);
   free(o->Bt);
+  free(o->rho_t);
+  free(o->qlink);
   free(o->afield);
   free(o->g);
   free(o->gn);
@@ -233,6 +238,25 @@ int orc_set_les(orc* o, double cs) {
   o->cs = cs;
   return 0;
 }
+
+/* Wall position per link for interpolated bounce-back: q[a][n] is the
+ * distance from fluid node n to the wall along link a, as a fraction of the
+ * link; 1/2 is the halfway wall.  Values of non-wall links are ignored. */
+int orc_set_link_fraction(orc* o, const double* q) {
+  if (!q) {
+    free(o->qlink);
+    o->qlink = NULL;
+    return 0;
+  }
+  if (!o->qlink) o->qlink = (double*)malloc(sizeof(double) * o->Q * o->N);
+  for (long i = 0; i < (long)o->Q * o->N; ++i) {
+    if (!(q[i] > 0.0 && q[i] <= 1.0)) return -1;
+    o->qlink[i] = q[i];
+  }
+  return 0;
+}
+
+static double link_fraction(const orc* o, int q, long idx) { return o->qlink ? o->qlink[(long)q * o->N + idx] : 0.5; }
 
 int orc_set_equilibrium(orc* o, int stokes) {
   o->stokes = stokes ? 1 : 0;
@@ -552,8 +576,10 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
   }
   node_t s;
   node_relax(o, dl, idx, o->mhd ? Bn : NULL, NULL, &s, drel);
-  /* kept for the half-step distribution of Eq. (27) */
+  /* kept for the half-step distribution of Eq. (27) and for interpolated
+   * bounce-back */
   for (int q = 0; q < Q; ++q) o->rel[(long)q * N + idx] = drel[q];
+  o->rho_t[idx] = s.rho;
   for (int k = 0; k < 3; ++k) o->Bt[(long)k * N + idx] = s.B[k];
 
   /* balance partials at time t (Eq. 32): mass, momentum, body force */
@@ -572,6 +598,9 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
       o->dn[(long)q * N + t] = drel[q];
       continue;
     }
+    /* a wall that is not halfway: bounce-back by interpolation after all
+     * nodes have relaxed (interpolated_bounce_back) */
+    if (link_fraction(o, q, idx) != 0.5) continue;
     const int qb = o->opp[q];
     real ladd = moving_wall_term(o, q, s.rho, o->uw[grp]);
     o->dn[(long)qb * N + idx] = drel[q] + ladd;
@@ -617,6 +646,62 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
   (void)D;
 }
 
+/* Linearly interpolated bounce-back (Bouzidi, Firdaouss and Lallemand 2001)
+ * for a wall at fraction qv of link a from fluid node x (a value of 1/2 is the
+ * halfway wall of Section 4, handled in update_node):
+ *   qv <  1/2: f_opp(a)(x, t+dt) = 2qv f_rel_a(x) + (1 - 2qv) f_rel_a(x - e_a)
+ *              (+ the moving-wall term), halfway bounce-back when x - e_a is
+ *              not a fluid node;
+ *   qv >= 1/2: f_opp(a)(x, t+dt) = f_rel_a(x) / (2qv) + (2qv - 1)/(2qv) f_rel_opp(a)(x)
+ *              (+ the moving-wall term / (2qv)).
+ * Deviations from w rho0 obey the same formulas (the weights sum to one).  The
+ * momentum exchange of Eq. (25) uses the values that leave and return at x,
+ * so its result is the stress at x + e_a dt / 2 (Section 4), not at the wall.
+ * Adds the links' wall-force contributions to tot (layout of part_size). */
+static void interpolated_bounce_back(orc* o, real* tot) {
+  const int Q = o->Q;
+  const long N = o->N;
+  const double c = o->c, dt = o->dt;
+  const double vol = o->lat == 0 ? o->dx * o->dx : o->dx * o->dx * o->dx;
+  for (int z = 0; z < o->nz; ++z)
+    for (int y = 0; y < o->ny; ++y)
+      for (int x = 0; x < o->nx; ++x) {
+        const long idx = ((long)z * o->ny + y) * o->nx + x;
+        if (o->solid[idx]) continue;
+        for (int q = 1; q < Q; ++q) {
+          long t;
+          int grp;
+          if (!link_target(o, x, y, z, o->e[q], &t, &grp)) continue;
+          const double qv = link_fraction(o, q, idx);
+          if (qv == 0.5) continue;
+          const int qb = o->opp[q];
+          const real rq = o->rel[(long)q * N + idx];
+          const real ladd = moving_wall_term(o, q, o->rho_t[idx], o->uw[grp]);
+          real din;
+          if (qv < 0.5) {
+            int back[3] = {-o->e[q][0], -o->e[q][1], -o->e[q][2]};
+            long tu;
+            int gu;
+            if (!link_target(o, x, y, z, back, &tu, &gu))
+              din = 2.0 * qv * rq + (1.0 - 2.0 * qv) * o->rel[(long)q * N + tu] + ladd;
+            else
+              din = rq + ladd;
+          } else {
+            din = rq / (2.0 * qv) + (2.0 * qv - 1.0) / (2.0 * qv) * o->rel[(long)qb * N + idx] + ladd / (2.0 * qv);
+          }
+          o->dn[(long)qb * N + idx] = din;
+          const real fout = rq + o->w[q] * o->rho0;
+          const real fin = din + o->w[q] * o->rho0;
+          real* pw = tot + grp * 9;
+          for (int k = 0; k < 3; ++k) {
+            double ek = c * o->e[q][k], ebk = c * o->e[qb][k];
+            pw[k] += vol / dt * (ek * fout - ebk * fin);
+            pw[3 + k] += -vol / dt * o->uw[grp][k] * (fout - fin);
+          }
+        }
+      }
+}
+
 int orc_step(orc* o, int n) {
   if (n < 0) return -1;
   const int P = part_size(o);
@@ -639,6 +724,7 @@ int orc_step(orc* o, int n) {
     memset(tot, 0, sizeof(tot));
     for (long r = 0; r < rows; ++r)
       for (int k = 0; k < P; ++k) tot[k] += part[r * P + k];
+    if (o->qlink) interpolated_bounce_back(o, tot);
     for (int gr = 0; gr < o->G; ++gr)
       for (int v = 0; v < 3; ++v)
         for (int k = 0; k < 3; ++k) o->wf[gr][v][k] = tot[gr * 9 + v * 3 + k];
@@ -933,7 +1019,7 @@ int orc_halfstep(const orc* o, double* fbar, double* rho_bar, double* u_bar, dou
  * All T pre-step states are kept (no checkpointing).  MHD is not supported. */
 #ifdef ORC_COMPLEX
 int orc_adjoint(orc* o, int T, int group, int axis, double* J, double* grad_a, double* grad_uw) {
-  if (T < 1 || o->mhd || group < 0 || group >= o->G || axis < 0 || axis >= o->D) return -1;
+  if (T < 1 || o->mhd || o->qlink || group < 0 || group >= o->G || axis < 0 || axis >= o->D) return -1;
   const int Q = o->Q, D = o->D, G = o->G;
   const long N = o->N;
   const long QN = (long)Q * N;

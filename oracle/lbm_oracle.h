@@ -49,7 +49,11 @@ int orc_set_body_force(orc* o, const double* a, const double* a_im);            
 int orc_set_body_force_field(orc* o, const double* a, const double* a_im);              /* [3][N] or NULL */
 int orc_set_les(orc* o, double cs);
 int orc_set_equilibrium(orc* o, int stokes);   /* 0: Eq. (1); 1: Stokes form (text after Eq. 11) */
-int orc_set_darcy(orc* o, double sigma);       /* porous resistance: adds -sigma v to the body force */
+int orc_set_darcy(orc* o, double sigma);
+/* Interpolated bounce-back: q [Q][N] = wall distance / link length per link
+ * (1/2 = halfway wall, values of non-wall links ignored), or NULL for all
+ * halfway.  -1 if a value is outside (0, 1]. */
+int orc_set_link_fraction(orc* o, const double* q);       /* porous resistance: adds -sigma v to the body force */
 int orc_set_artefact(orc* o, int on);
 int orc_set_mhd(orc* o, double B0x, double B0y, double B0z, double mu, double tau_m);
 

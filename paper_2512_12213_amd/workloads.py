@@ -117,6 +117,37 @@ def sphere_mask(nx, ny, nz, cx, cy, cz, r):
     return ((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 <= r * r).astype(np.uint8)
 
 
+def link_fractions_sphere(Q, nx, ny, nz, cx, cy, cz, r):
+    """[Q, nz, ny, nx] wall distance / link length for links from fluid nodes
+    into the solid ball (x - c)^2 <= r^2 (1/2 elsewhere): the smallest t in
+    (0, 1] with |x + t e - c| = r.  Two-dimensional lattices use nz = 1 and
+    the circle in the plane."""
+    if Q == 9:
+        e = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [1, 1, 0], [-1, -1, 0],
+                      [1, -1, 0], [-1, 1, 0]], float)
+    else:
+        e = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+                      [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1], [1, 0, -1],
+                      [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]], float)
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(float)
+    p = np.stack([x - cx, y - cy, (z - cz) if Q == 19 else 0.0 * z])
+    inside = (p ** 2).sum(0) <= r * r
+    q = np.full((Q, nz, ny, nx), 0.5)
+    for a in range(1, Q):
+        ea = e[a].reshape(3, 1, 1, 1)
+        # |p + t e|^2 = r^2: (e.e) t^2 + 2 (p.e) t + (p.p - r^2) = 0, smallest root
+        A = float((e[a] ** 2).sum())
+        B = 2.0 * (p * ea).sum(0)
+        Cc = (p ** 2).sum(0) - r * r
+        disc = np.maximum(B * B - 4 * A * Cc, 0.0)
+        t = (-B - np.sqrt(disc)) / (2 * A)
+        tgt = np.roll(inside, shift=(-int(e[a, 2]), -int(e[a, 1]), -int(e[a, 0])), axis=(0, 1, 2)) if Q == 19 else \
+            np.roll(inside, shift=(-int(e[a, 1]), -int(e[a, 0])), axis=(1, 2))
+        hit = (~inside) & tgt
+        q[a][hit] = np.clip(t[hit], 1e-6, 1.0)
+    return q
+
+
 def obstacle_mask(w: Workload):
     if w.obstacle is None:
         return None

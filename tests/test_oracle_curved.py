@@ -1,0 +1,120 @@
+"""Pins of the oracle's interpolated bounce-back (walls not halfway between
+nodes) and of the Section 4 statement that the momentum exchange of Eq. (25)
+then gives the stress at x_i = x_f + e dt / 2, not at the wall."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import make_oracle, rel_inf
+from paper_2512_12213_amd import workloads as W
+
+
+def channel(n, qv, tau=0.8, a=1e-6, steps=60000, uw=0.0, q_top=None):
+    o = oracle.Oracle(oracle.D2Q9, 1, n, 1, tau, 1.0, 1.0, oracle.GUO)
+    o.set_walls(1, 0, 1)
+    if uw:
+        o.set_wall_velocity(1, [uw, 0, 0])
+    q = np.full((9, 1, n, 1), 0.5)
+    q[:, 0, 0, 0] = qv
+    q[:, 0, n - 1, 0] = qv if q_top is None else q_top
+    o.set_link_fraction(q)
+    if a:
+        o.set_body_force([a, 0, 0])
+    o.init_equilibrium()
+    o.step(steps)
+    return o
+
+
+def test_halfway_fractions_change_nothing():
+    w = W.couette_cylinder(nx=40, ny=20, r=3.0, cx=12.0, cy=10.0)
+    o1 = make_oracle(w)
+    o2 = make_oracle(w)
+    o2.set_link_fraction(np.full((9, 1, w.ny, w.nx), 0.5))
+    o1.step(50)
+    o2.step(50)
+    assert np.array_equal(o1.get_state(), o2.get_state())
+    assert np.array_equal(o1.wall_force(3), o2.wall_force(3))
+
+
+@pytest.mark.parametrize("qv", [0.25, 0.7, 1.0])
+def test_offset_channel_profile_is_second_order(qv):
+    """Steady force-driven channel with walls a distance q from the end nodes:
+    the profile converges to the parabola between the true walls at second
+    order."""
+    errs = []
+    for n in (16, 32):
+        o = channel(n, qv)
+        _, v = o.get_macro()
+        nu = (0.8 - 0.5) / 3
+        y = np.arange(n, dtype=float)
+        ref = 1e-6 / (2 * nu) * (y + qv) * (n - 1 + qv - y)
+        errs.append(rel_inf(v[0, 0, :, 0], ref))
+    assert errs[1] < 3e-3
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+@pytest.mark.parametrize("qv", [0.25, 0.7, 1.0])
+def test_momentum_exchange_gives_the_stress_at_the_half_grid_point(qv):
+    """Section 4: with a wall that is not halfway, Eq. (25) still uses the
+    values leaving and returning at the fluid node, which trace back to the
+    point x_i half a link away; the force per area is the stress there, not
+    at the wall.  In the steady channel the Eq. (9) stress is linear across
+    the nodes: extrapolated to y_i = -dx/2 it equals the momentum exchange;
+    extrapolated to the wall y_w = -q dx it differs by rho a (q - 1/2) dx."""
+    n, a = 16, 1e-6
+    o = channel(n, qv, a=a)
+    fw = o.wall_force(2)
+    sig, _ = o.stress()
+    s = sig[1, 0, :, 0]
+    slope = s[1] - s[0]
+    s_i = s[0] - 0.5 * slope
+    s_w = s[0] - qv * slope
+    P = fw[0, 0, 0]  # force on the bottom wall per unit depth, one node wide
+    assert abs(P - a * n / 2) < 1e-12 * a * n
+    # inward normal +y on the bottom wall: P_x = sigma_xy there
+    assert abs(s_i - P) < 1e-9 * P
+    assert abs((s_w - P) - a * (qv - 0.5)) < 1e-9 * P
+    rec = o.force_balance()
+    assert abs(rec[0] / rec[3] - 1) < 1e-10
+
+
+def test_offset_couette_is_exact():
+    """Lid-driven channel with walls at arbitrary fractions: linear
+    interpolation reproduces the linear profile between the true walls, and
+    both walls carry rho nu U / H."""
+    n, tau, U = 16, 0.8, 0.02
+    for qb, qt in ((0.25, 0.8), (0.9, 0.3)):
+        o = channel(n, qb, tau=tau, a=0.0, steps=40000, uw=U, q_top=qt)
+        _, v = o.get_macro()
+        H = n - 1 + qb + qt
+        y = np.arange(n, dtype=float)
+        assert np.abs(v[0, 0, :, 0] - U * (y + qb) / H).max() < 1e-12 * U
+        fw = o.wall_force(2)
+        nu = (tau - 0.5) / 3
+        assert abs(fw[0, 0, 0] - nu * U / H) < 1e-10 * nu * U / H
+        assert abs(fw[1, 0, 0] + nu * U / H) < 1e-10 * nu * U / H
+
+
+def test_cylinder_with_geometric_fractions_balance():
+    """Cylinder with link fractions from the exact circle: Eq. (32) holds per
+    step (momentum exchange with the interpolated returning values)."""
+    w = W.couette_cylinder(nx=48, ny=24, r=4.3, cx=16.2, cy=11.7, uw=0.03, tau=0.7, a=2e-5)
+    o = make_oracle(w)
+    q = W.link_fractions_sphere(9, w.nx, w.ny, 1, 16.2, 11.7, 0.0, 4.3)
+    o.set_link_fraction(q)
+    o.step(400)
+    rec = o.force_balance()
+    assert np.abs(rec[9:12]).max() < 1e-12 * np.abs(rec[0:9]).max()
+    # the fractions are those of the circle: a link's wall point lies on it
+    assert ((q > 0) & (q <= 1)).all()
+
+
+def test_link_fractions_are_checked_and_adjoint_refuses_them():
+    o = oracle.Oracle(oracle.D2Q9, 4, 4, 1, 0.8, complex_step=True)
+    o.set_walls(1, 0, 1)
+    with pytest.raises(ValueError):
+        o.set_link_fraction(np.zeros((9, 1, 4, 4)))
+    o.set_link_fraction(np.full((9, 1, 4, 4), 0.3))
+    o.init_equilibrium()
+    with pytest.raises(ValueError):
+        o.adjoint(2, 0, 0)
