@@ -76,7 +76,7 @@ int lbm_set_rho0(lbm_ctx* ctx, double rho0);
 
 /* Halfway bounce-back plane walls half a spacing beyond the first and last
  * node along `axis` (0 = x, 1 = y, 2 = z); all nodes stay fluid
- * (Section 4, Eq. 25: wall a half grid away from the fluid node).  A group
+ * (Section 5, Eq. 25: wall a half grid away from the fluid node).  A group
  * is a label in [0, 16) under which wall forces are summed; -1 leaves that
  * end periodic.  A link crossing two walls (a corner) belongs to the
  * lower-numbered axis. */
@@ -85,6 +85,20 @@ int lbm_add_plane_walls(lbm_ctx* ctx, int axis, int group_lo, int group_hi);
 /* Solid nodes: mask_host [nz][ny][nx], nonzero = solid, links from fluid
  * nodes into them are halfway bounce-back links of `group`. */
 int lbm_add_solid_mask(lbm_ctx* ctx, const unsigned char* mask_host, int group);
+
+/* Walls that are not halfway between nodes (Section 5: the momentum exchange
+ * then gives the stress half a link from the fluid node, not at the wall).
+ * q_host [Q][nz][ny][nx]: for each fluid node and each link that ends in a
+ * wall or solid node, the distance to the wall as a fraction of the link, in
+ * (0, 1]; 1/2 keeps halfway bounce-back; entries of other links are ignored
+ * but must also lie in (0, 1]; NULL returns to halfway walls everywhere.
+ * Links with q != 1/2 are bounced back by linear interpolation (Bouzidi,
+ * Firdaouss and Lallemand 2001) in a pass after each step, with the
+ * moving-wall term: q < 1/2: 2q f_rel_a(x) + (1 - 2q) f_rel_a(x - e_a) (halfway
+ * when x - e_a is not fluid); q >= 1/2: [f_rel_a(x) + (2q - 1) f_rel_opp(a)(x)]
+ * / (2q).  The wall force uses the values that leave and return at the node.
+ * Not with MHD, lbm_halfstep or the adjoint (LBM_EINVAL).  Set-up only. */
+int lbm_set_link_fractions(lbm_ctx* ctx, const double* q_host);
 
 /* Wall velocity of a group (moving-wall bounce-back adds
  * 6 w rho (e.u_w)/c^2 to the returning population).  May change between
@@ -171,7 +185,7 @@ int lbm_get_field_B(lbm_ctx* ctx, double* B);
  * buffers [ncomp][nz][ny][nx]; either may be NULL.  Solid nodes read 0. */
 int lbm_stress(lbm_ctx* ctx, double* sigma, double* strain);
 
-/* Half-step distribution of the last step (Section 4, Eq. 27):
+/* Half-step distribution of the last step (Section 5, Eq. 27):
  * f_bar = (f_rel(x, t) + f(x, t + dt)) / 2, the relaxed value before
  * propagation averaged with the propagated one, and its moments: density
  * rho_bar = sum f_bar, velocity u_bar = sum e f_bar / rho_bar, and the stress

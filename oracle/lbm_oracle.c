@@ -648,7 +648,7 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
 
 /* Linearly interpolated bounce-back (Bouzidi, Firdaouss and Lallemand 2001)
  * for a wall at fraction qv of link a from fluid node x (a value of 1/2 is the
- * halfway wall of Section 4, handled in update_node):
+ * halfway wall of Section 5, handled in update_node):
  *   qv <  1/2: f_opp(a)(x, t+dt) = 2qv f_rel_a(x) + (1 - 2qv) f_rel_a(x - e_a)
  *              (+ the moving-wall term), halfway bounce-back when x - e_a is
  *              not a fluid node;
@@ -656,7 +656,7 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
  *              (+ the moving-wall term / (2qv)).
  * Deviations from w rho0 obey the same formulas (the weights sum to one).  The
  * momentum exchange of Eq. (25) uses the values that leave and return at x,
- * so its result is the stress at x + e_a dt / 2 (Section 4), not at the wall.
+ * so its result is the stress at x + e_a dt / 2 (Section 5), not at the wall.
  * Adds the links' wall-force contributions to tot (layout of part_size). */
 static void interpolated_bounce_back(orc* o, real* tot) {
   const int Q = o->Q;
@@ -939,7 +939,7 @@ int orc_force_balance(const orc* o, double* out) {
 }
 
 /* ---------------------------------------------------------------------------
- * Half-step distribution (Section 4, Eqs. 27-28)
+ * Half-step distribution (Section 5, Eqs. 27-28)
  * ---------------------------------------------------------------------------
  * fbar = (f_rel(x, t) + f(x, t + dt)) / 2 of the last step (Eq. 27), as a
  * deviation from w rho0; its density, velocity and the stress of Eq. (28):

@@ -75,7 +75,7 @@ int orc_wall_force(const orc* o, double* out, double* out_im, int G);
 int orc_force_balance(const orc* o, double* out);
 long orc_link_count(const orc* o, int group);
 
-/* Half-step distribution of the last step (Section 4, Eq. 27) and its moments:
+/* Half-step distribution of the last step (Section 5, Eq. 27) and its moments:
  * fbar [Q][N] = (f_rel(x,t) + f(x,t+dt))/2 - w rho0; rho_bar [N]; u_bar [D][N]
  * (sum e fbar / rho_bar); sigma_bar [ncomp][N] = -sum e e fbar + Mbar^eq (Eq. 28).
  * Any may be NULL.  -1 before the first step. */

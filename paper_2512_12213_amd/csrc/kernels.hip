@@ -572,7 +572,106 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
 // initial state / upload
 // ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
-// half-step distribution of the last step (Section 4, Eqs. 27-28)
+// interpolated bounce-back (walls that are not halfway between nodes)
+// ---------------------------------------------------------------------------
+// Run after a step on the nodes with such links.  The step itself returned
+// the halfway value f_rel_a(x) + ladd into the node's own slot for direction
+// opp(a); this replaces it with the linear interpolation of Bouzidi,
+// Firdaouss and Lallemand (2001) for a wall at fraction q of the link:
+//   q <  1/2: 2q f_rel_a(x) + (1 - 2q) f_rel_a(x - e_a) + ladd
+//             (f_rel_a(x - e_a) is the value that streamed into x along a;
+//             halfway when x - e_a is not a fluid node),
+//   q >= 1/2: [f_rel_a(x) + (2q - 1) f_rel_opp(a)(x) + ladd] / (2q).
+// f_rel(x, t) is read back as for the half-step distribution; the moving-wall
+// term ladd = -6 w rho(x, t) e_a.u_w needs rho(x, t), recovered by mass
+// conservation of the relaxation.  One thread per node: every slot it reads
+// belongs to links of its own node or to regular streamed values that no
+// other thread of this pass writes.
+template <class L, int P, int PAR>
+__global__ __launch_bounds__(NTHREADS) void k_ibb(const IbbArgs a) {
+  using S = Stor<P>;
+  using E = typename S::E;
+  using TS = typename S::T;
+  const Geom& g = a.geo;
+  const uint32_t i = blockIdx.x * NTHREADS + threadIdx.x;
+  if (i >= a.M) return;
+  const uint32_t n = a.node[i];
+  uint32_t x, y, z, r;
+  coords(g, n, x, y, z, r);
+  const AddrG Af = addr_g(g, x, y, z, r, L::Q);
+  const int rr = a.rowrec[r];
+  const uint4 rec = a.rec[rr + x];
+  const uint32_t mask = rec.x;
+  E* f = (E*)a.f;
+  TS d1[L::Q];
+  read_f<L, P, PAR, true>(f, Af, mask, a.p, d1);  // incoming values f(x, t + dt)
+  double V[L::Q];
+  double sV = 0.0, K = 0.0;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const bool wall = q > 0 && ((mask >> q) & 1u);
+    const E* ptr = (PAR == 1 || wall) ? Af.template ptr<L>((const E*)f, opp(q), -1) : Af.template ptr<L>((const E*)f, q, q);
+    double v = (double)S::ld(ptr);
+    if (P == S_F16 || P == S_BF16) v *= (double)a.p.inv_scale[q];
+    V[q] = v;
+    sV += v;
+    if (wall) {
+      const uint32_t gr = nibble(rec, q);
+      K += 6.0 * L::w(q) * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
+    }
+  }
+  const double rho_t = (a.p.rho0 + sV) / (1.0 - K);
+  double R[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    R[q] = V[q];
+    if (q > 0 && ((mask >> q) & 1u)) {
+      const uint32_t gr = nibble(rec, q);
+      R[q] += 6.0 * L::w(q) * rho_t * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
+    }
+  }
+#pragma unroll
+  for (int q = 1; q < L::Q; ++q) {
+    if (!((mask >> q) & 1u)) continue;
+    const double qv = a.qf[(uint64_t)i * L::Q + q];
+    double dnew = V[q];  // halfway value as the step returned it
+    if (qv != 0.5) {
+      const int qb = opp(q);
+      const uint32_t gr = nibble(rec, q);
+      const double ladd = -6.0 * L::w(q) * rho_t * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
+      if (qv < 0.5) {
+        if (!((mask >> qb) & 1u)) dnew = 2.0 * qv * R[q] + (1.0 - 2.0 * qv) * (double)d1[q] + ladd;
+      } else {
+        dnew = (R[q] + (2.0 * qv - 1.0) * R[qb] + ladd) / (2.0 * qv);
+      }
+      E* ptr = Af.template ptr<L>(f, qb, -1);
+      double sv = dnew;
+      if (P == S_F16 || P == S_BF16) sv *= (double)a.p.scale[q];
+      S::st(ptr, (TS)sv);
+    }
+    if (a.delta) a.delta[(uint64_t)i * L::Q + q] = dnew - V[q];
+  }
+}
+
+// Wall-force corrections of the interpolated links per group: out[g][k],
+// k < 3 the sum of e_k delta, k = 3 the sum of delta (block g * 4 + k).
+template <class L>
+__global__ __launch_bounds__(NTHREADS) void k_ibb_reduce(const double* __restrict__ delta, const uint8_t* __restrict__ grp,
+                                                         uint32_t M, double* __restrict__ out) {
+  const uint32_t gk = blockIdx.x, g = gk / 4, k = gk % 4;
+  double s = 0.0;
+  for (uint64_t e = threadIdx.x; e < (uint64_t)M * L::Q; e += NTHREADS) {
+    const int q = (int)(e % L::Q);
+    if (q == 0 || grp[e] != g) continue;
+    const int ek = k == 0 ? L::ex(q) : (k == 1 ? L::ey(q) : (k == 2 ? L::ez(q) : 1));
+    s += ek * delta[e];
+  }
+  double v[1] = {s};
+  tile_sum_store<1>(v, out + gk);
+}
+
+// ---------------------------------------------------------------------------
+// half-step distribution of the last step (Section 5, Eqs. 27-28)
 // ---------------------------------------------------------------------------
 // f_bar = (f_rel(x, t) + f(x, t + dt)) / 2.  f(t + dt) is the current state.
 // f_rel(x, t) is read back from where the last step put it: in a node's own
@@ -844,6 +943,16 @@ static hipError_t launch_diag_t(const DiagArgs& a, hipStream_t st) {
 }
 
 template <class L, int P, bool MHD>
+static hipError_t launch_ibb_t(const IbbArgs& a, hipStream_t st) {
+  const uint32_t nb = (a.M + NTHREADS - 1) / NTHREADS;
+  if (a.parity == 0)
+    k_ibb<L, P, 0><<<nb, NTHREADS, 0, st>>>(a);
+  else
+    k_ibb<L, P, 1><<<nb, NTHREADS, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+template <class L, int P, bool MHD>
 static hipError_t launch_half_t(const HalfArgs& a, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
   if (a.parity == 0)
@@ -901,6 +1010,20 @@ hipError_t launch_diag(int lattice, int prec, bool mhd, const DiagArgs& a, hipSt
 
 hipError_t launch_half(int lattice, int prec, bool mhd, const HalfArgs& a, hipStream_t st) {
   LBM_DISPATCH(launch_half_t, lattice, prec, mhd, a, st);
+}
+
+hipError_t launch_ibb(int lattice, int prec, const IbbArgs& a, hipStream_t st) {
+  if (a.M == 0) return hipSuccess;
+  LBM_DISPATCH(launch_ibb_t, lattice, prec, false, a, st);
+}
+
+hipError_t launch_ibb_reduce(int lattice, const double* delta, const uint8_t* grp, uint32_t M, int G, double* out,
+                             hipStream_t st) {
+  if (lattice == 0)
+    k_ibb_reduce<D2Q9><<<G * 4, NTHREADS, 0, st>>>(delta, grp, M, out);
+  else
+    k_ibb_reduce<D3Q19><<<G * 4, NTHREADS, 0, st>>>(delta, grp, M, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_init(int lattice, int prec, bool mhd, const InitArgs& a, hipStream_t st) {

@@ -94,7 +94,24 @@ struct DiagArgs {
   double area;                 // dx^(D-1)
 };
 
-// Half-step distribution of the last step (Section 4, Eq. 27).
+// Interpolated bounce-back after a step, for walls that are not halfway: one
+// entry per fluid node with such links.
+struct IbbArgs {
+  void* f;                 // state at t + dt, in the layout the next step reads
+  const uint32_t* node;    // [M] node index
+  const double* qf;        // [M][Q] wall distance / link length (1/2: halfway, left as is)
+  const uint8_t* grp;      // [M][Q] wall group of each link
+  double* delta;           // [M][Q] change of the returning value (diagnostic steps), or null
+  const uint4* rec;
+  const int* rowrec;
+  double uw[MAXG][3];      // wall velocities / c of the step
+  uint32_t M;
+  Geom geo;
+  Phys p;
+  int parity;              // parity of the next step
+};
+
+// Half-step distribution of the last step (Section 5, Eq. 27).
 struct HalfArgs {
   const void* f;        // state at t + dt, in the layout the next step reads
   const void* g;

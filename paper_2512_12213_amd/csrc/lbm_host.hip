@@ -22,6 +22,9 @@ hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t nt
                          hipStream_t st);
 hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, bool diag, hipStream_t st);
 hipError_t launch_half(int lattice, int prec, bool mhd, const HalfArgs& a, hipStream_t st);
+hipError_t launch_ibb(int lattice, int prec, const IbbArgs& a, hipStream_t st);
+hipError_t launch_ibb_reduce(int lattice, const double* delta, const uint8_t* grp, uint32_t M, int G, double* out,
+                             hipStream_t st);
 hipError_t launch_adj(int lattice, int prec, int adj_prec, const AdjArgs& a, int parity, bool seed, hipStream_t st);
 }  // namespace lbm
 
@@ -113,6 +116,11 @@ struct lbm_ctx {
   std::vector<long> nlink;  // [MAXG][Q]
 
   DevBuf f, g, rec, rowrec, blkgrp, uwdev, part, red, dpart, dred, tmp;
+  // walls that are not halfway: link fractions (host, [Q][N]) and the list of
+  // nodes whose links are interpolated after each step
+  std::vector<double> qlink;
+  DevBuf ibb_node, ibb_q, ibb_grp, ibb_delta, ibb_red;
+  uint32_t nibb = 0;
   double* hred = nullptr;  // pinned [NBAL + MAXG * NWALL]
   bool uw_dirty = true;
   bool have_state = false;
@@ -256,6 +264,33 @@ int build_geometry(lbm_ctx* h) {
       }
     }
   if (recs.size() > (size_t)INT32_MAX) return fail(LBM_EINVAL, "too many boundary rows");
+  // nodes with links to walls that are not halfway
+  std::vector<uint32_t> inode;
+  std::vector<double> iq;
+  std::vector<uint8_t> igrp;
+  if (!h->qlink.empty()) {
+    for (size_t row = 0; row < rows; ++row) {
+      if (rowrec[row] < 0) continue;
+      for (int x = 0; x < h->nx; ++x) {
+        const uint4 r = recs[(size_t)rowrec[row] + x];
+        if (r.x >> 31) continue;
+        const size_t n = row * h->nx + x;
+        bool any = false;
+        for (int q = 1; q < Q; ++q)
+          if (((r.x >> q) & 1u) && h->qlink[(size_t)q * h->N + n] != 0.5) any = true;
+        if (!any) continue;
+        inode.push_back((uint32_t)n);
+        for (int q = 0; q < Q; ++q) {
+          const bool wall = q > 0 && ((r.x >> q) & 1u);
+          const uint32_t wv = q < 8 ? r.y : (q < 16 ? r.z : r.w);
+          iq.push_back(wall ? h->qlink[(size_t)q * h->N + n] : 0.5);
+          igrp.push_back(wall ? (uint8_t)((wv >> (4 * (q & 7))) & 15u) : (uint8_t)0xFF);
+        }
+      }
+    }
+  }
+  h->nibb = (uint32_t)inode.size();
+  if (h->nibb && h->mhd) return fail(LBM_EINVAL, "walls that are not halfway are not supported with MHD");
   for (uint32_t t = 0; t < h->ntiles; ++t) {
     uint32_t cnt = 0, packed = 0;
     for (int gr = 0; gr < MAXG; ++gr)
@@ -279,6 +314,16 @@ int build_geometry(lbm_ctx* h) {
   HIPCHK(h->red.ensure((NBAL + MAXG * NWALL) * sizeof(double)));
   HIPCHK(h->dred.ensure(NDIAGPART * sizeof(double)));
   HIPCHK(h->uwdev.ensure(MAXG * 3 * sizeof(double)));
+  if (h->nibb) {
+    HIPCHK(h->ibb_node.ensure(inode.size() * sizeof(uint32_t)));
+    HIPCHK(h->ibb_q.ensure(iq.size() * sizeof(double)));
+    HIPCHK(h->ibb_grp.ensure(igrp.size()));
+    HIPCHK(h->ibb_delta.ensure(iq.size() * sizeof(double)));
+    HIPCHK(h->ibb_red.ensure(MAXG * 4 * sizeof(double)));
+    HIPCHK(hipMemcpy(h->ibb_node.p, inode.data(), inode.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->ibb_q.p, iq.data(), iq.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->ibb_grp.p, igrp.data(), igrp.size(), hipMemcpyHostToDevice));
+  }
   h->uw_dirty = true;
   h->geom_ok = true;
   return LBM_OK;
@@ -398,7 +443,8 @@ lbm_ctx* lbm_create(int lattice, int nx, int ny, int nz, double tau, double dx, 
     return nullptr;
   }
   h->stream = h->own;
-  if (hipHostMalloc((void**)&h->hred, (2 * (NBAL + MAXG * NWALL) + NDIAGPART) * sizeof(double)) != hipSuccess) {
+  if (hipHostMalloc((void**)&h->hred, (2 * (NBAL + MAXG * NWALL) + NDIAGPART + MAXG * 4) * sizeof(double)) !=
+      hipSuccess) {
     fail(LBM_ENOMEM, "pinned host buffer");
     (void)hipStreamDestroy(h->own);
     delete h;
@@ -492,6 +538,23 @@ int lbm_set_les(lbm_ctx* h, double cs) {
   h->tape = false;
   if (!(cs >= 0) || !std::isfinite(cs)) return fail(LBM_EINVAL, "C_s must be >= 0");
   h->cs = cs;
+  return LBM_OK;
+}
+
+int lbm_set_link_fractions(lbm_ctx* h, const double* q) {
+  int rc = setup_guard(h);
+  if (rc) return rc;
+  if (!q) {
+    h->qlink.clear();
+  } else {
+    std::vector<double> v((size_t)h->Q * h->N);
+    for (size_t i = 0; i < v.size(); ++i) {
+      if (!(q[i] > 0.0 && q[i] <= 1.0)) return fail(LBM_EINVAL, "link fraction %g outside (0, 1] at %zu", q[i], i);
+      v[i] = q[i];
+    }
+    h->qlink.swap(v);
+  }
+  h->geom_ok = false;
   return LBM_OK;
 }
 
@@ -653,6 +716,20 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
   if (rc) return rc;
   StepArgs a = step_args(h);
   const size_t mbytes = (size_t)4 * h->N * elem_bytes(h->prec);
+  IbbArgs ib = {};
+  if (h->nibb) {
+    ib.f = h->f.p;
+    ib.node = (const uint32_t*)h->ibb_node.p;
+    ib.qf = (const double*)h->ibb_q.p;
+    ib.grp = (const uint8_t*)h->ibb_grp.p;
+    ib.rec = (const uint4*)h->rec.p;
+    ib.rowrec = (const int*)h->rowrec.p;
+    for (int gr = 0; gr < MAXG; ++gr)
+      for (int k = 0; k < 3; ++k) ib.uw[gr][k] = h->uw[gr][k] / h->c;
+    ib.M = h->nibb;
+    ib.geo = a.geo;
+    ib.p = a.p;
+  }
   const size_t sbytes = (size_t)h->Q * h->N * elem_bytes(h->prec);
   if (h->timing) {
     while (h->ev.size() < (size_t)n + 2) {
@@ -674,12 +751,23 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
     } else {
       HIPCHK(launch_step(h->lattice, h->prec, h->mhd, a, h->parity, diag, h->stream));
     }
+    if (h->nibb) {
+      ib.parity = h->parity ^ 1;
+      ib.delta = diag ? (double*)h->ibb_delta.p : nullptr;
+      HIPCHK(launch_ibb(h->lattice, h->prec, ib, h->stream));
+    }
     if (h->timing) HIPCHK(hipEventRecord(h->ev[i + 1], h->stream));
     h->parity ^= 1;
   }
   HIPCHK(launch_reduce((const double*)h->part.p, (const uint32_t*)h->blkgrp.p, h->ntiles, 0, NBAL + MAXG * NWALL,
                        (double*)h->red.p, h->stream));
   HIPCHK(hipMemcpyAsync(h->hred, h->red.p, (NBAL + MAXG * NWALL) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  double* ibb_host = h->hred + 2 * (NBAL + MAXG * NWALL) + NDIAGPART;
+  if (h->nibb) {
+    HIPCHK(launch_ibb_reduce(h->lattice, (const double*)h->ibb_delta.p, (const uint8_t*)h->ibb_grp.p, h->nibb, h->G,
+                             (double*)h->ibb_red.p, h->stream));
+    HIPCHK(hipMemcpyAsync(ibb_host, h->ibb_red.p, (size_t)h->G * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  }
   if (h->timing) HIPCHK(hipEventRecord(h->ev[n + 1], h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   if (h->timing) {
@@ -708,6 +796,9 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
     h->tim[5] = tot * 1e-3;
   }
   std::memcpy(h->last, h->hred, sizeof(h->last));
+  // interpolated links: the returning values changed after the step's own sums
+  for (int gr = 0; h->nibb && gr < h->G; ++gr)
+    for (int k = 0; k < NWALL; ++k) h->last[NBAL + gr * NWALL + k] += ibb_host[gr * 4 + k];
   std::memcpy(h->last_uw, h->uw, sizeof(h->last_uw));
   h->steps += n;
   h->have_step = true;
@@ -778,6 +869,7 @@ int lbm_stress(lbm_ctx* h, double* sigma, double* strain) {
 int lbm_halfstep(lbm_ctx* h, double* fbar, double* rho_bar, double* u_bar, double* sigma_bar) {
   int rc = check_ready(h);
   if (rc) return rc;
+  if (h->nibb) return fail(LBM_EINVAL, "the half-step distribution is not available with interpolated walls");
   if (!h->have_step) return fail(LBM_ESTATE, "no step taken since the state was set");
   const size_t N = h->N, Q = h->Q, D = h->D, nc = h->NC;
   const size_t total = (fbar ? Q : 0) + (rho_bar ? 1 : 0) + (u_bar ? D : 0) + (sigma_bar ? nc : 0);
@@ -932,6 +1024,7 @@ long lbm_link_count(lbm_ctx* h, int group) {
 }
 
 static int adjoint_supported(lbm_ctx* h) {
+  if (h->nibb) return fail(LBM_EINVAL, "the adjoint covers halfway walls only");
   if (h->prec != S_F32 && h->prec != S_F64) return fail(LBM_EINVAL, "the adjoint needs F32 or F64 storage");
   if (h->mhd) return fail(LBM_EINVAL, "the adjoint does not cover the MHD equilibrium");
   if (h->cs > 0) return fail(LBM_EINVAL, "the adjoint does not cover the Smagorinsky closure");

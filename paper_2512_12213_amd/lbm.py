@@ -31,6 +31,7 @@ _SIGS = [
     ("lbm_set_rho0", C.c_int, [_P, C.c_double]),
     ("lbm_add_plane_walls", C.c_int, [_P, C.c_int, C.c_int, C.c_int]),
     ("lbm_add_solid_mask", C.c_int, [_P, C.c_void_p, C.c_int]),
+    ("lbm_set_link_fractions", C.c_int, [_P, _D]),
     ("lbm_set_wall_velocity", C.c_int, [_P, C.c_int, C.c_double, C.c_double, C.c_double]),
     ("lbm_set_body_force", C.c_int, [_P, C.c_double, C.c_double, C.c_double]),
     ("lbm_set_body_force_field", C.c_int, [_P, C.c_void_p]),
@@ -159,6 +160,13 @@ class Lattice:
         m = np.ascontiguousarray(mask, dtype=np.uint8)
         assert m.size == self.N
         _chk(self.L.lbm_add_solid_mask(self.h, m.ctypes.data, group))
+
+    def set_link_fractions(self, q):
+        """q [Q, nz, ny, nx]: wall distance / link length of wall links (1/2 halfway), or None."""
+        q = _f64(q)
+        if q is not None:
+            assert q.size == self.Q * self.N
+        _chk(self.L.lbm_set_link_fractions(self.h, _dp(q)))
 
     def set_wall_velocity(self, group, u):
         u = list(u) + [0.0] * (3 - len(u))
@@ -306,6 +314,9 @@ def from_workload(w, storage=None, u0=None, init=True):
     mask = W.obstacle_mask(w)
     if mask is not None:
         lat.add_solid_mask(mask, w.obstacle[-1])
+    qf = W.link_fractions(w)
+    if qf is not None:
+        lat.set_link_fractions(qf)
     lat.set_body_force(list(w.body_force))
     if w.les_cs:
         lat.set_les(w.les_cs)

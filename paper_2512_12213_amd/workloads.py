@@ -41,6 +41,7 @@ class Workload:
     darcy: float = 0.0                  # porous resistance sigma (1/time)
     mhd: Optional[Tuple] = None         # (B0x, B0y, B0z, mu, tau_m)
     obstacle: Optional[Tuple] = None    # ("cylinder", cx, cy, r, group) or ("sphere", cx, cy, cz, r, group)
+    curved: bool = False                # obstacle walls at their exact distance (link fractions), not halfway
     u0_amp: float = 0.0
     u0_seed: int = 2512
     steps: int = 0
@@ -146,6 +147,18 @@ def link_fractions_sphere(Q, nx, ny, nz, cx, cy, cz, r):
         hit = (~inside) & tgt
         q[a][hit] = np.clip(t[hit], 1e-6, 1.0)
     return q
+
+
+def link_fractions(w: Workload):
+    """[Q, nz, ny, nx] link fractions of the workload's obstacle surface when
+    it is curved, else None (halfway walls everywhere)."""
+    if not w.curved or w.obstacle is None:
+        return None
+    if w.obstacle[0] == "cylinder":
+        _, cx, cy, r, _g = w.obstacle
+        return link_fractions_sphere(9, w.nx, w.ny, 1, cx, cy, 0.0, r)
+    _, cx, cy, cz, r, _g = w.obstacle
+    return link_fractions_sphere(19, w.nx, w.ny, w.nz, cx, cy, cz, r)
 
 
 def obstacle_mask(w: Workload):

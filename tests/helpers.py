@@ -16,6 +16,9 @@ def make_oracle(w: W.Workload, complex_step=False, u0=None, init=True):
     if mask is not None:
         o.set_solid(mask, w.obstacle[-1])
     o.set_body_force(list(w.body_force))
+    qf = W.link_fractions(w)
+    if qf is not None:
+        o.set_link_fraction(qf)
     if w.les_cs:
         o.set_les(w.les_cs)
     if w.stokes:

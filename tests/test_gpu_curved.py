@@ -1,0 +1,191 @@
+"""Walls that are not halfway between nodes on the GPU: linearly interpolated
+bounce-back (Bouzidi, Firdaouss and Lallemand 2001) run as a pass after each
+step, against the oracle element by element, and the Section 5 statement that
+the momentum exchange of Eq. (25) then gives the stress at the half-grid point
+x_f + e dt / 2, checked on the GPU alone in steady flows.
+
+Tolerances are those of the halfway parity tests: FP64 1e-12, FP32 1e-5 on
+fields and 1e-4 on wall forces."""
+import sys
+
+import numpy as np
+import pytest
+
+from helpers import make_oracle, rel_inf
+from paper_2512_12213_amd import workloads as W
+from test_gpu_parity import compare_all
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_2512_12213_amd import lbm as L
+    L.lib()
+    return L
+
+
+def offset_channel(nx, n, qb, qt, tau=0.8, a=1e-6, uw=0.0, storage=W.F64):
+    w = W.Workload("offset_channel_d2q9_%dx%d" % (nx, n), W.D2Q9, nx, n, 1, tau, storage=storage,
+                   body_force=(a, 0.0, 0.0), walls=((1, 0, 1),),
+                   wall_velocity=((1, uw, 0.0, 0.0),) if uw else (), groups=2)
+    q = np.full((9, 1, n, nx), 0.5)
+    q[:, 0, 0, :] = qb
+    q[:, 0, n - 1, :] = qt
+    return w, q
+
+
+def pair(lbm, w, q, storage=None):
+    g = lbm.from_workload(w, storage=storage, init=False)
+    o = make_oracle(w, init=False)
+    if q is not None:
+        g.set_link_fractions(q)
+        o.set_link_fraction(q)
+    u0 = W.initial_velocity(w)
+    g.init_equilibrium(u0)
+    o.init_equilibrium(u0)
+    return g, o
+
+
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+@pytest.mark.parametrize("steps", [300, 301])
+def test_offset_channel_matches_oracle(lbm, storage, steps):
+    """Force-driven channel with walls at q = 0.25 below and 0.8 above the
+    end nodes; both A-A parities end the call."""
+    w, q = offset_channel(8, 16, 0.25, 0.8, a=2e-5)
+    say("case offset channel", storage, steps)
+    g, o = pair(lbm, w, q, storage)
+    g.step(steps)
+    o.step(steps)
+    compare_all(g, o, storage, 2, "offset channel")
+
+
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+def test_offset_couette_matches_oracle(lbm, storage):
+    """Moving top wall with fractions 0.9 (bottom) and 0.3 (top): the
+    moving-wall term enters both interpolation branches."""
+    w, q = offset_channel(8, 12, 0.9, 0.3, a=0.0, uw=0.03)
+    say("case offset couette", storage)
+    g, o = pair(lbm, w, q, storage)
+    for _ in range(3):
+        g.step(67)
+        o.step(67)
+    compare_all(g, o, storage, 2, "offset couette")
+
+
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+def test_curved_cylinder_matches_oracle(lbm, storage):
+    """Couette channel with a cylinder whose links carry the exact circle's
+    fractions (both interpolation branches, the halfway fallback where the
+    upstream node is solid), moving top wall, body force."""
+    w = W.couette_cylinder(nx=64, ny=32, r=5.3, cx=20.4, cy=15.7, uw=0.03, tau=0.7, a=2e-5, storage=storage)
+    w.curved = True
+    q = W.link_fractions(w)
+    assert (q < 0.5).any() and (q > 0.5).any()
+    say("case curved cylinder", storage)
+    g, o = pair(lbm, w, None, storage)
+    for n in (150, 151):
+        g.step(n)
+        o.step(n)
+        compare_all(g, o, storage, 3, "curved cylinder")
+    bg = g.force_balance()
+    assert np.abs(bg[9:12]).max() <= (1e-12 if storage == W.F64 else 1e-4) * np.abs(bg[0:9]).max()
+
+
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+def test_curved_sphere_matches_oracle(lbm, storage):
+    """D3Q19 duct with an off-lattice sphere (fractions of the exact sphere)
+    and a moving top wall."""
+    w = W.duct_sphere(nx=24, ny=16, nz=14, r=3.7, storage=storage)
+    w.curved = True
+    say("case curved sphere", storage)
+    g, o = pair(lbm, w, None, storage)
+    for n in (60, 61):
+        g.step(n)
+        o.step(n)
+        compare_all(g, o, storage, 5, "curved sphere")
+
+
+@pytest.mark.parametrize("qv", [0.25, 0.7, 1.0])
+def test_gpu_momentum_exchange_is_the_half_grid_stress(lbm, qv):
+    """Steady offset channel on the GPU alone: the bottom wall carries half
+    the body force on the n fluid nodes of a column (the enveloped domain of
+    Section 6), rho a n / 2, equal to the Eq. (9) stress extrapolated to
+    y_i = -dx/2 and not to the wall at y_w = -q dx (Section 5)."""
+    n, a = 16, 1e-6
+    w, q = offset_channel(4, n, qv, qv, a=a)
+    say("case half-grid stress", qv)
+    g = lbm.from_workload(w, init=False)
+    g.set_link_fractions(q)
+    g.init_equilibrium()
+    g.step(60000)
+    fw = g.wall_force()
+    sig, _ = g.stress()
+    s = sig[1, 0, :, 0]
+    slope = s[1] - s[0]
+    s_i = s[0] - 0.5 * slope
+    s_w = s[0] - qv * slope
+    P = fw[0, 0, 0] / w.nx  # per node width
+    assert abs(P - a * n / 2) < 1e-12 * a * n
+    assert abs(s_i - P) < 1e-9 * P
+    assert abs((s_w - P) - a * (qv - 0.5)) < 1e-9 * P
+
+
+def test_gpu_offset_couette_is_exact(lbm):
+    """Linear interpolation makes the linear profile between the true walls
+    exact: u(y) = U (y + q_b) / H with H = n - 1 + q_b + q_t, and both walls
+    carry rho nu U / H."""
+    n, tau, U = 16, 0.8, 0.02
+    for qb, qt in ((0.25, 0.8), (0.9, 0.3)):
+        w, q = offset_channel(4, n, qb, qt, tau=tau, a=0.0, uw=U)
+        say("case exact couette", qb, qt)
+        g = lbm.from_workload(w, init=False)
+        g.set_link_fractions(q)
+        g.init_equilibrium()
+        g.step(40000)
+        _, v = g.get_macro()
+        H = n - 1 + qb + qt
+        y = np.arange(n, dtype=float)
+        assert np.abs(v[0, 0, :, 0] - U * (y + qb) / H).max() < 1e-12 * U
+        fw = g.wall_force() / w.nx
+        nu = (tau - 0.5) / 3
+        assert abs(fw[0, 0, 0] - nu * U / H) < 1e-10 * nu * U / H
+        assert abs(fw[1, 0, 0] + nu * U / H) < 1e-10 * nu * U / H
+
+
+def test_halfway_fractions_change_nothing(lbm):
+    w = W.couette_cylinder(nx=40, ny=20, r=3.0, cx=12.0, cy=10.0, storage=W.F64)
+    g1 = lbm.from_workload(w)
+    g2 = lbm.from_workload(w, init=False)
+    g2.set_link_fractions(np.full((9, 1, w.ny, w.nx), 0.5))
+    g2.init_equilibrium(W.initial_velocity(w))
+    g1.step(50)
+    g2.step(50)
+    assert np.array_equal(g1.get_state(), g2.get_state())
+    assert np.array_equal(g1.wall_force(), g2.wall_force())
+
+
+def test_link_fraction_errors(lbm):
+    w, q = offset_channel(4, 8, 0.3, 0.3)
+    g = lbm.from_workload(w, init=False)
+    with pytest.raises(lbm.LBMError):
+        g.set_link_fractions(np.zeros((9, 1, 8, 4)))
+    g.set_link_fractions(q)
+    g.init_equilibrium()
+    g.step(2)
+    with pytest.raises(lbm.LBMError):
+        g.halfstep()
+    with pytest.raises(lbm.LBMError):
+        g.adjoint_forward(4, 2, 0, 0)
+    with pytest.raises(lbm.LBMError):
+        g.set_link_fractions(q)  # set-up only
+    h = W.hartmann_duct(nx=4, ny=8, nz=4, steps=1)
+    m = lbm.from_workload(h, init=False)
+    m.set_link_fractions(np.full((19, 4, 8, 4), 0.3))
+    with pytest.raises(lbm.LBMError):
+        m.init_equilibrium()

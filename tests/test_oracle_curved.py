@@ -1,5 +1,5 @@
 """Pins of the oracle's interpolated bounce-back (walls not halfway between
-nodes) and of the Section 4 statement that the momentum exchange of Eq. (25)
+nodes) and of the Section 5 statement that the momentum exchange of Eq. (25)
 then gives the stress at x_i = x_f + e dt / 2, not at the wall."""
 import numpy as np
 import pytest
@@ -55,7 +55,7 @@ def test_offset_channel_profile_is_second_order(qv):
 
 @pytest.mark.parametrize("qv", [0.25, 0.7, 1.0])
 def test_momentum_exchange_gives_the_stress_at_the_half_grid_point(qv):
-    """Section 4: with a wall that is not halfway, Eq. (25) still uses the
+    """Section 5: with a wall that is not halfway, Eq. (25) still uses the
     values leaving and returning at the fluid node, which trace back to the
     point x_i half a link away; the force per area is the stress there, not
     at the wall.  In the steady channel the Eq. (9) stress is linear across

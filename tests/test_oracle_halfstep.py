@@ -1,4 +1,4 @@
-"""Pins of the oracle's half-step distribution (Section 4, Eqs. 27-30).
+"""Pins of the oracle's half-step distribution (Section 5, Eqs. 27-30).
 
 fbar = (f_rel(x, t) + f(x, t + dt)) / 2 and the stress of Eq. (28),
 sigma_bar = -sum e e fbar + Mbar^eq.  Checked against what the paper and the

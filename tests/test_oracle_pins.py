@@ -278,7 +278,7 @@ def test_steady_channel_wall_force_equals_body_force():
 
 
 # ---------------------------------------------------------------------------
-# Section 4 (after Eq. 28): moving-boundary momentum-flux correction.
+# Section 5 (after Eq. 28): moving-boundary momentum-flux correction.
 # ---------------------------------------------------------------------------
 def test_momentum_flux_correction_transpiration():
     """Walls moving along their normal (fluid passing through them): the
