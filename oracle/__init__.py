@@ -48,6 +48,7 @@ def _lib(complex_step: bool):
         lib.orc_set_link_fraction.argtypes = [P, dp]
         lib.orc_set_artefact.argtypes = [P, C.c_int]
         lib.orc_set_mhd.argtypes = [P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
+        lib.orc_set_lorentz_force.argtypes = [P, C.c_int]
         lib.orc_init_equilibrium.argtypes = [P, dp]
         lib.orc_set_state.argtypes = [P, dp, dp]
         lib.orc_get_state.argtypes = [P, dp, dp]
@@ -158,6 +159,11 @@ class Oracle:
         self._chk(self.lib.orc_set_mhd(self.h, B0[0], B0[1], B0[2], mu, tau_m))
         self.mhd = True
 
+    def set_lorentz_force(self, on):
+        """MHD coupling: True = Lorentz force through the force term (equilibrium
+        hydrodynamic), False = magnetic stress in the equilibrium (Eq. 10)."""
+        self._chk(self.lib.orc_set_lorentz_force(self.h, int(on)))
+
     def init_equilibrium(self, u0=None):
         self._chk(self.lib.orc_init_equilibrium(self.h, _dp(_f64(u0))))
 
@@ -176,7 +182,7 @@ class Oracle:
         return (d, di) if imag else d
 
     def get_induction(self):
-        g = np.empty((7, 3, self.nz, self.ny, self.nx))
+        g = np.empty((7 if self.D == 3 else 5, 3, self.nz, self.ny, self.nx))
         self._chk(self.lib.orc_get_induction(self.h, _dp(g)))
         return g
 

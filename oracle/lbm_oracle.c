@@ -70,8 +70,10 @@ struct orc {
   double darcy; /* porous resistance sigma: body force -sigma v added to a (Brinkman) */
   int artefact;
   int mhd;
+  int lorentz;  /* MHD coupling: 0 magnetic stress in the equilibrium (Eq. 10), 1 Lorentz force as a body force */
+  int K;        /* induction directions: 7 (D3Q7) or 5 (its planar restriction) */
   double B0[3], mu, tau_m;
-  real *g, *gn; /* induction distributions [7][3][N] */
+  real *g, *gn; /* induction distributions [K][3][N] */
   real *d, *dn; /* [Q][N] deviations */
   real* rel;     /* [Q][N] relaxed values f_rel(x, t) of the last step, before propagation */
   real* rho_t;   /* [N] density of the last step's pre-step state */
@@ -122,10 +124,13 @@ static void set_lattice(orc* o) {
 }
 
 /* D3Q7 lattice of the induction solver: weights 1/4 (rest) and 1/8, so that
- * sum_k W_k e_k e_k = theta c^2 I with theta = 1/4. */
+ * sum_k W_k e_k e_k = theta c^2 I with theta = 1/4.  Two-dimensional flows use
+ * its restriction to the plane (directions 0-4): the two z links fold into
+ * the rest direction, weights 1/2 and 1/8, the same theta and therefore the
+ * same magnetic diffusivity eta = theta c^2 dt (tau_m - 1/2). */
 static const int e7[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
 static const int opp7[7] = {0, 2, 1, 4, 3, 6, 5};
-static double w7(int k) { return k == 0 ? 0.25 : 0.125; }
+static double w7(const orc* o, int k) { return k == 0 ? (o->lat == 0 ? 0.5 : 0.25) : 0.125; }
 #define THETA7 0.25
 
 orc* orc_create(int lattice, int nx, int ny, int nz, double tau, double dx, double dt, int model) {
@@ -264,7 +269,7 @@ int orc_set_equilibrium(orc* o, int stokes) {
 }
 
 int orc_set_darcy(orc* o, double sigma) {
-  if (!(sigma >= 0)) return -1;
+  if (!(sigma >= 0) || (sigma > 0 && o->lorentz)) return -1;
   o->darcy = sigma;
   return 0;
 }
@@ -275,8 +280,10 @@ int orc_set_artefact(orc* o, int on) {
 }
 
 int orc_set_mhd(orc* o, double B0x, double B0y, double B0z, double mu, double tau_m) {
-  if (o->lat != 1 || !(mu > 0) || !(tau_m > 0.5)) return -1;
+  if (!(mu > 0) || !(tau_m > 0.5)) return -1;
+  if (o->lat == 0 && B0z != 0.0) return -1; /* planar field in two dimensions */
   o->mhd = 1;
+  o->K = o->lat == 0 ? 5 : 7;
   o->B0[0] = B0x;
   o->B0[1] = B0y;
   o->B0[2] = B0z;
@@ -284,8 +291,17 @@ int orc_set_mhd(orc* o, double B0x, double B0y, double B0z, double mu, double ta
   o->tau_m = tau_m;
   free(o->g);
   free(o->gn);
-  o->g = (real*)calloc((size_t)21 * o->N, sizeof(real));
-  o->gn = (real*)calloc((size_t)21 * o->N, sizeof(real));
+  o->g = (real*)calloc((size_t)3 * o->K * o->N, sizeof(real));
+  o->gn = (real*)calloc((size_t)3 * o->K * o->N, sizeof(real));
+  return 0;
+}
+
+/* 1: the Lorentz force enters through the force term and the equilibrium
+ * stays hydrodynamic (the third approach of Section 4; the text after Eq. 36
+ * gives its balance); 0: the paper's approach, magnetic stress in f^eq. */
+int orc_set_lorentz_force(orc* o, int on) {
+  if (!o->mhd || (on && o->darcy > 0)) return -1;
+  o->lorentz = on ? 1 : 0;
   return 0;
 }
 
@@ -310,7 +326,8 @@ static real feq_dev(const orc* o, int q, real rho, real drho, const real* u) {
   return o->w[q] * (drho + rho * (3.0 * eu / c2 + 4.5 * eu * eu / (c2 * c2) - 1.5 * uu / c2));
 }
 
-/* Magnetic part of the MHD equilibrium, Eq. (10) (three-dimensional form). */
+/* Magnetic part of the MHD equilibrium, Eq. (10); two-dimensional flows
+ * leave out its -c^2 B^2 / 6 term (the text after Eq. 10). */
 static real phi_mhd(const orc* o, int q, const real* B) {
   const double c2 = o->c * o->c;
   real ee = 0, eB = 0, B2 = 0;
@@ -319,8 +336,12 @@ static real phi_mhd(const orc* o, int q, const real* B) {
     eB += (real)(o->c * o->e[q][k]) * B[k];
     B2 += B[k] * B[k];
   }
-  return 9.0 * o->w[q] / (2.0 * c2 * c2 * o->mu) * (0.5 * B2 * ee - eB * eB - c2 * B2 / 6.0);
+  real last = o->lat == 1 ? c2 * B2 / 6.0 : 0.0;
+  return 9.0 * o->w[q] / (2.0 * c2 * c2 * o->mu) * (0.5 * B2 * ee - eB * eB - last);
 }
+
+/* Is the magnetic stress carried by the equilibrium (Eq. 10)? */
+static int mhd_eq(const orc* o) { return o->mhd && !o->lorentz; }
 
 /* Maxwell stress L_ij = (B^2 delta_ij / 2 - B_i B_j) / mu (after Eq. 11). */
 static real maxwell(const orc* o, int i, int j, const real* B) {
@@ -343,10 +364,57 @@ typedef struct {
   real E[3][3];  /* artefact term E_ij of Eq. (9) */
 } node_t;
 
-/* Moments, model velocities, Pi^neq, Smagorinsky tau, force term.  a_node,
- * when not NULL, replaces the node's body force (used to differentiate with
- * respect to it). */
-static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, const real* a_node, node_t* s) {
+/* Lorentz force per unit mass a_L = J x B / rho, J = curl B / mu, when it
+ * enters through the force term.  curl B comes from the first moment of the
+ * induction distributions, Lambda_lm = sum_k c e_kl g_km, whose equilibrium
+ * part is v_l B_m - B_l v_m and whose non-equilibrium part is, to first
+ * order in the Chapman-Enskog expansion (as Pi^neq for the flow),
+ * -tau_m dt theta c^2 d_l B_m.  With lambda_i = eps_ilm Lambda_lm and
+ * kappa = tau_m dt theta c^2 this reads mu kappa J = -lambda + 2 v x B.  The
+ * velocity v = u* + dt a_L / 2 (u* = u + dt a_ext / 2) holds J itself, which
+ * makes it the linear system
+ *   [mu kappa I + (dt / rho) (B^2 I - B B^T)] J = -lambda + 2 u* x B,
+ * solved here by Gaussian elimination with partial pivoting. */
+static void lorentz_accel(const orc* o, real rho, const real* ustar, const real* B, const real* lam, real* aL) {
+  const double kappa = o->tau_m * o->dt * THETA7 * o->c * o->c;
+  real B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+  real A[3][4];
+  real uxB[3] = {ustar[1] * B[2] - ustar[2] * B[1], ustar[2] * B[0] - ustar[0] * B[2], ustar[0] * B[1] - ustar[1] * B[0]};
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) A[i][j] = (i == j ? o->mu * kappa + o->dt / rho * B2 : 0.0) - o->dt / rho * B[i] * B[j];
+    A[i][3] = -lam[i] + 2.0 * uxB[i];
+  }
+  for (int col = 0; col < 3; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 3; ++r)
+      if (fabs(RE(A[r][col])) > fabs(RE(A[piv][col]))) piv = r;
+    if (piv != col)
+      for (int j = 0; j < 4; ++j) {
+        real t = A[col][j];
+        A[col][j] = A[piv][j];
+        A[piv][j] = t;
+      }
+    for (int r = col + 1; r < 3; ++r) {
+      real f = A[r][col] / A[col][col];
+      for (int j = col; j < 4; ++j) A[r][j] -= f * A[col][j];
+    }
+  }
+  real J[3];
+  for (int i = 2; i >= 0; --i) {
+    real v = A[i][3];
+    for (int j = i + 1; j < 3; ++j) v -= A[i][j] * J[j];
+    J[i] = v / A[i][i];
+  }
+  aL[0] = (J[1] * B[2] - J[2] * B[1]) / rho;
+  aL[1] = (J[2] * B[0] - J[0] * B[2]) / rho;
+  aL[2] = (J[0] * B[1] - J[1] * B[0]) / rho;
+}
+
+/* Moments, model velocities, Pi^neq, Smagorinsky tau, force term.  gl: the
+ * node's induction distributions [K][3] (MHD) or NULL.  a_node, when not
+ * NULL, replaces the node's body force (used to differentiate with respect
+ * to it). */
+static void node_setup(const orc* o, const real* dl, long idx, const real (*gl)[3], const real* a_node, node_t* s) {
   const int D = o->D, Q = o->Q;
   const double c = o->c, c2 = c * c, dt = o->dt;
   memset(s, 0, sizeof(*s));
@@ -361,14 +429,30 @@ static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, c
   s->rho = rho;
   s->drho = drho;
   for (int k = 0; k < 3; ++k) {
+    s->B[k] = 0;
+    if (gl)
+      for (int m = 0; m < o->K; ++m) s->B[k] += gl[m][k]; /* B = sum_k g_k */
+  }
+  for (int k = 0; k < 3; ++k) {
     s->u[k] = k < D ? j[k] / rho : 0;
     s->a[k] = k < D ? (a_node ? a_node[k] : body_force(o, idx, k)) : 0;
     /* porous resistance -sigma v with v = u + dt a / 2, a including it:
      * a = (a_ext - sigma u) / (1 + sigma dt / 2) */
     if (o->darcy > 0) s->a[k] = (s->a[k] - o->darcy * s->u[k]) / (1.0 + 0.5 * o->darcy * dt);
-    s->v[k] = s->u[k] + 0.5 * dt * s->a[k]; /* v = u + dt a / 2 for all models */
-    s->B[k] = Bn ? Bn[k] : 0;
   }
+  if (o->mhd && o->lorentz && gl) {
+    real Lam[3][3] = {{0}}, lam[3], us[3], aL[3];
+    for (int m = 0; m < o->K; ++m)
+      for (int l = 0; l < 3; ++l)
+        for (int n = 0; n < 3; ++n) Lam[l][n] += (real)(c * e7[m][l]) * gl[m][n];
+    lam[0] = Lam[1][2] - Lam[2][1];
+    lam[1] = Lam[2][0] - Lam[0][2];
+    lam[2] = Lam[0][1] - Lam[1][0];
+    for (int k = 0; k < 3; ++k) us[k] = s->u[k] + 0.5 * dt * s->a[k];
+    lorentz_accel(o, rho, us, s->B, lam, aL);
+    for (int k = 0; k < D; ++k) s->a[k] += aL[k];
+  }
+  for (int k = 0; k < 3; ++k) s->v[k] = s->u[k] + 0.5 * dt * s->a[k]; /* v = u + dt a / 2 for all models */
   /* u^eq per model (Section 2): [e] uses v, the original Shan-Chen form uses
    * u + tau dt a, all others use u. */
   for (int k = 0; k < 3; ++k) {
@@ -386,7 +470,7 @@ static void node_setup(const orc* o, const real* dl, long idx, const real* Bn, c
       real m = 0;
       for (int q = 0; q < Q; ++q) m += (real)(c2 * o->e[q][i] * o->e[q][k]) * dl[q];
       real eqm = (i == k ? drho * c2 / 3.0 : 0.0) + (o->stokes ? 0.0 : rho * s->ueq[i] * s->ueq[k]);
-      if (o->mhd) eqm += maxwell(o, i, k, s->B);
+      if (mhd_eq(o)) eqm += maxwell(o, i, k, s->B);
       s->Pi[i][k] = m - eqm;
     }
   /* Smagorinsky closure (C_s > 0): nu_eff = nu0 + (C_s dx)^2 |S| with
@@ -487,16 +571,16 @@ int orc_init_equilibrium(orc* o, const double* u0) {
     real B[3] = {o->B0[0], o->B0[1], o->B0[2]};
     for (int q = 0; q < o->Q; ++q) {
       real v = o->solid[i] ? 0 : feq_dev(o, q, o->rho0, 0.0, u);
-      if (o->mhd && !o->solid[i]) v += phi_mhd(o, q, B);
+      if (mhd_eq(o) && !o->solid[i]) v += phi_mhd(o, q, B);
       o->d[(long)q * N + i] = v;
     }
     if (o->mhd) {
-      for (int k = 0; k < 7; ++k)
+      for (int k = 0; k < o->K; ++k)
         for (int c = 0; c < 3; ++c) {
-          real geq = w7(k) * B[c];
+          real geq = w7(o, k) * B[c];
           if (!o->solid[i])
             for (int m = 0; m < 3; ++m)
-              geq += w7(k) * (e7[k][m] / (THETA7 * o->c)) * (u[m] * B[c] - B[m] * u[c]);
+              geq += w7(o, k) * (e7[k][m] / (THETA7 * o->c)) * (u[m] * B[c] - B[m] * u[c]);
           o->g[((long)k * 3 + c) * N + i] = geq;
         }
     }
@@ -528,7 +612,7 @@ int orc_get_state(const orc* o, double* d, double* d_im) {
 
 int orc_get_induction(const orc* o, double* g) {
   if (!o->mhd) return -1;
-  for (long i = 0; i < 21 * o->N; ++i) g[i] = RE(o->g[i]);
+  for (long i = 0; i < 3L * o->K * o->N; ++i) g[i] = RE(o->g[i]);
   return 0;
 }
 
@@ -541,12 +625,12 @@ static int part_size(const orc* o) { return o->G * 9 + 7; }
 /* Everything of one node's update before propagation: node_setup, then the
  * relaxation of Eq. (2), drel = d + (d^eq - d)/tau + F, with the equilibrium
  * of Eq. (1) (+ the magnetic term of Eq. 10). */
-static void node_relax(const orc* o, const real* dl, long idx, const real* Bn, const real* a_node, node_t* s,
+static void node_relax(const orc* o, const real* dl, long idx, const real (*gl)[3], const real* a_node, node_t* s,
                        real* drel) {
-  node_setup(o, dl, idx, Bn, a_node, s);
+  node_setup(o, dl, idx, gl, a_node, s);
   for (int q = 0; q < o->Q; ++q) {
     real deq = feq_dev(o, q, s->rho, s->drho, s->ueq);
-    if (o->mhd) deq += phi_mhd(o, q, s->B);
+    if (mhd_eq(o)) deq += phi_mhd(o, q, s->B);
     drel[q] = dl[q] + (deq - dl[q]) / s->tau + s->F[q];
   }
 }
@@ -565,17 +649,12 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
   const long idx = ((long)z * o->ny + y) * o->nx + x;
   real dl[19], drel[19];
   for (int q = 0; q < Q; ++q) dl[q] = o->d[(long)q * N + idx];
-  real Bn[3] = {0, 0, 0};
   real gl[7][3];
-  if (o->mhd) {
-    for (int k = 0; k < 7; ++k)
-      for (int m = 0; m < 3; ++m) {
-        gl[k][m] = o->g[((long)k * 3 + m) * N + idx];
-        Bn[m] += gl[k][m]; /* B = sum_k g_k */
-      }
-  }
+  if (o->mhd)
+    for (int k = 0; k < o->K; ++k)
+      for (int m = 0; m < 3; ++m) gl[k][m] = o->g[((long)k * 3 + m) * N + idx];
   node_t s;
-  node_relax(o, dl, idx, o->mhd ? Bn : NULL, NULL, &s, drel);
+  node_relax(o, dl, idx, o->mhd ? (const real(*)[3])gl : NULL, NULL, &s, drel);
   /* kept for the half-step distribution of Eq. (27) and for interpolated
    * bounce-back */
   for (int q = 0; q < Q; ++q) o->rel[(long)q * N + idx] = drel[q];
@@ -613,7 +692,7 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
       pw[k] += vol / dt * (ek * fout - ebk * fin);          /* raw momentum exchange */
       pw[3 + k] += -vol / dt * o->uw[grp][k] * (fout - fin); /* minus momentum flux */
     }
-    if (o->mhd) {
+    if (mhd_eq(o)) {
       /* minus Maxwell stress: the magnetic part of the equilibrium at the wall
        * field carried by both populations of the link */
       real Bw[3] = {o->B0[0], o->B0[1], o->B0[2]};
@@ -624,12 +703,12 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
 
   /* induction lattice (D3Q7 vector distributions, B Dirichlet on walls) */
   if (o->mhd) {
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < o->K; ++k) {
       real grel[3];
       for (int m = 0; m < 3; ++m) {
-        real geq = w7(k) * s.B[m];
+        real geq = w7(o, k) * s.B[m];
         for (int j = 0; j < 3; ++j)
-          geq += w7(k) * (e7[k][j] / (THETA7 * c)) * (s.v[j] * s.B[m] - s.B[j] * s.v[m]);
+          geq += w7(o, k) * (e7[k][j] / (THETA7 * c)) * (s.v[j] * s.B[m] - s.B[j] * s.v[m]);
         grel[m] = gl[k][m] + (geq - gl[k][m]) / o->tau_m;
       }
       long t;
@@ -639,7 +718,7 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
       } else {
         /* anti-bounce-back imposing B = B0 at the halfway wall */
         int kb = opp7[k];
-        for (int m = 0; m < 3; ++m) o->gn[((long)kb * 3 + m) * N + idx] = -grel[m] + 2.0 * w7(k) * o->B0[m];
+        for (int m = 0; m < 3; ++m) o->gn[((long)kb * 3 + m) * N + idx] = -grel[m] + 2.0 * w7(o, k) * o->B0[m];
       }
     }
   }
@@ -754,8 +833,16 @@ int orc_step(orc* o, int n) {
 static void node_B(const orc* o, long idx, real* B) {
   B[0] = B[1] = B[2] = 0;
   if (!o->mhd) return;
-  for (int k = 0; k < 7; ++k)
+  for (int k = 0; k < o->K; ++k)
     for (int m = 0; m < 3; ++m) B[m] += o->g[((long)k * 3 + m) * o->N + idx];
+}
+
+/* The node's induction distributions [K][3]; NULL without MHD. */
+static const real (*load_g(const orc* o, long idx, real gl[7][3]))[3] {
+  if (!o->mhd) return NULL;
+  for (int k = 0; k < o->K; ++k)
+    for (int m = 0; m < 3; ++m) gl[k][m] = o->g[((long)k * 3 + m) * o->N + idx];
+  return (const real(*)[3])gl;
 }
 
 static void load_node(const orc* o, long idx, real* dl) {
@@ -771,15 +858,14 @@ int orc_get_macro(const orc* o, double* rho, double* v, double* B) {
         for (int k = 0; k < 3; ++k) B[(long)k * o->N + i] = 0;
       continue;
     }
-    real dl[19], Bn[3];
+    real dl[19], gl[7][3];
     load_node(o, i, dl);
-    node_B(o, i, Bn);
     node_t s;
-    node_setup(o, dl, i, Bn, NULL, &s);
+    node_setup(o, dl, i, load_g(o, i, gl), NULL, &s);
     rho[i] = RE(s.rho);
     for (int k = 0; k < o->D; ++k) v[(long)k * o->N + i] = RE(s.v[k]);
     if (B)
-      for (int k = 0; k < 3; ++k) B[(long)k * o->N + i] = RE(Bn[k]);
+      for (int k = 0; k < 3; ++k) B[(long)k * o->N + i] = RE(s.B[k]);
   }
   return 0;
 }
@@ -807,11 +893,10 @@ int orc_stress(const orc* o, double* sigma, double* strain) {
     memset(sig, 0, sizeof(sig));
     memset(S, 0, sizeof(S));
     if (!o->solid[i]) {
-      real dl[19], Bn[3];
+      real dl[19], gl[7][3];
       load_node(o, i, dl);
-      node_B(o, i, Bn);
       node_t s;
-      node_setup(o, dl, i, Bn, NULL, &s);
+      node_setup(o, dl, i, load_g(o, i, gl), NULL, &s);
       node_stress(o, &s, sig, S);
     }
     for (int m = 0; m < nc; ++m) {
@@ -882,11 +967,10 @@ static void stress_integral(const orc* o, real* F) {
             real T[2][3][3];
             long ids[2] = {i0, i1};
             for (int l = 0; l < 2; ++l) {
-              real dl[19], Bn[3], sig[3][3], S[3][3];
+              real dl[19], gl[7][3], sig[3][3], S[3][3];
               load_node(o, ids[l], dl);
-              node_B(o, ids[l], Bn);
               node_t s;
-              node_setup(o, dl, ids[l], Bn, NULL, &s);
+              node_setup(o, dl, ids[l], load_g(o, ids[l], gl), NULL, &s);
               memset(sig, 0, sizeof(sig));
               node_stress(o, &s, sig, S);
               for (int i = 0; i < 3; ++i)
@@ -992,7 +1076,7 @@ int orc_halfstep(const orc* o, double* fbar, double* rho_bar, double* u_bar, dou
         real mom = 0;
         for (int q = 0; q < Q; ++q) mom += (real)(c2 * o->e[q][a] * o->e[q][b]) * db[q];
         real meq = (a == b ? rho * c2 / 3.0 : 0.0) + (o->stokes ? 0.0 : rho * u[a] * u[b]);
-        if (o->mhd) meq += maxwell(o, a, b, B);
+        if (mhd_eq(o)) meq += maxwell(o, a, b, B);
         real val = -(mom + (a == b ? o->rho0 * c2 / 3.0 : 0.0)) + meq;
         sigma_bar[(long)m * N + i] = RE(val);
       }

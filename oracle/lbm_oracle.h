@@ -24,6 +24,7 @@
  *   D3Q19: 0 rest; 1,2 +-x; 3,4 +-y; 5,6 +-z; 7,8 +-(x+y); 9,10 +-(x-y);
  *          11,12 +-(x+z); 13,14 +-(x-z); 15,16 +-(y+z); 17,18 +-(y-z)
  *   D3Q7 (induction): 0 rest; 1,2 +-x; 3,4 +-y; 5,6 +-z
+ *   D2Q5 (induction, two dimensions): directions 0-4 of D3Q7
  */
 #ifndef LBM_ORACLE_H
 #define LBM_ORACLE_H
@@ -55,13 +56,16 @@ int orc_set_darcy(orc* o, double sigma);
  * halfway.  -1 if a value is outside (0, 1]. */
 int orc_set_link_fraction(orc* o, const double* q);       /* porous resistance: adds -sigma v to the body force */
 int orc_set_artefact(orc* o, int on);
+/* MHD: D3Q19 with D3Q7 induction, or D2Q9 with D2Q5 induction (B0z = 0) */
 int orc_set_mhd(orc* o, double B0x, double B0y, double B0z, double mu, double tau_m);
+/* after orc_set_mhd: 1 = Lorentz force through the force term, f^eq hydrodynamic */
+int orc_set_lorentz_force(orc* o, int on);
 
 int orc_init_equilibrium(orc* o, const double* u0);   /* u0 [D][N] or NULL */
 int orc_set_state(orc* o, const double* d, const double* d_im);   /* [Q][N] deviations */
 int orc_get_state(const orc* o, double* d, double* d_im);
 int orc_replace_state(orc* o, const double* d);            /* keeps the last-step records */
-int orc_get_induction(const orc* o, double* g);                   /* [7][3][N] */
+int orc_get_induction(const orc* o, double* g);                   /* [K][3][N], K = 7 or 5 */
 
 int orc_step(orc* o, int n);
 

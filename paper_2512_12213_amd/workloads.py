@@ -40,6 +40,7 @@ class Workload:
     stokes: bool = False                # Stokes form of the equilibrium
     darcy: float = 0.0                  # porous resistance sigma (1/time)
     mhd: Optional[Tuple] = None         # (B0x, B0y, B0z, mu, tau_m)
+    lorentz: bool = False               # MHD: Lorentz force through the force term, equilibrium hydrodynamic
     obstacle: Optional[Tuple] = None    # ("cylinder", cx, cy, r, group) or ("sphere", cx, cy, cz, r, group)
     curved: bool = False                # obstacle walls at their exact distance (link fractions), not halfway
     u0_amp: float = 0.0
@@ -94,6 +95,20 @@ def hartmann_duct(nx=192, ny=96, nz=96, storage=F32, Ha=20.0, tau=0.8, tau_m=0.9
     return Workload("hartmann_duct_d3q19_%dx%dx%d" % (nx, ny, nz), D3Q19, nx, ny, nz, tau, storage=storage,
                     body_force=(a, 0.0, 0.0), walls=walls, mhd=(0.0, float(B0), 0.0, mu, tau_m), steps=steps,
                     groups=2 if nz == 1 else 4)
+
+
+def hartmann_channel(nx=1, ny=96, lattice=D2Q9, storage=F64, Ha=20.0, tau=0.8, tau_m=0.9, mu=1.0, a=1e-5,
+                     lorentz=False, steps=20000):
+    """Hartmann channel between insulating walls across y, periodic x (and z):
+    D2Q9 with the planar induction lattice, or a one-node-thick D3Q19 slab.
+    B0 along y from the Hartmann number on the half-width, as for the duct."""
+    nu = (tau - 0.5) / 3.0
+    eta = 0.25 * (tau_m - 0.5)
+    B0 = Ha * np.sqrt(mu * 1.0 * nu * eta) / (0.5 * ny)
+    d = "d2q9" if lattice == D2Q9 else "d3q19"
+    return Workload("hartmann_channel_%s_%dx%d%s" % (d, nx, ny, "_lorentz" if lorentz else ""), lattice, nx, ny, 1,
+                    tau, storage=storage, body_force=(a, 0.0, 0.0), walls=((1, 0, 1),),
+                    mhd=(0.0, float(B0), 0.0, mu, tau_m), lorentz=lorentz, steps=steps, groups=2)
 
 
 def duct_sphere(nx=128, ny=64, nz=64, storage=F32, r=8.0, tau=0.55, a=1e-5, uw=0.01, steps=400):
@@ -177,6 +192,11 @@ def initial_velocity(w: Workload):
         return None
     rng = np.random.default_rng(w.u0_seed)
     return rng.uniform(-w.u0_amp, w.u0_amp, size=(w.D, w.nz, w.ny, w.nx))
+
+
+def random_velocity(D, nz, ny, nx, amp=1e-3, seed=0):
+    """[D, nz, ny, nx] float64 i.i.d. uniform(-amp, amp)."""
+    return np.random.default_rng(seed).uniform(-amp, amp, size=(D, nz, ny, nx))
 
 
 def random_state(Q, nx, ny, nz, amp=1e-3, seed=0):

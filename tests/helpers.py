@@ -27,6 +27,8 @@ def make_oracle(w: W.Workload, complex_step=False, u0=None, init=True):
         o.set_darcy(w.darcy)
     if w.mhd is not None:
         o.set_mhd(w.mhd[:3], w.mhd[3], w.mhd[4])
+        if w.lorentz:
+            o.set_lorentz_force(True)
     o.groups = max(o.groups, w.groups)
     if init:
         o.init_equilibrium(W.initial_velocity(w) if u0 is None else u0)

@@ -36,8 +36,8 @@ def moments(d, rho0, name, c):
 @pytest.mark.parametrize("lat,name", [(oracle.D2Q9, "D2Q9"), (oracle.D3Q19, "D3Q19")])
 @pytest.mark.parametrize("mhd", [False, True])
 def test_equilibrium_moments(lat, name, mhd):
-    if mhd and lat == oracle.D2Q9:
-        pytest.skip("the three-dimensional MHD equilibrium only")
+    """Two-dimensional MHD (planar B) leaves out -c^2 B^2 / 6: with it the
+    magnetic part would carry mass (sum w c^2 B^2 / 6 != 0)."""
     dx, dt = 0.51, 0.3
     c = dx / dt
     nx, ny, nz = 3, 4, (1 if lat == oracle.D2Q9 else 2)
@@ -45,7 +45,7 @@ def test_equilibrium_moments(lat, name, mhd):
     o = oracle.Oracle(lat, nx, ny, nz, 0.9, dx, dt, oracle.GUO)
     rho0 = 1.3
     o.set_rho0(rho0)
-    B = np.array([0.03, -0.05, 0.02])
+    B = np.array([0.03, -0.05, 0.02 if D == 3 else 0.0])
     mu = 1.7
     if mhd:
         o.set_mhd(B, mu, 0.8)
