@@ -29,6 +29,7 @@
  *   D3Q19: 0 rest; 1,2 +-x; 3,4 +-y; 5,6 +-z; 7,8 +-(x+y); 9,10 +-(x-y);
  *          11,12 +-(x+z); 13,14 +-(x-z); 15,16 +-(y+z); 17,18 +-(y-z)
  *   D3Q7 (induction): 0 rest; 1,2 +-x; 3,4 +-y; 5,6 +-z
+ *   D2Q5 (induction, two dimensions): directions 0-4 of D3Q7
  */
 #ifndef LBM_H
 #define LBM_H
@@ -133,11 +134,31 @@ int lbm_set_darcy(lbm_ctx* ctx, double sigma);
  * outputs (0 = off, the default).  Any time. */
 int lbm_set_artefact(lbm_ctx* ctx, int include_Eij);
 
-/* MHD equilibrium of Eq. (10) (D3Q19 only, F32/F64 storage) with a D3Q7
- * vector-distribution induction lattice (relaxation time tau_m > 1/2,
- * magnetic diffusivity dt c^2 (tau_m - 1/2) / 4).  All walls are insulating:
- * B = B0 on them.  mu is the magnetic permeability. */
+/* MHD (Section 4; F32/F64 storage) with a vector-distribution induction
+ * lattice (relaxation time tau_m > 1/2, magnetic diffusivity
+ * dt c^2 (tau_m - 1/2) / 4): D3Q7 with three field components on D3Q19; on
+ * D2Q9 its planar restriction (rest weight 1/2, 1/8 per axis link) with the
+ * two in-plane components, which needs B0z = 0.  All walls are insulating:
+ * B = B0 on them.  mu is the magnetic permeability.  The coupling is the
+ * paper's by default (magnetic stress in the equilibrium, Eq. 10; in two
+ * dimensions without its -c^2 B^2 / 6 term); see lbm_set_mhd_coupling. */
 int lbm_set_mhd(lbm_ctx* ctx, double B0x, double B0y, double B0z, double mu, double tau_m);
+
+/* MHD coupling (Section 4 names three approaches; two are provided):
+ *   LBM_MHD_EQUILIBRIUM   the Lorentz force as minus the divergence of the
+ *                         Maxwell stress in f^eq (Eq. 10); P of Eq. (25)
+ *                         then holds -L, which the Maxwell variant of
+ *                         lbm_wall_force removes;
+ *   LBM_MHD_LORENTZ_FORCE f^eq hydrodynamic and the Lorentz force J x B
+ *                         added to the body force of the force model; P
+ *                         holds no -L and the balance record's body force
+ *                         includes the Lorentz force (text after Eq. 36).
+ * J = curl B / mu comes from the non-equilibrium part of the induction
+ * distributions' first moment (-tau_m dt theta c^2 grad B to first order),
+ * with the velocity's own half-force solved for in closed form.  After
+ * lbm_set_mhd; set-up only; not with lbm_set_darcy (LBM_EINVAL). */
+enum { LBM_MHD_EQUILIBRIUM = 0, LBM_MHD_LORENTZ_FORCE = 1 };
+int lbm_set_mhd_coupling(lbm_ctx* ctx, int kind);
 
 /* HIP stream (hipStream_t) on which all later work of the context is
  * enqueued, e.g. torch.cuda.current_stream().cuda_stream; NULL = the
@@ -156,7 +177,8 @@ int lbm_init_equilibrium(lbm_ctx* ctx, const double* u0_host);
 int lbm_set_state(lbm_ctx* ctx, const double* d_host);
 int lbm_get_state(lbm_ctx* ctx, double* d_host);
 
-/* Induction distributions g [7][3][nz][ny][nx] (absolute values). MHD only. */
+/* Induction distributions g [K][NB][nz][ny][nx] (absolute values; K = 7,
+ * NB = 3 on D3Q19, K = 5, NB = 2 on D2Q9).  MHD only. */
 int lbm_get_induction(lbm_ctx* ctx, double* g_host);
 
 /* ---- the hot path ---- */

@@ -270,44 +270,47 @@ __device__ __forceinline__ void write_f1(typename Stor<P>::E* __restrict__ f, co
   }
 }
 
-// Same pattern for the 21 induction planes (7 directions x 3 components).
-template <int P, int PAR, bool BND, class AD>
+// Same pattern for the induction planes (K directions x NB components,
+// plane NB k + i).
+template <class L, int P, int PAR, bool BND, class AD>
 __device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g, const AD& A, uint32_t mask,
-                                       typename Stor<P>::T (&h)[7][3]) {
+                                       typename Stor<P>::T (&h)[Ind<L>::K][Ind<L>::NB]) {
   using S = Stor<P>;
+  constexpr int NB = Ind<L>::NB;
 #pragma unroll
-  for (int k = 0; k < 7; ++k) {
+  for (int k = 0; k < Ind<L>::K; ++k) {
     const int kb = opp(k);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < NB; ++i) {
       const typename S::E* ptr;
       if (PAR == 0) {
-        ptr = A.template ptr<D3Q19>(g, 3 * k + i, -1);
+        ptr = A.template ptr<L>(g, NB * k + i, -1);
       } else {
-        ptr = A.template ptr<D3Q19>(g, 3 * kb + i, kb);
+        ptr = A.template ptr<L>(g, NB * kb + i, kb);
       }
-      if (PAR == 1 && BND) ptr = pick((mask >> kb) & 1u, A.template ptr<D3Q19>(g, 3 * k + i, -1), ptr);
+      if (PAR == 1 && BND) ptr = pick((mask >> kb) & 1u, A.template ptr<L>(g, NB * k + i, -1), ptr);
       h[k][i] = S::ld(ptr);
     }
   }
 }
 
-template <int P, int PAR, bool BND, class AD>
+template <class L, int P, int PAR, bool BND, class AD>
 __device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, const AD& A, uint32_t mask,
-                                        const typename Stor<P>::T (&h)[7][3]) {
+                                        const typename Stor<P>::T (&h)[Ind<L>::K][Ind<L>::NB]) {
   using S = Stor<P>;
+  constexpr int NB = Ind<L>::NB;
 #pragma unroll
-  for (int k = 0; k < 7; ++k) {
+  for (int k = 0; k < Ind<L>::K; ++k) {
     const int kb = opp(k);
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < NB; ++i) {
       typename S::E* ptr;
       if (PAR == 0) {
-        ptr = A.template ptr<D3Q19>(g, 3 * kb + i, -1);
+        ptr = A.template ptr<L>(g, NB * kb + i, -1);
       } else {
-        ptr = A.template ptr<D3Q19>(g, 3 * k + i, k);
+        ptr = A.template ptr<L>(g, NB * k + i, k);
       }
-      if (PAR == 1 && BND) ptr = pick((mask >> k) & 1u, A.template ptr<D3Q19>(g, 3 * kb + i, -1), ptr);
+      if (PAR == 1 && BND) ptr = pick((mask >> k) & 1u, A.template ptr<L>(g, NB * kb + i, -1), ptr);
       S::st(ptr, h[k][i]);
     }
   }

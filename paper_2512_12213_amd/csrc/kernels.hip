@@ -34,12 +34,19 @@ struct Macro {
   T b[3];
 };
 
+// MHD couplings (template parameter MHD): 0 none; 1 magnetic stress in the
+// equilibrium (Eq. 10, the paper's approach); 2 Lorentz force through the
+// force term with a hydrodynamic equilibrium (the third approach of Section 4).
+//
 // Moments (Section 2), model velocities, Pi^neq (cheap form after Eq. 9,
-// with the Maxwell stress of Eq. 11 under MHD), Smagorinsky tau.
-// Under MHD the stored deviations are taken from w rho0 + phi(B0) (the rest
-// equilibrium in the uniform field), db = b - b0 is the induced field.
-template <class L, class T, bool MHD, bool NEED_PI>
-__device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T Ay, T Az, const T (&db)[3], Macro<T>& m) {
+// with the Maxwell stress of Eq. 11 under coupling 1), Smagorinsky tau.
+// Under coupling 1 the stored deviations are taken from w rho0 + phi(B0)
+// (the rest equilibrium in the uniform field); db = b - b0 is the induced
+// field and lam (coupling 2) the antisymmetric first moment of the induction
+// distributions, lam_i = eps_ilm sum_k e_kl h_km.
+template <class L, class T, int MHD, bool NEED_PI>
+__device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T Ay, T Az, const T (&db)[3],
+                                      const T (&lam)[3], Macro<T>& m) {
   // Moments from sums and differences of opposite populations (q odd, q + 1):
   // s = d_q + d_q+1 carries the even moments (rho, second moments), t = d_q -
   // d_q+1 the odd ones (momentum).  Pairing values of like size first keeps
@@ -78,13 +85,29 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
   m.A[0] = (Ax - ds * m.U[0]) * di;
   m.A[1] = (Ay - ds * m.U[1]) * di;
   m.A[2] = (Az - ds * m.U[2]) * di;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) m.b[k] = (T)p.b0[k] + db[k];
+  if (MHD == 2) {
+    // Lorentz force J x B / rho.  The induction moment's non-equilibrium
+    // part gives curl b (first order Chapman-Enskog); with the velocity's own
+    // half-force the current solves [tau_m theta I + (b^2 I - b b^T) / rho] J
+    // = r, r = -lam + 2 U* x b, U* = U + A_ext / 2 (dimensionless), and the
+    // force needs only J x b = (r x b) / (tau_m theta + b^2 / rho).
+    const T* b = m.b;
+    const T us[3] = {m.U[0] + T(0.5) * m.A[0], m.U[1] + T(0.5) * m.A[1], m.U[2] + T(0.5) * m.A[2]};
+    const T r[3] = {-lam[0] + T(2) * (us[1] * b[2] - us[2] * b[1]), -lam[1] + T(2) * (us[2] * b[0] - us[0] * b[2]),
+                    -lam[2] + T(2) * (us[0] * b[1] - us[1] * b[0])};
+    const T ia = rcp(m.rho * (T)p.tm_theta + (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]));
+    m.A[0] += (r[1] * b[2] - r[2] * b[1]) * ia;
+    m.A[1] += (r[2] * b[0] - r[0] * b[2]) * ia;
+    m.A[2] += (r[0] * b[1] - r[1] * b[0]) * ia;
+  }
   const T lEq = (T)p.lEq;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     m.V[k] = m.U[k] + T(0.5) * m.A[k];
     m.Ue[k] = m.U[k] + lEq * m.A[k];
     m.Je[k] = m.J[k] + lEq * m.rho * m.A[k];
-    m.b[k] = (T)p.b0[k] + db[k];
   }
   m.tau = (T)p.tau0;
   m.itau = (T)p.inv_tau0;
@@ -111,7 +134,7 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
     m.pi[3] = sxy - rho * m.Ue[0] * m.Ue[1];
     m.pi[4] = L::D == 3 ? sxz - rho * m.Ue[0] * m.Ue[2] : T(0);
     m.pi[5] = L::D == 3 ? syz - rho * m.Ue[1] * m.Ue[2] : T(0);
-    if (MHD) {
+    if (MHD == 1) {
       // the stored second moment lacks L(b0); subtract L(b) - L(b0),
       // L_ij = b^2 delta_ij / 2 - b_i b_j, formed from db to keep precision
       const T bs[3] = {m.b[0] + (T)p.b0[0], m.b[1] + (T)p.b0[1], m.b[2] + (T)p.b0[2]};  // b + b0
@@ -163,7 +186,7 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
 // part's moments are not scaled by the weights' own rounding.
 // sink(q, value) receives each post-collision value as soon as it is formed,
 // so that it can be stored at once and its register freed.
-template <class L, class T, bool MHD, class Sink>
+template <class L, class T, int MHD, class Sink>
 __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, const T (&db)[3], const Phys& p,
                                         Sink&& sink) {
   const T rho = m.rho;
@@ -178,7 +201,7 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
   const T quad = (T)p.quad;  // 0 for the Stokes equilibrium
   const T rq = rho * quad, rlq = rl * quad, rl2q = rl2 * quad;
   T bs[3] = {T(0), T(0), T(0)}, db2 = T(0);
-  if (MHD) {
+  if (MHD == 1) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) bs[k] = m.b[k] + (T)p.b0[k];  // b + b0
     db2 = db[0] * bs[0] + db[1] * bs[1] + db[2] * bs[2];     // b^2 - b0^2
@@ -197,11 +220,13 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
     //   rho [(e.ue)^2 9/2 - ue.ue 3/2] - (same at u) + 3 e.(rho lEq A),
     // and the magnetic term phi(b) - phi(b0)
     T Rs = rl * (T(3) * ea) + rlq * (T(9) * eu * ea - T(3) * ua) + rl2q * (T(4.5) * ea * ea - T(1.5) * aa);
-    if (MHD) {
-      // (e.b)^2 - (e.b0)^2 = (e.db)(e.(b + b0))
+    if (MHD == 1) {
+      // (e.b)^2 - (e.b0)^2 = (e.db)(e.(b + b0)); two-dimensional flows have
+      // no -b^2 / 6 term (the text after Eq. 10)
       const T edb = edot<L>(q, db[0], db[1], db[2]);
       const T ebs = edot<L>(q, bs[0], bs[1], bs[2]);
-      Rs += T(4.5) * (T(0.5) * db2 * (T)L::e2(q) - edb * ebs - db2 * T(1.0 / 6.0));
+      const T last = L::D == 3 ? db2 * T(1.0 / 6.0) : T(0);
+      Rs += T(4.5) * (T(0.5) * db2 * (T)L::e2(q) - edb * ebs - last);
     }
     const T euf = edot<L>(q, m.UF[0], m.UF[1], m.UF[2]);
     const T F = cr * w * (T(3) * (ea - ufa) + T(9) * euf * ea);
@@ -215,30 +240,56 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
 
 // Induction lattice: g^eq_{k,i} = W_k [b_i + (e_kj / theta)(V_j b_i - b_j V_i)],
 // stored as deviations from W_k b0_i; relaxation with 1/tau_m.
-template <class T>
-__device__ __forceinline__ void collide_g(T (&h)[7][3], const Macro<T>& m, const Phys& p) {
+template <class L, class T>
+__device__ __forceinline__ void collide_g(T (&h)[Ind<L>::K][Ind<L>::NB], const Macro<T>& m, const Phys& p) {
+  using I = Ind<L>;
   const T itm = (T)p.inv_tau_m;
   const T b[3] = {m.b[0], m.b[1], m.b[2]};
   const T V[3] = {m.V[0], m.V[1], m.V[2]};
   const T b0[3] = {(T)p.b0[0], (T)p.b0[1], (T)p.b0[2]};
 #pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    const T w = (T)D3Q7::w(k);
+  for (int k = 0; k < I::K; ++k) {
+    const T w = (T)I::w(k);
     const int ax = (k - 1) >> 1;           // axis of direction k (k >= 1)
     const T sgn = (k & 1) ? T(1) : T(-1);  // +1 for odd k
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < I::NB; ++i) {
       T heq = w * (b[i] - b0[i]);
-      if (k > 0) heq += w * sgn * T(1.0 / D3Q7::theta) * (V[ax] * b[i] - b[ax] * V[i]);
+      if (k > 0) heq += w * sgn * T(1.0 / I::theta) * (V[ax] * b[i] - b[ax] * V[i]);
       h[k][i] = h[k][i] + (heq - h[k][i]) * itm;
     }
+  }
+}
+
+// Induced field db = sum_k h_k and the antisymmetric first moment
+// lam_i = eps_ilm Lambda_lm, Lambda_lm = sum_k e_kl h_km = h_{+l,m} - h_{-l,m}.
+template <class L, class T>
+__device__ __forceinline__ void ind_moments(const T (&h)[Ind<L>::K][Ind<L>::NB], T (&db)[3], T (&lam)[3]) {
+  constexpr int NB = Ind<L>::NB;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T s = T(0);
+    if (i < NB) {
+#pragma unroll
+      for (int k = 0; k < Ind<L>::K; ++k) s += h[k][i < NB ? i : 0];
+    }
+    db[i] = s;
+  }
+  if constexpr (NB == 3) {
+    lam[0] = (h[3][2] - h[4][2]) - (h[5][1] - h[6][1]);
+    lam[1] = (h[5][0] - h[6][0]) - (h[1][2] - h[2][2]);
+    lam[2] = (h[1][1] - h[2][1]) - (h[3][0] - h[4][0]);
+  } else {
+    lam[0] = T(0);
+    lam[1] = T(0);
+    lam[2] = (h[1][1] - h[2][1]) - (h[3][0] - h[4][0]);
   }
 }
 
 // ---------------------------------------------------------------------------
 // the fused step
 // ---------------------------------------------------------------------------
-template <class L, int P, bool MHD, int PAR, bool DIAG, bool MAC, bool BND, class AD>
+template <class L, int P, int MHD, int PAR, bool DIAG, bool MAC, bool BND, class AD>
 __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const AD& Af, const AD& Ag, const uint4& rec,
                                             typename Stor<P>::T (&bal)[NBAL],
                                             typename Stor<P>::T (&wacc)[MAXBG][NWALL], uint32_t bgrp) {
@@ -259,20 +310,14 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
     Ay = (T)a.p.A[1];
     Az = (T)a.p.A[2];
   }
-  T h[7][3];
-  T db[3] = {T(0), T(0), T(0)};
+  T h[Ind<L>::K][Ind<L>::NB];
+  T db[3] = {T(0), T(0), T(0)}, lam[3] = {T(0), T(0), T(0)};
   if (MHD) {
-    read_g<P, PAR, BND>((const typename S::E*)a.g, Ag, mask, h);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      T s = T(0);
-#pragma unroll
-      for (int k = 0; k < 7; ++k) s += h[k][i];  // B - B0 = sum_k (g_k - W_k B0)
-      db[i] = s;
-    }
+    read_g<L, P, PAR, BND>((const typename S::E*)a.g, Ag, mask, h);
+    ind_moments<L, T>(h, db, lam);  // B - B0 = sum_k (g_k - W_k B0)
   }
   Macro<T> m;
-  macro<L, T, MHD, false>(d, a.p, Ax, Ay, Az, db, m);
+  macro<L, T, MHD, false>(d, a.p, Ax, Ay, Az, db, lam, m);
   if (MAC) {
     // density and velocity of the pre-step state, for the adjoint
     T* mo = (T*)a.mac;
@@ -318,21 +363,21 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
     write_f1<L, P, PAR, BND>(fo, Af, mask, a.p, q, v);
   });
   if (MHD) {
-    collide_g<T>(h, m, a.p);
+    collide_g<L, T>(h, m, a.p);
     if (BND) {
       // insulating walls: anti-bounce-back to B = B0 (zero deviation)
 #pragma unroll
-      for (int k = 1; k < 7; ++k)
+      for (int k = 1; k < Ind<L>::K; ++k)
         if ((mask >> k) & 1u) {
 #pragma unroll
-          for (int i = 0; i < 3; ++i) h[k][i] = -h[k][i];
+          for (int i = 0; i < Ind<L>::NB; ++i) h[k][i] = -h[k][i];
         }
     }
-    write_g<P, PAR, BND>((typename S::E*)a.g, Ag, mask, h);
+    write_g<L, P, PAR, BND>((typename S::E*)a.g, Ag, mask, h);
   }
 }
 
-template <class L, int P, bool MHD, int PAR, bool DIAG, bool RU, bool MAC = false>
+template <class L, int P, int MHD, int PAR, bool DIAG, bool RU, bool MAC = false>
 __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   using T = typename Stor<P>::T;
   const Geom& g = a.geo;
@@ -363,14 +408,14 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
     if (!(rec.x >> 31)) {
       if (RU) {
         const AddrR Af = addr_r(g, x, y, z, L::Q);
-        const AddrR Ag = addr_r(g, x, y, z, MHD ? 21 : L::Q);
+        const AddrR Ag = addr_r(g, x, y, z, MHD ? Ind<L>::K * Ind<L>::NB : L::Q);
         if (rr < 0)
           node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
         else
           node_update<L, P, MHD, PAR, DIAG, MAC, true>(a, n, Af, Ag, rec, bal, wacc, bgrp);
       } else {
         const AddrG Af = addr_g(g, x, y, z, r, L::Q);
-        const AddrG Ag = addr_g(g, x, y, z, r, MHD ? 21 : L::Q);
+        const AddrG Ag = addr_g(g, x, y, z, r, MHD ? Ind<L>::K * Ind<L>::NB : L::Q);
         if (rr < 0)
           node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
         else
@@ -390,13 +435,15 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   }
 }
 
-// Magnetic part of the rest equilibrium in the uniform field b0 (Eq. 10).
-template <class L>
+// Magnetic part of the rest equilibrium in the uniform field b0 (Eq. 10; in
+// two dimensions without -b^2 / 6); zero unless the equilibrium carries it.
+template <class L, int MHD>
 __device__ __forceinline__ double mhd_phi0(int q, const Phys& p) {
+  if (MHD != 1) return 0.0;
   const double* b0 = p.b0;
   const double eb = edot<L>(q, b0[0], b0[1], b0[2]);
   const double b2 = b0[0] * b0[0] + b0[1] * b0[1] + b0[2] * b0[2];
-  return 4.5 * L::w(q) * (0.5 * b2 * L::e2(q) - eb * eb - b2 / 6.0);
+  return 4.5 * L::w(q) * (0.5 * b2 * L::e2(q) - eb * eb - (L::D == 3 ? b2 / 6.0 : 0.0));
 }
 
 // ---------------------------------------------------------------------------
@@ -410,7 +457,7 @@ __device__ __forceinline__ bool node_solid(const DiagArgs& a, uint32_t n) {
 }
 
 // All diagnostic arithmetic is FP64, applied to the stored values.
-template <class L, int P, bool MHD, int PAR>
+template <class L, int P, int MHD, int PAR>
 __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
   using S = Stor<P>;
   using T = double;
@@ -422,15 +469,15 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
     uint32_t x, y, z, r;
     coords(g, n, x, y, z, r);
     const AddrG Af = addr_g(g, x, y, z, r, L::Q);
-    const AddrG Ag = addr_g(g, x, y, z, r, 21);
+    const AddrG Ag = addr_g(g, x, y, z, r, Ind<L>::K * Ind<L>::NB);
     const Offs on = offsets(g, x, y, z, (uint64_t)g.nx);  // node-index offsets
     const int rr = a.rowrec[r];
     const uint4 rec = rr >= 0 ? a.rec[rr + x] : make_uint4(0u, 0u, 0u, 0u);
     const bool solid = rec.x >> 31;
     T d[L::Q] = {};
-    T h[7][3] = {};
+    T h[Ind<L>::K][Ind<L>::NB] = {};
     T b[3] = {T(0), T(0), T(0)};
-    T db[3] = {T(0), T(0), T(0)};
+    T db[3] = {T(0), T(0), T(0)}, lam[3] = {T(0), T(0), T(0)};
     Macro<T> m = {};
     if (!solid) {
       TS ds[L::Q];
@@ -449,21 +496,15 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
         Az = (T)a.p.A[2];
       }
       if (MHD) {
-        TS hs[7][3];
-        read_g<P, PAR, true>((const typename S::E*)a.g, Ag, rec.x, hs);
+        TS hs[Ind<L>::K][Ind<L>::NB];
+        read_g<L, P, PAR, true>((const typename S::E*)a.g, Ag, rec.x, hs);
 #pragma unroll
-        for (int k = 0; k < 7; ++k)
+        for (int k = 0; k < Ind<L>::K; ++k)
 #pragma unroll
-          for (int i = 0; i < 3; ++i) h[k][i] = (T)hs[k][i];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          T s = T(0);
-#pragma unroll
-          for (int k = 0; k < 7; ++k) s += h[k][i];
-          db[i] = s;
-        }
+          for (int i = 0; i < Ind<L>::NB; ++i) h[k][i] = (T)hs[k][i];
+        ind_moments<L, T>(h, db, lam);
       }
-      macro<L, T, MHD, true>(d, a.p, Ax, Ay, Az, db, m);
+      macro<L, T, MHD, true>(d, a.p, Ax, Ay, Az, db, lam, m);
 #pragma unroll
       for (int i = 0; i < 3; ++i) b[i] = m.b[i];
     }
@@ -471,17 +512,18 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
 #pragma unroll
       for (int q = 0; q < L::Q; ++q) {
         double v = (double)d[q];
-        if (MHD) v += mhd_phi0<L>(q, a.p);  // back to f - w rho0
+        v += mhd_phi0<L, MHD>(q, a.p);  // back to f - w rho0
         a.state[(uint64_t)q * g.N + n] = solid ? 0.0 : v;
       }
     }
     if (a.gstate) {
       // absolute g in units of B (the host rescales by c sqrt(mu))
 #pragma unroll
-      for (int k = 0; k < 7; ++k)
+      for (int k = 0; k < Ind<L>::K; ++k)
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-          a.gstate[(uint64_t)(3 * k + i) * g.N + n] = solid ? 0.0 : (double)h[k][i] + D3Q7::w(k) * a.p.b0[i];
+        for (int i = 0; i < Ind<L>::NB; ++i)
+          a.gstate[(uint64_t)(Ind<L>::NB * k + i) * g.N + n] =
+              solid ? 0.0 : (double)h[k][i] + Ind<L>::w(k) * a.p.b0[i];
     }
     if (a.rho) a.rho[n] = solid ? 0.0 : (double)m.rho;
     if (a.vel) {
@@ -682,7 +724,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ibb_reduce(const double* __restric
 // rho = rho0 + sum_a f_rel_a = rho0 + sum_a V_a + rho K, with V the values as
 // read and K = sum over wall links of 6 w (e.u_w).  Induction distributions
 // likewise (anti-bounce-back: the stored value is the negated relaxed one).
-template <class L, int P, bool MHD, int PAR>
+template <class L, int P, int MHD, int PAR>
 __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
   using S = Stor<P>;
   using E = typename S::E;
@@ -693,7 +735,7 @@ __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
   uint32_t x, y, z, r;
   coords(g, n, x, y, z, r);
   const AddrG Af = addr_g(g, x, y, z, r, L::Q);
-  const AddrG Ag = addr_g(g, x, y, z, r, 21);
+  const AddrG Ag = addr_g(g, x, y, z, r, Ind<L>::K * Ind<L>::NB);
   const int rr = a.rowrec[r];
   const uint4 rec = rr >= 0 ? a.rec[rr + x] : make_uint4(0u, 0u, 0u, 0u);
   const uint32_t mask = rec.x;
@@ -730,15 +772,16 @@ __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
       db[q] = 0.5 * (rel + (double)d1[q]);
     }
     if (MHD) {
-      TS h1[7][3];
-      read_g<P, PAR, true>((const E*)a.g, Ag, mask, h1);
+      constexpr int NB = Ind<L>::NB;
+      TS h1[Ind<L>::K][NB];
+      read_g<L, P, PAR, true>((const E*)a.g, Ag, mask, h1);
 #pragma unroll
-      for (int k = 0; k < 7; ++k) {
+      for (int k = 0; k < Ind<L>::K; ++k) {
         const bool wall = k > 0 && ((mask >> k) & 1u);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const E* ptr = (PAR == 1 || wall) ? Ag.template ptr<D3Q19>((const E*)a.g, 3 * opp(k) + i, -1)
-                                            : Ag.template ptr<D3Q19>((const E*)a.g, 3 * k + i, k);
+        for (int i = 0; i < NB; ++i) {
+          const E* ptr = (PAR == 1 || wall) ? Ag.template ptr<L>((const E*)a.g, NB * opp(k) + i, -1)
+                                            : Ag.template ptr<L>((const E*)a.g, NB * k + i, k);
           double hr = (double)S::ld(ptr);
           if (wall) hr = -hr;
           Bh[i] += 0.5 * (hr + (double)h1[k][i]);
@@ -753,7 +796,7 @@ __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
       double v = db[q];
-      if (MHD && !solid) v += mhd_phi0<L>(q, a.p);  // back to f - w rho0
+      if (!solid) v += mhd_phi0<L, MHD>(q, a.p);  // back to f - w rho0
       a.fbar[(uint64_t)q * g.N + n] = v;
     }
   }
@@ -782,15 +825,16 @@ __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
     for (int k = 0; k < L::D; ++k) a.vel[(uint64_t)k * g.N + n] = solid ? 0.0 : u[k] * a.c;
   }
   if (a.sigma) {
-    // -sum e e f_bar + p_bar delta + rho_bar u u (+ L(B_bar)); the stored
-    // deviations exclude w rho0 (and phi(B0), whose second moment is L(B0))
+    // -sum e e f_bar + p_bar delta + rho_bar u u (+ L(B_bar) when the
+    // equilibrium carries it); the stored deviations exclude w rho0 (and then
+    // phi(B0), whose second moment is L(B0))
     const int ci[6] = {0, 1, 2, 0, 0, 1}, cj[6] = {0, 1, 2, 1, 2, 2};
     double sg[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       const int i = ci[c], k = cj[c];
       double v = -m2[c] + (i == k ? srho / 3.0 : 0.0) + a.p.quad * rho * u[i] * u[k];
-      if (MHD) {
+      if (MHD == 1) {
         // L(b) - L(b0) with b = b0 + Bh, L_ij = b^2 delta_ij / 2 - b_i b_j
         const double* b0 = a.p.b0;
         const double bs[3] = {2.0 * b0[0] + Bh[0], 2.0 * b0[1] + Bh[1], 2.0 * b0[2] + Bh[2]};  // b + b0
@@ -805,7 +849,7 @@ __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
   }
 }
 
-template <class L, int P, bool MHD>
+template <class L, int P, int MHD>
 __global__ __launch_bounds__(NTHREADS) void k_init(const InitArgs a) {
   using S = Stor<P>;
   using T = typename S::T;
@@ -827,7 +871,7 @@ __global__ __launch_bounds__(NTHREADS) void k_init(const InitArgs a) {
     if (!solid) {
       if (a.state) {
         v = a.state[(uint64_t)q * g.N + n];
-        if (MHD) v -= mhd_phi0<L>(q, a.p);  // stored relative to the rest equilibrium in B0
+        v -= mhd_phi0<L, MHD>(q, a.p);  // stored relative to the rest equilibrium in B0
       } else {
         // f^eq(rho0, u0) (+ phi(B0), which the stored deviation excludes)
         const double w = L::w(q);
@@ -841,14 +885,15 @@ __global__ __launch_bounds__(NTHREADS) void k_init(const InitArgs a) {
     S::st(f + ((uint64_t)r * (L::Q * g.nx) + x) + q * g.nx, s);
   }
   if (MHD) {
+    using I = Ind<L>;
     typename S::E* gg = (typename S::E*)a.g;
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < I::K; ++k) {
       const int ax = (k - 1) >> 1;
       const double sgn = (k & 1) ? 1.0 : -1.0;
-      for (int i = 0; i < 3; ++i) {
+      for (int i = 0; i < I::NB; ++i) {
         double hv = 0.0;
-        if (!solid && k > 0) hv = D3Q7::w(k) * sgn * (1.0 / D3Q7::theta) * (U[ax] * b0[i] - b0[ax] * U[i]);
-        S::st(gg + ((uint64_t)r * (21 * g.nx) + x) + (3 * k + i) * g.nx, (T)hv);
+        if (!solid && k > 0) hv = I::w(k) * sgn * (1.0 / I::theta) * (U[ax] * b0[i] - b0[ax] * U[i]);
+        S::st(gg + ((uint64_t)r * (I::K * I::NB * g.nx) + x) + (I::NB * k + i) * g.nx, (T)hv);
       }
     }
   }
@@ -883,7 +928,7 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // launchers (called by the host library)
 // ---------------------------------------------------------------------------
-template <class L, int P, bool MHD, bool RU>
+template <class L, int P, int MHD, bool RU>
 static void launch_step_ru(const StepArgs& a, int parity, bool diag, uint32_t nb, hipStream_t st) {
   if (parity == 0) {
     if (diag)
@@ -898,7 +943,7 @@ static void launch_step_ru(const StepArgs& a, int parity, bool diag, uint32_t nb
   }
 }
 
-template <class L, int P, bool MHD>
+template <class L, int P, int MHD>
 static hipError_t launch_step_t(const StepArgs& a, int parity, bool diag, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
   if (a.geo.nx % 64 == 0)
@@ -914,7 +959,7 @@ template <class L, int P>
 static hipError_t launch_step_mac_t(const StepArgs& a, int parity, bool diag, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
   const bool ru = a.geo.nx % 64 == 0;
-#define LBM_MAC(PAR, DG, RU) k_step<L, P, false, PAR, DG, RU, true><<<nb, NTHREADS, 0, st>>>(a)
+#define LBM_MAC(PAR, DG, RU) k_step<L, P, 0, PAR, DG, RU, true><<<nb, NTHREADS, 0, st>>>(a)
   if (ru) {
     if (parity == 0) {
       if (diag) LBM_MAC(0, true, true); else LBM_MAC(0, false, true);
@@ -932,7 +977,7 @@ static hipError_t launch_step_mac_t(const StepArgs& a, int parity, bool diag, hi
   return hipGetLastError();
 }
 
-template <class L, int P, bool MHD>
+template <class L, int P, int MHD>
 static hipError_t launch_diag_t(const DiagArgs& a, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
   if (a.parity == 0)
@@ -942,7 +987,7 @@ static hipError_t launch_diag_t(const DiagArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <class L, int P, bool MHD>
+template <class L, int P, int MHD>
 static hipError_t launch_ibb_t(const IbbArgs& a, hipStream_t st) {
   const uint32_t nb = (a.M + NTHREADS - 1) / NTHREADS;
   if (a.parity == 0)
@@ -952,7 +997,7 @@ static hipError_t launch_ibb_t(const IbbArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <class L, int P, bool MHD>
+template <class L, int P, int MHD>
 static hipError_t launch_half_t(const HalfArgs& a, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
   if (a.parity == 0)
@@ -962,36 +1007,44 @@ static hipError_t launch_half_t(const HalfArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <class L, int P, bool MHD>
+template <class L, int P, int MHD>
 static hipError_t launch_init_t(const InitArgs& a, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
   k_init<L, P, MHD><<<nb, NTHREADS, 0, st>>>(a);
   return hipGetLastError();
 }
 
+// mhd: 0 none, 1 magnetic stress in the equilibrium, 2 Lorentz force through
+// the force term (F64 / F32 storage only under MHD).
 #define LBM_DISPATCH(FN, lattice, prec, mhd, ...)                                          \
   do {                                                                                       \
+    if (mhd) {                                                                               \
+      const bool d64 = prec == S_F64;                                                        \
+      if (lattice == 0) {                                                                    \
+        if (mhd == 1) return d64 ? FN<D2Q9, S_F64, 1>(__VA_ARGS__) : FN<D2Q9, S_F32, 1>(__VA_ARGS__); \
+        return d64 ? FN<D2Q9, S_F64, 2>(__VA_ARGS__) : FN<D2Q9, S_F32, 2>(__VA_ARGS__);      \
+      }                                                                                      \
+      if (mhd == 1) return d64 ? FN<D3Q19, S_F64, 1>(__VA_ARGS__) : FN<D3Q19, S_F32, 1>(__VA_ARGS__); \
+      return d64 ? FN<D3Q19, S_F64, 2>(__VA_ARGS__) : FN<D3Q19, S_F32, 2>(__VA_ARGS__);      \
+    }                                                                                        \
     if (lattice == 0) {                                                                      \
       switch (prec) {                                                                        \
-        case S_F64: return FN<D2Q9, S_F64, false>(__VA_ARGS__);                              \
-        case S_F32: return FN<D2Q9, S_F32, false>(__VA_ARGS__);                              \
-        case S_F16: return FN<D2Q9, S_F16, false>(__VA_ARGS__);                              \
-        default: return FN<D2Q9, S_BF16, false>(__VA_ARGS__);                                \
+        case S_F64: return FN<D2Q9, S_F64, 0>(__VA_ARGS__);                                  \
+        case S_F32: return FN<D2Q9, S_F32, 0>(__VA_ARGS__);                                  \
+        case S_F16: return FN<D2Q9, S_F16, 0>(__VA_ARGS__);                                  \
+        default: return FN<D2Q9, S_BF16, 0>(__VA_ARGS__);                                    \
       }                                                                                      \
-    } else if (mhd) {                                                                        \
-      if (prec == S_F64) return FN<D3Q19, S_F64, true>(__VA_ARGS__);                         \
-      return FN<D3Q19, S_F32, true>(__VA_ARGS__);                                            \
     } else {                                                                                 \
       switch (prec) {                                                                        \
-        case S_F64: return FN<D3Q19, S_F64, false>(__VA_ARGS__);                             \
-        case S_F32: return FN<D3Q19, S_F32, false>(__VA_ARGS__);                             \
-        case S_F16: return FN<D3Q19, S_F16, false>(__VA_ARGS__);                             \
-        default: return FN<D3Q19, S_BF16, false>(__VA_ARGS__);                               \
+        case S_F64: return FN<D3Q19, S_F64, 0>(__VA_ARGS__);                                 \
+        case S_F32: return FN<D3Q19, S_F32, 0>(__VA_ARGS__);                                 \
+        case S_F16: return FN<D3Q19, S_F16, 0>(__VA_ARGS__);                                 \
+        default: return FN<D3Q19, S_BF16, 0>(__VA_ARGS__);                                   \
       }                                                                                      \
     }                                                                                        \
   } while (0)
 
-hipError_t launch_step(int lattice, int prec, bool mhd, const StepArgs& a, int parity, bool diag, hipStream_t st) {
+hipError_t launch_step(int lattice, int prec, int mhd, const StepArgs& a, int parity, bool diag, hipStream_t st) {
   LBM_DISPATCH(launch_step_t, lattice, prec, mhd, a, parity, diag, st);
 }
 
@@ -1004,17 +1057,17 @@ hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity,
                        : launch_step_mac_t<D3Q19, S_F32>(a, parity, diag, st);
 }
 
-hipError_t launch_diag(int lattice, int prec, bool mhd, const DiagArgs& a, hipStream_t st) {
+hipError_t launch_diag(int lattice, int prec, int mhd, const DiagArgs& a, hipStream_t st) {
   LBM_DISPATCH(launch_diag_t, lattice, prec, mhd, a, st);
 }
 
-hipError_t launch_half(int lattice, int prec, bool mhd, const HalfArgs& a, hipStream_t st) {
+hipError_t launch_half(int lattice, int prec, int mhd, const HalfArgs& a, hipStream_t st) {
   LBM_DISPATCH(launch_half_t, lattice, prec, mhd, a, st);
 }
 
 hipError_t launch_ibb(int lattice, int prec, const IbbArgs& a, hipStream_t st) {
   if (a.M == 0) return hipSuccess;
-  LBM_DISPATCH(launch_ibb_t, lattice, prec, false, a, st);
+  LBM_DISPATCH(launch_ibb_t, lattice, prec, 0, a, st);
 }
 
 hipError_t launch_ibb_reduce(int lattice, const double* delta, const uint8_t* grp, uint32_t M, int G, double* out,
@@ -1026,7 +1079,7 @@ hipError_t launch_ibb_reduce(int lattice, const double* delta, const uint8_t* gr
   return hipGetLastError();
 }
 
-hipError_t launch_init(int lattice, int prec, bool mhd, const InitArgs& a, hipStream_t st) {
+hipError_t launch_init(int lattice, int prec, int mhd, const InitArgs& a, hipStream_t st) {
   LBM_DISPATCH(launch_init_t, lattice, prec, mhd, a, st);
 }
 

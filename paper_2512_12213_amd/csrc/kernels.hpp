@@ -35,12 +35,13 @@ struct Phys {
   double darcy_inv;    // 1 / (1 + sigma dt / 2)
   double b0[3];        // MHD B0 / (c sqrt(mu))
   double inv_tau_m;
+  double tm_theta;     // tau_m theta of the induction lattice (Lorentz-force coupling)
   float scale[19], inv_scale[19];  // storage scaling per direction
 };
 
 struct StepArgs {
   void* f;                 // distributions, row-blocked [ny nz][Q][nx]
-  void* g;                 // induction deviations, row-blocked [ny nz][21][nx] (MHD) or null
+  void* g;                 // induction deviations, row-blocked [ny nz][K NB][nx] (MHD) or null
   const float* afield;     // [3][N] or null
   const uint4* rec;        // boundary records: x = solid-link mask (bit 31: node solid), y..w = group nibbles
   const int* rowrec;       // per row: index of the row's first record, or -1

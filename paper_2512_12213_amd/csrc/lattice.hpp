@@ -70,14 +70,25 @@ struct D3Q19 {
   __host__ __device__ static constexpr double w(int q) { return e2(q) == 0 ? 1.0 / 3.0 : (e2(q) == 1 ? 1.0 / 18.0 : 1.0 / 36.0); }
 };
 
-// D3Q7 shares the first seven D3Q19 directions.
-struct D3Q7 {
-  static constexpr int Q = 7;
-  __host__ __device__ static constexpr int ex(int q) { return D3Q19::ex(q); }
-  __host__ __device__ static constexpr int ey(int q) { return D3Q19::ey(q); }
-  __host__ __device__ static constexpr int ez(int q) { return D3Q19::ez(q); }
-  __host__ __device__ static constexpr double w(int q) { return q == 0 ? 0.25 : 0.125; }
-  static constexpr double theta = 0.25;  // sum_k W_k e_k e_k = theta c^2 I
+// Induction lattice of a flow lattice.  Its direction k is the flow
+// lattice's direction k (rest, then +-x, +-y, +-z), so that wall masks and
+// neighbour offsets are shared.  D3Q19 pairs with D3Q7 and three field
+// components; D2Q9 with the planar restriction of D3Q7 (the two z links
+// folded into the rest weight: 1/4 + 2/8 = 1/2) and the two in-plane
+// components.  Both have sum_k W_k e_k e_k = theta c^2 I, theta = 1/4.
+template <class L>
+struct Ind;
+template <>
+struct Ind<D3Q19> {
+  static constexpr int K = 7, NB = 3;
+  __host__ __device__ static constexpr double w(int k) { return k == 0 ? 0.25 : 0.125; }
+  static constexpr double theta = 0.25;
+};
+template <>
+struct Ind<D2Q9> {
+  static constexpr int K = 5, NB = 2;
+  __host__ __device__ static constexpr double w(int k) { return k == 0 ? 0.5 : 0.125; }
+  static constexpr double theta = 0.25;
 };
 
 }  // namespace lbm

@@ -15,13 +15,13 @@
 #include "lattice.hpp"
 
 namespace lbm {
-hipError_t launch_step(int lattice, int prec, bool mhd, const StepArgs& a, int parity, bool diag, hipStream_t st);
-hipError_t launch_diag(int lattice, int prec, bool mhd, const DiagArgs& a, hipStream_t st);
-hipError_t launch_init(int lattice, int prec, bool mhd, const InitArgs& a, hipStream_t st);
+hipError_t launch_step(int lattice, int prec, int mhd, const StepArgs& a, int parity, bool diag, hipStream_t st);
+hipError_t launch_diag(int lattice, int prec, int mhd, const DiagArgs& a, hipStream_t st);
+hipError_t launch_init(int lattice, int prec, int mhd, const InitArgs& a, hipStream_t st);
 hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t ntiles, int mode, int nout, double* out,
                          hipStream_t st);
 hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, bool diag, hipStream_t st);
-hipError_t launch_half(int lattice, int prec, bool mhd, const HalfArgs& a, hipStream_t st);
+hipError_t launch_half(int lattice, int prec, int mhd, const HalfArgs& a, hipStream_t st);
 hipError_t launch_ibb(int lattice, int prec, const IbbArgs& a, hipStream_t st);
 hipError_t launch_ibb_reduce(int lattice, const double* delta, const uint8_t* grp, uint32_t M, int G, double* out,
                              hipStream_t st);
@@ -104,6 +104,7 @@ struct lbm_ctx {
   double darcy = 0;
   int artefact = 0;
   bool mhd = false;
+  bool lorentz = false;  // MHD coupling: Lorentz force through the force term
   double B0[3] = {0, 0, 0}, mu = 1, tau_m = 1;
   int device = 0;
   hipStream_t own = nullptr, stream = nullptr;
@@ -143,6 +144,13 @@ struct lbm_ctx {
 
 namespace {
 
+// MHD coupling as the kernels take it: 0 none, 1 equilibrium, 2 Lorentz force.
+int mhd_mode(const lbm_ctx* h) { return h->mhd ? (h->lorentz ? 2 : 1) : 0; }
+
+// Induction planes per node: D3Q7 x 3 components, or 5 x 2 in two dimensions.
+int ind_planes(const lbm_ctx* h) { return h->lattice == LBM_D2Q9 ? 10 : 21; }
+
+
 Phys make_phys(const lbm_ctx* h) {
   Phys p = {};
   p.rho0 = h->rho0;
@@ -166,6 +174,7 @@ Phys make_phys(const lbm_ctx* h) {
   const double bs = h->mhd ? 1.0 / (h->c * std::sqrt(h->mu)) : 0.0;
   for (int k = 0; k < 3; ++k) p.b0[k] = h->B0[k] * bs;
   p.inv_tau_m = h->mhd ? 1.0 / h->tau_m : 0.0;
+  p.tm_theta = h->mhd ? 0.25 * h->tau_m : 0.0;
   for (int q = 0; q < 19; ++q) {
     double s = 1.0;
     if (q < h->Q) {
@@ -332,7 +341,7 @@ int build_geometry(lbm_ctx* h) {
 int alloc_state(lbm_ctx* h) {
   const size_t eb = elem_bytes(h->prec);
   HIPCHK(h->f.ensure((size_t)h->Q * h->N * eb));
-  if (h->mhd) HIPCHK(h->g.ensure((size_t)21 * h->N * eb));
+  if (h->mhd) HIPCHK(h->g.ensure((size_t)ind_planes(h) * h->N * eb));
   return LBM_OK;
 }
 
@@ -569,6 +578,7 @@ int lbm_set_equilibrium(lbm_ctx* h, int kind) {
 int lbm_set_darcy(lbm_ctx* h, double sigma) {
   if (!h) return fail(LBM_EINVAL, "null context");
   if (!(sigma >= 0) || !std::isfinite(sigma)) return fail(LBM_EINVAL, "sigma must be >= 0");
+  if (sigma > 0 && h->lorentz) return fail(LBM_EINVAL, "porous resistance is not combined with the Lorentz-force coupling");
   h->darcy = sigma;
   h->tape = false;
   return LBM_OK;
@@ -583,7 +593,7 @@ int lbm_set_artefact(lbm_ctx* h, int on) {
 int lbm_set_mhd(lbm_ctx* h, double B0x, double B0y, double B0z, double mu, double tau_m) {
   int rc = setup_guard(h);
   if (rc) return rc;
-  if (h->lattice != LBM_D3Q19) return fail(LBM_EINVAL, "MHD requires D3Q19");
+  if (h->lattice == LBM_D2Q9 && B0z != 0.0) return fail(LBM_EINVAL, "two-dimensional MHD needs B0z = 0");
   if (h->prec == S_F16 || h->prec == S_BF16) return fail(LBM_EINVAL, "MHD supports F32 and F64 storage only");
   if (!(mu > 0) || !(tau_m > 0.5)) return fail(LBM_EINVAL, "need mu > 0 and tau_m > 1/2");
   h->mhd = true;
@@ -592,6 +602,17 @@ int lbm_set_mhd(lbm_ctx* h, double B0x, double B0y, double B0z, double mu, doubl
   h->B0[2] = B0z;
   h->mu = mu;
   h->tau_m = tau_m;
+  return LBM_OK;
+}
+
+int lbm_set_mhd_coupling(lbm_ctx* h, int kind) {
+  int rc = setup_guard(h);
+  if (rc) return rc;
+  if (!h->mhd) return fail(LBM_ESTATE, "MHD is not enabled");
+  if (kind != LBM_MHD_EQUILIBRIUM && kind != LBM_MHD_LORENTZ_FORCE) return fail(LBM_EINVAL, "unknown coupling %d", kind);
+  if (kind == LBM_MHD_LORENTZ_FORCE && h->darcy > 0)
+    return fail(LBM_EINVAL, "porous resistance is not combined with the Lorentz-force coupling");
+  h->lorentz = kind == LBM_MHD_LORENTZ_FORCE;
   return LBM_OK;
 }
 
@@ -621,7 +642,7 @@ int lbm_init_equilibrium(lbm_ctx* h, const double* u0) {
     HIPCHK(hipMemcpyAsync(h->tmp.p, u0, (size_t)h->D * h->N * sizeof(double), hipMemcpyHostToDevice, h->stream));
     a.u0 = (const double*)h->tmp.p;
   }
-  HIPCHK(launch_init(h->lattice, h->prec, h->mhd, a, h->stream));
+  HIPCHK(launch_init(h->lattice, h->prec, mhd_mode(h), a, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   h->have_state = true;
   h->steps = 0;
@@ -649,7 +670,7 @@ int lbm_set_state(lbm_ctx* h, const double* d) {
   HIPCHK(h->tmp.ensure((size_t)h->Q * h->N * sizeof(double)));
   HIPCHK(hipMemcpyAsync(h->tmp.p, d, (size_t)h->Q * h->N * sizeof(double), hipMemcpyHostToDevice, h->stream));
   a.state = (const double*)h->tmp.p;
-  HIPCHK(launch_init(h->lattice, h->prec, h->mhd, a, h->stream));
+  HIPCHK(launch_init(h->lattice, h->prec, mhd_mode(h), a, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   h->have_state = true;
   h->steps = 0;
@@ -659,7 +680,7 @@ int lbm_set_state(lbm_ctx* h, const double* d) {
 }
 
 static int run_diag(lbm_ctx* h, DiagArgs& a) {
-  HIPCHK(launch_diag(h->lattice, h->prec, h->mhd, a, h->stream));
+  HIPCHK(launch_diag(h->lattice, h->prec, mhd_mode(h), a, h->stream));
   return LBM_OK;
 }
 
@@ -683,7 +704,7 @@ int lbm_get_induction(lbm_ctx* h, double* gout) {
   if (rc) return rc;
   if (!h->mhd) return fail(LBM_ESTATE, "MHD is not enabled");
   if (!gout) return fail(LBM_EINVAL, "null buffer");
-  const size_t bytes = (size_t)21 * h->N * sizeof(double);
+  const size_t bytes = (size_t)ind_planes(h) * h->N * sizeof(double);
   HIPCHK(h->tmp.ensure(bytes));
   DiagArgs a = diag_args(h);
   a.gstate = (double*)h->tmp.p;
@@ -692,7 +713,7 @@ int lbm_get_induction(lbm_ctx* h, double* gout) {
   HIPCHK(hipMemcpyAsync(gout, h->tmp.p, bytes, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   const double s = h->c * std::sqrt(h->mu);
-  for (size_t i = 0; i < (size_t)21 * h->N; ++i) gout[i] *= s;
+  for (size_t i = 0; i < (size_t)ind_planes(h) * h->N; ++i) gout[i] *= s;
   return LBM_OK;
 }
 
@@ -749,7 +770,7 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
       a.mac = (char*)tape + (size_t)i * mbytes;
       HIPCHK(launch_step_mac(h->lattice, h->prec, a, h->parity, diag, h->stream));
     } else {
-      HIPCHK(launch_step(h->lattice, h->prec, h->mhd, a, h->parity, diag, h->stream));
+      HIPCHK(launch_step(h->lattice, h->prec, mhd_mode(h), a, h->parity, diag, h->stream));
     }
     if (h->nibb) {
       ib.parity = h->parity ^ 1;
@@ -892,7 +913,7 @@ int lbm_halfstep(lbm_ctx* h, double* fbar, double* rho_bar, double* u_bar, doubl
   a.p = make_phys(h);
   a.parity = h->parity;
   a.c = h->c;
-  HIPCHK(launch_half(h->lattice, h->prec, h->mhd, a, h->stream));
+  HIPCHK(launch_half(h->lattice, h->prec, mhd_mode(h), a, h->stream));
   if (fbar) HIPCHK(hipMemcpyAsync(fbar, a.fbar, Q * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   if (rho_bar) HIPCHK(hipMemcpyAsync(rho_bar, a.rho, N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   if (u_bar) HIPCHK(hipMemcpyAsync(u_bar, a.vel, D * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -918,10 +939,13 @@ static void wall_variants(const lbm_ctx* h, int gr, double out[4][3]) {
     lat_e(h->lattice, q, e);
     const double w = lat_w(h->lattice, q);
     double phi = 0.0;
-    if (h->mhd) {
+    if (h->mhd && !h->lorentz) {
+      // magnetic part of the equilibrium at the wall field B0 (Eq. 10; two
+      // dimensions without -b^2 / 6); with the Lorentz force in the force
+      // term the equilibrium has none and P carries no Maxwell stress
       const double eb = e[0] * bb[0] + e[1] * bb[1] + e[2] * bb[2];
       const double e2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
-      phi = 4.5 * w * (0.5 * b2 * e2 - eb * eb - b2 / 6.0);
+      phi = 4.5 * w * (0.5 * b2 * e2 - eb * eb - (h->D == 3 ? b2 / 6.0 : 0.0));
     }
     for (int k = 0; k < 3; ++k) {
       // rest-state part of 2 f_out: 2 (w rho0 + phi(B0)) per link (the stored

@@ -17,6 +17,7 @@ LBM_D2Q9, LBM_D3Q19 = 0, 1
 LBM_FORCE_HE, LBM_FORCE_LUO, LBM_FORCE_SHANCHEN, LBM_FORCE_EDM, LBM_FORCE_GUO = range(5)
 LBM_F64, LBM_F32, LBM_F16, LBM_BF16 = range(4)
 LBM_EQ_NS, LBM_EQ_STOKES = 0, 1
+LBM_MHD_EQUILIBRIUM, LBM_MHD_LORENTZ_FORCE = 0, 1
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_EUNSTABLE = 0, -1, -2, -3, -4, -5
 LBM_MAX_GROUPS, LBM_NREC = 16, 24
 
@@ -40,6 +41,7 @@ _SIGS = [
     ("lbm_set_darcy", C.c_int, [_P, C.c_double]),
     ("lbm_set_artefact", C.c_int, [_P, C.c_int]),
     ("lbm_set_mhd", C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]),
+    ("lbm_set_mhd_coupling", C.c_int, [_P, C.c_int]),
     ("lbm_set_stream", C.c_int, [_P, C.c_void_p]),
     ("lbm_init_equilibrium", C.c_int, [_P, _D]),
     ("lbm_set_state", C.c_int, [_P, _D]),
@@ -196,6 +198,10 @@ class Lattice:
         _chk(self.L.lbm_set_mhd(self.h, B0[0], B0[1], B0[2], mu, tau_m))
         self.mhd = True
 
+    def set_mhd_coupling(self, kind):
+        """LBM_MHD_EQUILIBRIUM (Eq. 10, default) or LBM_MHD_LORENTZ_FORCE."""
+        _chk(self.L.lbm_set_mhd_coupling(self.h, kind))
+
     def set_stream(self, stream_ptr):
         _chk(self.L.lbm_set_stream(self.h, stream_ptr))
 
@@ -217,7 +223,7 @@ class Lattice:
         return d
 
     def get_induction(self):
-        g = np.empty((7, 3, self.nz, self.ny, self.nx))
+        g = np.empty((7, 3, self.nz, self.ny, self.nx) if self.Q == 19 else (5, 2, self.nz, self.ny, self.nx))
         _chk(self.L.lbm_get_induction(self.h, _dp(g)))
         return g
 
@@ -326,6 +332,8 @@ def from_workload(w, storage=None, u0=None, init=True):
         lat.set_darcy(w.darcy)
     if w.mhd is not None:
         lat.set_mhd(w.mhd[:3], w.mhd[3], w.mhd[4])
+        if w.lorentz:
+            lat.set_mhd_coupling(LBM_MHD_LORENTZ_FORCE)
     if init:
         lat.init_equilibrium(W.initial_velocity(w) if u0 is None else u0)
     return lat
