@@ -127,7 +127,8 @@ def timed_run(lbm, torch, w, steps, warmup, storage=None):
     st = w.storage if storage is None else storage
     mask = W_obstacle_mask(w)
     nfluid = w.N if mask is None else int((mask == 0).sum())
-    bpn = 2 * w.Q * BYTES[st] + (2 * 21 * BYTES[st] if w.mhd is not None else 0)
+    ind_planes = 21 if w.Q == 19 else 10  # induction directions x field components
+    bpn = 2 * w.Q * BYTES[st] + (2 * ind_planes * BYTES[st] if w.mhd is not None else 0)
     n_even = (steps - 1 + 1) // 2
     launch = (tim["even"] * n_even + tim["odd"] * (steps - 1 - n_even)) / max(steps - 1, 1)
     return {
@@ -319,6 +320,18 @@ def main():
             variants[name] = timed_run(lbm, torch, w, half, min(args.warmup, 10), storage=st)
         print("bench: variant hartmann duct", file=sys.stderr, flush=True)
         variants["hartmann_duct_f32_192x96x96"] = timed_run(lbm, torch, W.hartmann_duct(), half, 10)
+        print("bench: variant hartmann duct, Lorentz-force coupling", file=sys.stderr, flush=True)
+        hl = W.hartmann_duct()
+        hl.lorentz = True
+        variants["hartmann_duct_lorentz_f32_192x96x96"] = timed_run(lbm, torch, hl, half, 10)
+        print("bench: variant 2D hartmann channel", file=sys.stderr, flush=True)
+        variants["hartmann_channel_d2q9_f32_4096x2048"] = timed_run(
+            lbm, torch, W.hartmann_channel(nx=4096, ny=2048, storage=W.F32), half, 10)
+        for curved in (False, True):
+            print("bench: variant duct with sphere, curved %d" % curved, file=sys.stderr, flush=True)
+            ws = W.duct_sphere()
+            ws.curved = curved
+            variants["duct_sphere_%sf32_128x64x64" % ("curved_" if curved else "")] = timed_run(lbm, torch, ws, half, 10)
         print("bench: variant couette cylinder", file=sys.stderr, flush=True)
         variants["couette_cylinder_f32_512x128"] = timed_run(lbm, torch, W.couette_cylinder(), 2000, 100)
         print("bench: variant poiseuille", file=sys.stderr, flush=True)

@@ -57,6 +57,17 @@ struct Stor<S_BF16> {
   }
 };
 
+// A parameter in the arithmetic type T: the FP64 value, or its FP32 copy
+// (rounded by the host exactly as the conversion here would round it).
+template <class T>
+__device__ __forceinline__ T par(double v, float) {
+  return (T)v;
+}
+template <>
+__device__ __forceinline__ float par<float>(double, float v) {
+  return v;
+}
+
 template <class T>
 __device__ __forceinline__ T rcp(T x) {
   return T(1) / x;

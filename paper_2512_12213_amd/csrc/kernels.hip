@@ -71,7 +71,7 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
     if (L::ez(q) < 0) jz -= pt[k];
   }
   m.drho = drho;
-  m.rho = (T)p.rho0 + drho;
+  m.rho = par<T>(p.rho0, p.f.rho0) + drho;
   m.irho = rcp(m.rho);
   m.J[0] = jx;
   m.J[1] = jy;
@@ -81,12 +81,12 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
   m.U[2] = jz * m.irho;
   // porous resistance -sigma v, v = U + A / 2 with A including it:
   // A = (A_ext - sigma dt U) / (1 + sigma dt / 2) (exactly A_ext without it)
-  const T ds = (T)p.darcy_s, di = (T)p.darcy_inv;
+  const T ds = par<T>(p.darcy_s, p.f.darcy_s), di = par<T>(p.darcy_inv, p.f.darcy_inv);
   m.A[0] = (Ax - ds * m.U[0]) * di;
   m.A[1] = (Ay - ds * m.U[1]) * di;
   m.A[2] = (Az - ds * m.U[2]) * di;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) m.b[k] = (T)p.b0[k] + db[k];
+  for (int k = 0; k < 3; ++k) m.b[k] = par<T>(p.b0[k], p.f.b0[k]) + db[k];
   if (MHD == 2) {
     // Lorentz force J x B / rho.  The induction moment's non-equilibrium
     // part gives curl b (first order Chapman-Enskog); with the velocity's own
@@ -97,20 +97,20 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
     const T us[3] = {m.U[0] + T(0.5) * m.A[0], m.U[1] + T(0.5) * m.A[1], m.U[2] + T(0.5) * m.A[2]};
     const T r[3] = {-lam[0] + T(2) * (us[1] * b[2] - us[2] * b[1]), -lam[1] + T(2) * (us[2] * b[0] - us[0] * b[2]),
                     -lam[2] + T(2) * (us[0] * b[1] - us[1] * b[0])};
-    const T ia = rcp(m.rho * (T)p.tm_theta + (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]));
+    const T ia = rcp(m.rho * par<T>(p.tm_theta, p.f.tm_theta) + (b[0] * b[0] + b[1] * b[1] + b[2] * b[2]));
     m.A[0] += (r[1] * b[2] - r[2] * b[1]) * ia;
     m.A[1] += (r[2] * b[0] - r[0] * b[2]) * ia;
     m.A[2] += (r[0] * b[1] - r[1] * b[0]) * ia;
   }
-  const T lEq = (T)p.lEq;
+  const T lEq = par<T>(p.lEq, p.f.lEq);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     m.V[k] = m.U[k] + T(0.5) * m.A[k];
     m.Ue[k] = m.U[k] + lEq * m.A[k];
     m.Je[k] = m.J[k] + lEq * m.rho * m.A[k];
   }
-  m.tau = (T)p.tau0;
-  m.itau = (T)p.inv_tau0;
+  m.tau = par<T>(p.tau0, p.f.tau0);
+  m.itau = par<T>(p.inv_tau0, p.f.inv_tau0);
   if (NEED_PI || p.les_K > 0.0) {
     T sxx = T(0), syy = T(0), szz = T(0), sxy = T(0), sxz = T(0), syz = T(0);
 #pragma unroll
@@ -127,7 +127,7 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
       if (L::ey(q) * L::ez(q) < 0) syz -= ps[k];
     }
     const T third = drho * T(1.0 / 3.0);
-    const T rho = m.rho * (T)p.quad;  // the Stokes equilibrium has no rho u u part
+    const T rho = m.rho * par<T>(p.quad, p.f.quad);  // the Stokes equilibrium has no rho u u part
     m.pi[0] = sxx - third - rho * m.Ue[0] * m.Ue[0];
     m.pi[1] = syy - third - rho * m.Ue[1] * m.Ue[1];
     m.pi[2] = L::D == 3 ? szz - third - rho * m.Ue[2] * m.Ue[2] : T(0);
@@ -137,7 +137,7 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
     if (MHD == 1) {
       // the stored second moment lacks L(b0); subtract L(b) - L(b0),
       // L_ij = b^2 delta_ij / 2 - b_i b_j, formed from db to keep precision
-      const T bs[3] = {m.b[0] + (T)p.b0[0], m.b[1] + (T)p.b0[1], m.b[2] + (T)p.b0[2]};  // b + b0
+      const T bs[3] = {m.b[0] + par<T>(p.b0[0], p.f.b0[0]), m.b[1] + par<T>(p.b0[1], p.f.b0[1]), m.b[2] + par<T>(p.b0[2], p.f.b0[2])};  // b + b0
       const T b2h = T(0.5) * (db[0] * bs[0] + db[1] * bs[1] + db[2] * bs[2]);      // (b^2 - b0^2)/2
       // b_i b_j - b0_i b0_j = (db_i bs_j + bs_i db_j) / 2
       m.pi[0] -= b2h - db[0] * bs[0];
@@ -154,14 +154,14 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
       const T pp = m.pi[0] * m.pi[0] + m.pi[1] * m.pi[1] + m.pi[2] * m.pi[2] +
                    T(2) * (m.pi[3] * m.pi[3] + m.pi[4] * m.pi[4] + m.pi[5] * m.pi[5]);
       const T qn = sqrt(pp);
-      const T t0 = (T)p.tau0;
-      m.tau = T(0.5) * (t0 + sqrt(t0 * t0 + (T)p.les_K * qn * m.irho));
+      const T t0 = par<T>(p.tau0, p.f.tau0);
+      m.tau = T(0.5) * (t0 + sqrt(t0 * t0 + par<T>(p.les_K, p.f.les_K) * qn * m.irho));
       m.itau = rcp(m.tau);
     }
   }
-  m.C = T(1) - (T)p.cG * T(0.5) * m.itau;
-  const T lF = (T)p.lF0 + (T)p.lF1 * m.tau;
-  const T kF = (T)p.kF;
+  m.C = T(1) - par<T>(p.cG, p.f.cG) * T(0.5) * m.itau;
+  const T lF = par<T>(p.lF0, p.f.lF0) + par<T>(p.lF1, p.f.lF1) * m.tau;
+  const T kF = par<T>(p.kF, p.f.kF);
 #pragma unroll
   for (int k = 0; k < 3; ++k) m.UF[k] = kF * m.U[k] + lF * m.A[k];
 }
@@ -190,7 +190,7 @@ template <class L, class T, int MHD, class Sink>
 __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, const T (&db)[3], const Phys& p,
                                         Sink&& sink) {
   const T rho = m.rho;
-  const T lEq = (T)p.lEq;
+  const T lEq = par<T>(p.lEq, p.f.lEq);
   const T usq = T(1.5) * (m.U[0] * m.U[0] + m.U[1] * m.U[1] + m.U[2] * m.U[2]);
   const T ua = m.U[0] * m.A[0] + m.U[1] * m.A[1] + m.U[2] * m.A[2];
   const T aa = m.A[0] * m.A[0] + m.A[1] * m.A[1] + m.A[2] * m.A[2];
@@ -198,43 +198,70 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
   const T cr = m.C * rho;
   const T itau = m.itau;
   const T rl = rho * lEq, rl2 = rho * lEq * lEq;
-  const T quad = (T)p.quad;  // 0 for the Stokes equilibrium
+  const T quad = par<T>(p.quad, p.f.quad);  // 0 for the Stokes equilibrium
   const T rq = rho * quad, rlq = rl * quad, rl2q = rl2 * quad;
   T bs[3] = {T(0), T(0), T(0)}, db2 = T(0);
   if (MHD == 1) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) bs[k] = m.b[k] + (T)p.b0[k];  // b + b0
+    for (int k = 0; k < 3; ++k) bs[k] = m.b[k] + par<T>(p.b0[k], p.f.b0[k]);  // b + b0
     db2 = db[0] * bs[0] + db[1] * bs[1] + db[2] * bs[2];     // b^2 - b0^2
   }
+  const T last = (MHD == 1 && L::D == 3) ? db2 * T(1.0 / 6.0) : T(0);  // no -b^2 / 6 in two dimensions
+  // The increment is formed first and added to d once: adding the small
+  // force term F to an already rounded d + (neq + w Rs) / tau would round it
+  // away in the same direction at every step (a drift of momentum and mass in
+  // slowly varying flows).
+  //
+  // rest direction (e = 0)
+  {
+    const T w = (T)L::w(0);
+    const T wlo = (T)(L::w(0) - (double)w);
+    const T Rb = m.drho - rq * usq;
+    const T neq = (w * Rb + wlo * Rb) - d[0];
+    T Rs = rlq * (T(-3) * ua) + rl2q * (T(-1.5) * aa);
+    if (MHD == 1) Rs += T(-4.5) * last;
+    const T F = cr * w * (T(-3) * ufa);
+    sink(0, d[0] + ((neq + w * Rs) * itau + F));
+  }
+  // direction q and its opposite q + 1 (q odd, e_{q+1} = -e_q): the parts even
+  // in e are formed once, the odd ones change sign
 #pragma unroll
-  for (int q = 0; q < L::Q; ++q) {
+  for (int k = 0; k < (L::Q - 1) / 2; ++k) {
+    const int q = 2 * k + 1;
     const T w = (T)L::w(q);
     const T wlo = (T)(L::w(q) - (double)w);
     const T eu = edot<L>(q, m.U[0], m.U[1], m.U[2]);
     const T ej = edot<L>(q, m.J[0], m.J[1], m.J[2]);
     const T ea = edot<L>(q, m.A[0], m.A[1], m.A[2]);
+    const T euf = edot<L>(q, m.UF[0], m.UF[1], m.UF[2]);
     // large part: w [drho + 3 e.j + rho (9/2 (e.u)^2 - 3/2 u.u)]
-    const T Rb = m.drho + T(3) * ej + rq * (T(4.5) * eu * eu - usq);
-    const T neq = (w * Rb + wlo * Rb) - d[q];
+    const T Eb = m.drho + rq * (T(4.5) * eu * eu - usq);
+    const T Ob = T(3) * ej;
     // small part: the u^eq shift
     //   rho [(e.ue)^2 9/2 - ue.ue 3/2] - (same at u) + 3 e.(rho lEq A),
     // and the magnetic term phi(b) - phi(b0)
-    T Rs = rl * (T(3) * ea) + rlq * (T(9) * eu * ea - T(3) * ua) + rl2q * (T(4.5) * ea * ea - T(1.5) * aa);
+    T Es = rlq * (T(9) * eu * ea - T(3) * ua) + rl2q * (T(4.5) * ea * ea - T(1.5) * aa);
     if (MHD == 1) {
-      // (e.b)^2 - (e.b0)^2 = (e.db)(e.(b + b0)); two-dimensional flows have
-      // no -b^2 / 6 term (the text after Eq. 10)
+      // (e.b)^2 - (e.b0)^2 = (e.db)(e.(b + b0))
       const T edb = edot<L>(q, db[0], db[1], db[2]);
       const T ebs = edot<L>(q, bs[0], bs[1], bs[2]);
-      const T last = L::D == 3 ? db2 * T(1.0 / 6.0) : T(0);
-      Rs += T(4.5) * (T(0.5) * db2 * (T)L::e2(q) - edb * ebs - last);
+      Es += T(4.5) * (T(0.5) * db2 * (T)L::e2(q) - edb * ebs - last);
     }
-    const T euf = edot<L>(q, m.UF[0], m.UF[1], m.UF[2]);
-    const T F = cr * w * (T(3) * (ea - ufa) + T(9) * euf * ea);
-    // the increment is formed first and added to d once: adding the small
-    // force term F to an already rounded d + (neq + w Rs) / tau would round it
-    // away in the same direction at every step (a drift of momentum and mass
-    // in slowly varying flows)
-    sink(q, d[q] + ((neq + w * Rs) * itau + F));
+    const T Os = rl * (T(3) * ea);
+    // force term C rho w [3 (e - u^F).a + 9 (e.u^F)(e.a)]
+    const T cw = cr * w;
+    const T EF = cw * (T(9) * euf * ea - T(3) * ufa);
+    const T OF = cw * (T(3) * ea);
+    {
+      const T Rb = Eb + Ob;
+      const T neq = (w * Rb + wlo * Rb) - d[q];
+      sink(q, d[q] + ((neq + w * (Es + Os)) * itau + (EF + OF)));
+    }
+    {
+      const T Rb = Eb - Ob;
+      const T neq = (w * Rb + wlo * Rb) - d[q + 1];
+      sink(q + 1, d[q + 1] + ((neq + w * (Es - Os)) * itau + (EF - OF)));
+    }
   }
 }
 
@@ -243,10 +270,10 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
 template <class L, class T>
 __device__ __forceinline__ void collide_g(T (&h)[Ind<L>::K][Ind<L>::NB], const Macro<T>& m, const Phys& p) {
   using I = Ind<L>;
-  const T itm = (T)p.inv_tau_m;
+  const T itm = par<T>(p.inv_tau_m, p.f.inv_tau_m);
   const T b[3] = {m.b[0], m.b[1], m.b[2]};
   const T V[3] = {m.V[0], m.V[1], m.V[2]};
-  const T b0[3] = {(T)p.b0[0], (T)p.b0[1], (T)p.b0[2]};
+  const T b0[3] = {par<T>(p.b0[0], p.f.b0[0]), par<T>(p.b0[1], p.f.b0[1]), par<T>(p.b0[2], p.f.b0[2])};
 #pragma unroll
   for (int k = 0; k < I::K; ++k) {
     const T w = (T)I::w(k);
@@ -301,14 +328,14 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
   read_f<L, P, PAR, BND>((const typename S::E*)a.f, Af, mask, a.p, d);
   T Ax, Ay, Az;
   if (a.afield) {
-    const T s = (T)a.p.afield_scale;
+    const T s = par<T>(a.p.afield_scale, a.p.f.afield_scale);
     Ax = (T)a.afield[n] * s;
     Ay = (T)a.afield[g.N + n] * s;
     Az = L::D == 3 ? (T)a.afield[2 * (uint64_t)g.N + n] * s : T(0);
   } else {
-    Ax = (T)a.p.A[0];
-    Ay = (T)a.p.A[1];
-    Az = (T)a.p.A[2];
+    Ax = par<T>(a.p.A[0], a.p.f.A[0]);
+    Ay = par<T>(a.p.A[1], a.p.f.A[1]);
+    Az = par<T>(a.p.A[2], a.p.f.A[2]);
   }
   T h[Ind<L>::K][Ind<L>::NB];
   T db[3] = {T(0), T(0), T(0)}, lam[3] = {T(0), T(0), T(0)};
@@ -486,14 +513,14 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
       for (int q = 0; q < L::Q; ++q) d[q] = (T)ds[q];
       T Ax, Ay, Az;
       if (a.afield) {
-        const T s = (T)a.p.afield_scale;
+        const T s = par<T>(a.p.afield_scale, a.p.f.afield_scale);
         Ax = (T)a.afield[n] * s;
         Ay = (T)a.afield[g.N + n] * s;
         Az = L::D == 3 ? (T)a.afield[2 * (uint64_t)g.N + n] * s : T(0);
       } else {
-        Ax = (T)a.p.A[0];
-        Ay = (T)a.p.A[1];
-        Az = (T)a.p.A[2];
+        Ax = par<T>(a.p.A[0], a.p.f.A[0]);
+        Ay = par<T>(a.p.A[1], a.p.f.A[1]);
+        Az = par<T>(a.p.A[2], a.p.f.A[2]);
       }
       if (MHD) {
         TS hs[Ind<L>::K][Ind<L>::NB];
@@ -543,13 +570,13 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
       if (a.artefact) {
         // E / c^2 = tau rho [(Ue_i A_j + Ue_j A_i) - C (UF_i A_j + UF_j A_i)] (Eq. 9 with Eq. 4)
         const int ci[6] = {0, 1, 2, 0, 0, 1}, cj[6] = {0, 1, 2, 1, 2, 2};
-        const T thc = (T)a.p.thC * m.C;
+        const T thc = par<T>(a.p.thC, a.p.f.thC) * m.C;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
           const int i = ci[c], j = cj[c];
           // (no u^eq a part with the Stokes equilibrium, whose M^eq has no rho u u)
           Pn[c] += m.tau * m.rho *
-                   ((T)a.p.quad * (m.Ue[i] * m.A[j] + m.Ue[j] * m.A[i]) - thc * (m.UF[i] * m.A[j] + m.UF[j] * m.A[i]));
+                   (par<T>(a.p.quad, a.p.f.quad) * (m.Ue[i] * m.A[j] + m.Ue[j] * m.A[i]) - thc * (m.UF[i] * m.A[j] + m.UF[j] * m.A[i]));
         }
       }
       const double cS = -3.0 / (2.0 * (double)m.tau * a.dt * (double)m.rho);
@@ -629,20 +656,29 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
 // conservation of the relaxation.  One thread per node: every slot it reads
 // belongs to links of its own node or to regular streamed values that no
 // other thread of this pass writes.
+// One wavefront per block: the list is short (boundary nodes only) and its
+// gathers are scattered, so spreading it over as many compute units as
+// possible is what shortens the pass.
+constexpr int IBB_THREADS = 64;
+
 template <class L, int P, int PAR>
-__global__ __launch_bounds__(NTHREADS) void k_ibb(const IbbArgs a) {
+__global__ __launch_bounds__(IBB_THREADS) void k_ibb(const IbbArgs a) {
   using S = Stor<P>;
   using E = typename S::E;
   using TS = typename S::T;
   const Geom& g = a.geo;
-  const uint32_t i = blockIdx.x * NTHREADS + threadIdx.x;
+  const uint32_t i = blockIdx.x * IBB_THREADS + threadIdx.x;
   if (i >= a.M) return;
+  // every read comes before the first store (the stores could alias the
+  // other arrays as far as the compiler knows, which would serialise them)
+  double qv[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) qv[q] = a.qf[(uint64_t)i * L::Q + q];
   const uint32_t n = a.node[i];
   uint32_t x, y, z, r;
   coords(g, n, x, y, z, r);
   const AddrG Af = addr_g(g, x, y, z, r, L::Q);
-  const int rr = a.rowrec[r];
-  const uint4 rec = a.rec[rr + x];
+  const uint4 rec = a.rec[a.rowrec[r] + x];
   const uint32_t mask = rec.x;
   E* f = (E*)a.f;
   TS d1[L::Q];
@@ -663,6 +699,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ibb(const IbbArgs a) {
     }
   }
   const double rho_t = (a.p.rho0 + sV) / (1.0 - K);
+  // f_rel(x, t) of each direction (the moving-wall term removed again)
   double R[L::Q];
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) {
@@ -672,44 +709,58 @@ __global__ __launch_bounds__(NTHREADS) void k_ibb(const IbbArgs a) {
       R[q] += 6.0 * L::w(q) * rho_t * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
     }
   }
+  double dnew[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    dnew[q] = V[q];  // halfway value as the step returned it
+    if (q == 0 || !((mask >> q) & 1u) || qv[q] == 0.5) continue;
+    const int qb = opp(q);
+    const uint32_t gr = nibble(rec, q);
+    const double ladd = -6.0 * L::w(q) * rho_t * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
+    if (qv[q] < 0.5) {
+      if (!((mask >> qb) & 1u)) dnew[q] = 2.0 * qv[q] * R[q] + (1.0 - 2.0 * qv[q]) * (double)d1[q] + ladd;
+    } else {
+      dnew[q] = (R[q] + (2.0 * qv[q] - 1.0) * R[qb] + ladd) / (2.0 * qv[q]);
+    }
+  }
 #pragma unroll
   for (int q = 1; q < L::Q; ++q) {
     if (!((mask >> q) & 1u)) continue;
-    const double qv = a.qf[(uint64_t)i * L::Q + q];
-    double dnew = V[q];  // halfway value as the step returned it
-    if (qv != 0.5) {
-      const int qb = opp(q);
-      const uint32_t gr = nibble(rec, q);
-      const double ladd = -6.0 * L::w(q) * rho_t * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
-      if (qv < 0.5) {
-        if (!((mask >> qb) & 1u)) dnew = 2.0 * qv * R[q] + (1.0 - 2.0 * qv) * (double)d1[q] + ladd;
-      } else {
-        dnew = (R[q] + (2.0 * qv - 1.0) * R[qb] + ladd) / (2.0 * qv);
-      }
-      E* ptr = Af.template ptr<L>(f, qb, -1);
-      double sv = dnew;
+    if (qv[q] != 0.5) {
+      double sv = dnew[q];
       if (P == S_F16 || P == S_BF16) sv *= (double)a.p.scale[q];
-      S::st(ptr, (TS)sv);
+      S::st(Af.template ptr<L>(f, opp(q), -1), (TS)sv);
     }
-    if (a.delta) a.delta[(uint64_t)i * L::Q + q] = dnew - V[q];
+    if (a.delta) a.delta[(uint64_t)i * L::Q + q] = dnew[q] - V[q];
   }
 }
 
-// Wall-force corrections of the interpolated links per group: out[g][k],
-// k < 3 the sum of e_k delta, k = 3 the sum of delta (block g * 4 + k).
+// Wall-force corrections of the interpolated links: per block of 256 list
+// entries (node, direction) the sums of e_k delta (k < 3) and delta (k = 3)
+// of each group g < G into part[block][4 g + k]; k_colsum then adds the
+// blocks' rows.  Both deterministic.
 template <class L>
-__global__ __launch_bounds__(NTHREADS) void k_ibb_reduce(const double* __restrict__ delta, const uint8_t* __restrict__ grp,
-                                                         uint32_t M, double* __restrict__ out) {
-  const uint32_t gk = blockIdx.x, g = gk / 4, k = gk % 4;
-  double s = 0.0;
-  for (uint64_t e = threadIdx.x; e < (uint64_t)M * L::Q; e += NTHREADS) {
-    const int q = (int)(e % L::Q);
-    if (q == 0 || grp[e] != g) continue;
-    const int ek = k == 0 ? L::ex(q) : (k == 1 ? L::ey(q) : (k == 2 ? L::ez(q) : 1));
-    s += ek * delta[e];
+__global__ __launch_bounds__(NTHREADS) void k_ibb_part(const double* __restrict__ delta, const uint8_t* __restrict__ grp,
+                                                       uint64_t entries, int G, double* __restrict__ part) {
+  const uint64_t e = (uint64_t)blockIdx.x * NTHREADS + threadIdx.x;
+  const int q = (int)(e % L::Q);
+  const bool live = e < entries && q > 0;
+  const uint32_t ge = live ? grp[e] : 0xFFu;
+  const double dv = (live && ge != 0xFFu) ? delta[e] : 0.0;
+  for (int gr = 0; gr < G; ++gr) {
+    const double s = ge == (uint32_t)gr ? dv : 0.0;
+    double v[4] = {L::ex(q) * s, L::ey(q) * s, L::ez(q) * s, s};
+    tile_sum_store<4>(v, part + ((uint64_t)blockIdx.x * G + gr) * 4);
   }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_colsum(const double* __restrict__ part, uint32_t rows, uint32_t cols,
+                                                     double* __restrict__ out) {
+  const uint32_t c = blockIdx.x;
+  double s = 0.0;
+  for (uint32_t r = threadIdx.x; r < rows; r += NTHREADS) s += part[(uint64_t)r * cols + c];
   double v[1] = {s};
-  tile_sum_store<1>(v, out + gk);
+  tile_sum_store<1>(v, out + c);
 }
 
 // ---------------------------------------------------------------------------
@@ -989,11 +1040,11 @@ static hipError_t launch_diag_t(const DiagArgs& a, hipStream_t st) {
 
 template <class L, int P, int MHD>
 static hipError_t launch_ibb_t(const IbbArgs& a, hipStream_t st) {
-  const uint32_t nb = (a.M + NTHREADS - 1) / NTHREADS;
+  const uint32_t nb = (a.M + IBB_THREADS - 1) / IBB_THREADS;
   if (a.parity == 0)
-    k_ibb<L, P, 0><<<nb, NTHREADS, 0, st>>>(a);
+    k_ibb<L, P, 0><<<nb, IBB_THREADS, 0, st>>>(a);
   else
-    k_ibb<L, P, 1><<<nb, NTHREADS, 0, st>>>(a);
+    k_ibb<L, P, 1><<<nb, IBB_THREADS, 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -1070,12 +1121,15 @@ hipError_t launch_ibb(int lattice, int prec, const IbbArgs& a, hipStream_t st) {
   LBM_DISPATCH(launch_ibb_t, lattice, prec, 0, a, st);
 }
 
-hipError_t launch_ibb_reduce(int lattice, const double* delta, const uint8_t* grp, uint32_t M, int G, double* out,
-                             hipStream_t st) {
+hipError_t launch_ibb_reduce(int lattice, const double* delta, const uint8_t* grp, uint32_t M, int G, double* part,
+                             double* out, hipStream_t st) {
+  const uint64_t entries = (uint64_t)M * (lattice == 0 ? 9 : 19);
+  const uint32_t nb = (uint32_t)((entries + NTHREADS - 1) / NTHREADS);
   if (lattice == 0)
-    k_ibb_reduce<D2Q9><<<G * 4, NTHREADS, 0, st>>>(delta, grp, M, out);
+    k_ibb_part<D2Q9><<<nb, NTHREADS, 0, st>>>(delta, grp, entries, G, part);
   else
-    k_ibb_reduce<D3Q19><<<G * 4, NTHREADS, 0, st>>>(delta, grp, M, out);
+    k_ibb_part<D3Q19><<<nb, NTHREADS, 0, st>>>(delta, grp, entries, G, part);
+  k_colsum<<<G * 4, NTHREADS, 0, st>>>(part, nb, (uint32_t)G * 4, out);
   return hipGetLastError();
 }
 

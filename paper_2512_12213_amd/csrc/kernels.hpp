@@ -37,6 +37,12 @@ struct Phys {
   double inv_tau_m;
   double tm_theta;     // tau_m theta of the induction lattice (Lorentz-force coupling)
   float scale[19], inv_scale[19];  // storage scaling per direction
+  // the same parameters rounded to FP32 by the host, so that FP32 kernels
+  // read them from scalar registers instead of converting them per thread
+  struct {
+    float rho0, tau0, inv_tau0, A[3], afield_scale, kF, lF0, lF1, lEq, cG, thC, les_K, quad, darcy_s, darcy_inv;
+    float b0[3], inv_tau_m, tm_theta;
+  } f;
 };
 
 struct StepArgs {

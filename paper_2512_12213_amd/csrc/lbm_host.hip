@@ -23,8 +23,8 @@ hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t nt
 hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, bool diag, hipStream_t st);
 hipError_t launch_half(int lattice, int prec, int mhd, const HalfArgs& a, hipStream_t st);
 hipError_t launch_ibb(int lattice, int prec, const IbbArgs& a, hipStream_t st);
-hipError_t launch_ibb_reduce(int lattice, const double* delta, const uint8_t* grp, uint32_t M, int G, double* out,
-                             hipStream_t st);
+hipError_t launch_ibb_reduce(int lattice, const double* delta, const uint8_t* grp, uint32_t M, int G, double* part,
+                             double* out, hipStream_t st);
 hipError_t launch_adj(int lattice, int prec, int adj_prec, const AdjArgs& a, int parity, bool seed, hipStream_t st);
 }  // namespace lbm
 
@@ -120,7 +120,7 @@ struct lbm_ctx {
   // walls that are not halfway: link fractions (host, [Q][N]) and the list of
   // nodes whose links are interpolated after each step
   std::vector<double> qlink;
-  DevBuf ibb_node, ibb_q, ibb_grp, ibb_delta, ibb_red;
+  DevBuf ibb_node, ibb_q, ibb_grp, ibb_delta, ibb_part, ibb_red;
   uint32_t nibb = 0;
   double* hred = nullptr;  // pinned [NBAL + MAXG * NWALL]
   bool uw_dirty = true;
@@ -184,6 +184,26 @@ Phys make_phys(const lbm_ctx* h) {
     p.scale[q] = (float)s;
     p.inv_scale[q] = (float)(1.0 / s);
   }
+  p.f.rho0 = (float)p.rho0;
+  p.f.tau0 = (float)p.tau0;
+  p.f.inv_tau0 = (float)p.inv_tau0;
+  for (int k = 0; k < 3; ++k) {
+    p.f.A[k] = (float)p.A[k];
+    p.f.b0[k] = (float)p.b0[k];
+  }
+  p.f.afield_scale = (float)p.afield_scale;
+  p.f.kF = (float)p.kF;
+  p.f.lF0 = (float)p.lF0;
+  p.f.lF1 = (float)p.lF1;
+  p.f.lEq = (float)p.lEq;
+  p.f.cG = (float)p.cG;
+  p.f.thC = (float)p.thC;
+  p.f.les_K = (float)p.les_K;
+  p.f.quad = (float)p.quad;
+  p.f.darcy_s = (float)p.darcy_s;
+  p.f.darcy_inv = (float)p.darcy_inv;
+  p.f.inv_tau_m = (float)p.inv_tau_m;
+  p.f.tm_theta = (float)p.tm_theta;
   return p;
 }
 
@@ -329,6 +349,7 @@ int build_geometry(lbm_ctx* h) {
     HIPCHK(h->ibb_grp.ensure(igrp.size()));
     HIPCHK(h->ibb_delta.ensure(iq.size() * sizeof(double)));
     HIPCHK(h->ibb_red.ensure(MAXG * 4 * sizeof(double)));
+    HIPCHK(h->ibb_part.ensure(((iq.size() + NTHREADS - 1) / NTHREADS) * MAXG * 4 * sizeof(double)));
     HIPCHK(hipMemcpy(h->ibb_node.p, inode.data(), inode.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(h->ibb_q.p, iq.data(), iq.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(h->ibb_grp.p, igrp.data(), igrp.size(), hipMemcpyHostToDevice));
@@ -786,7 +807,7 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
   double* ibb_host = h->hred + 2 * (NBAL + MAXG * NWALL) + NDIAGPART;
   if (h->nibb) {
     HIPCHK(launch_ibb_reduce(h->lattice, (const double*)h->ibb_delta.p, (const uint8_t*)h->ibb_grp.p, h->nibb, h->G,
-                             (double*)h->ibb_red.p, h->stream));
+                             (double*)h->ibb_part.p, (double*)h->ibb_red.p, h->stream));
     HIPCHK(hipMemcpyAsync(ibb_host, h->ibb_red.p, (size_t)h->G * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   }
   if (h->timing) HIPCHK(hipEventRecord(h->ev[n + 1], h->stream));
