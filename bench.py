@@ -227,11 +227,36 @@ def cpu_baseline(W, budget_s):
     t0 = time.perf_counter()
     oa.adjoint(2, 4, 0)
     t_adj = time.perf_counter() - t0
+    # the other configurations: the channel in full, the Hartmann duct 20
+    # steps after 2 untimed ones
+    wp = W.poiseuille()
+    op = make_oracle(wp)
+    t0 = time.perf_counter()
+    op.step(wp.steps)
+    t_chan = time.perf_counter() - t0
+    op.close()
+    wh = W.hartmann_duct()
+    oh = make_oracle(wh)
+    oh.step(2)
+    t0 = time.perf_counter()
+    oh.step(20)
+    t_mhd = time.perf_counter() - t0
+    oh.close()
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {
         "value": w.N * n / t / 1e6,
         "unit": "MLUPS",
         "cores": threads,
         "kind": "oracle",
+        "cpu_model": cpu_model,
+        "nproc": os.cpu_count(),
+        "channel_64x32_f64_mlups": wp.N * wp.steps / t_chan / 1e6,
+        "hartmann_duct_192x96x96_mlups": wh.N * 20 / t_mhd / 1e6,
         "sample": "%d steps of the full %dx%dx%d duct (FP64, LES, walls) after 1 untimed step, %.1f s"
                   % (n, w.nx, w.ny, w.nz, t),
         "single_thread_mlups": w.N * 2 / t_one / 1e6,
@@ -239,6 +264,31 @@ def cpu_baseline(W, budget_s):
         "adjoint_sample": "forward and reverse pass (complex-step node Jacobians) of 2 steps of the "
                           "128x64x64 duct with a sphere, %d threads, %.1f s" % (threads, t_adj),
     }
+
+
+def errors_vs_oracle(lbm, W):
+    """Each storage format's error against the FP64 oracle on the duct with
+    LES at 64x32x32, 300 steps (same workload recipe as the timed duct)."""
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from helpers import make_oracle
+    w = W.duct_les(nx=64, ny=32, nz=32, steps=300)
+    o = make_oracle(w)
+    o.step(w.steps)
+    ro, vo = o.get_macro()
+    fo = o.wall_force(4)
+    o.close()
+    out = {"workload": "duct_les_d3q19_64x32x32, 300 steps, FP64 oracle; max-norm relative errors"}
+    for st, name in ((W.F64, "f64"), (W.F32, "f32"), (W.F16, "f16"), (W.BF16, "bf16")):
+        g = lbm.from_workload(w, storage=st)
+        g.step(w.steps)
+        rg, vg = g.get_macro()
+        fg = g.wall_force()[:4]
+        g.close()
+        out[name] = {"v": float(np.abs(vg - vo).max() / np.abs(vo).max()),
+                     "rho": float(np.abs(rg - ro).max()),
+                     "wall_force": float(np.linalg.norm(fg[:, 0] - fo[:, 0]) / np.linalg.norm(fo[:, 0]))}
+    return out
 
 
 def main():
@@ -318,6 +368,12 @@ def main():
         for name, st in (("duct_f16", W.F16), ("duct_bf16", W.BF16), ("duct_f64", W.F64)):
             print("bench: variant %s" % name, file=sys.stderr, flush=True)
             variants[name] = timed_run(lbm, torch, w, half, min(args.warmup, 10), storage=st)
+        print("bench: variant duct without LES", file=sys.stderr, flush=True)
+        wn = W.duct_les()
+        wn.les_cs = 0.0
+        variants["duct_no_les_f32"] = timed_run(lbm, torch, wn, half, min(args.warmup, 10))
+        print("bench: variant large duct (beyond the last-level cache)", file=sys.stderr, flush=True)
+        variants["duct_les_f32_512x256x256"] = timed_run(lbm, torch, W.duct_les(nx=512, ny=256, nz=256), 60, 5)
         print("bench: variant hartmann duct", file=sys.stderr, flush=True)
         variants["hartmann_duct_f32_192x96x96"] = timed_run(lbm, torch, W.hartmann_duct(), half, 10)
         print("bench: variant hartmann duct, Lorentz-force coupling", file=sys.stderr, flush=True)
@@ -349,6 +405,8 @@ def main():
     if not args.no_cpu:
         print("bench: CPU reference baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)
+        print("bench: storage formats against the oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"]["errors_vs_oracle"] = errors_vs_oracle(lbm, W)
     print(json.dumps(out), flush=True)
 
 
