@@ -77,6 +77,51 @@ __device__ __forceinline__ float rcp<float>(float x) {
   return __builtin_amdgcn_rcpf(x);
 }
 
+// The same formats through a buffer resource (scalar base and range,
+// wave-uniform scalar byte offset, per-lane byte offset), with the same cache
+// hints (aux bit 1: non-temporal).
+template <int P>
+struct BufIO;
+template <>
+struct BufIO<S_F64> {
+  static __device__ __forceinline__ double ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v, s, 2));
+  }
+  static __device__ __forceinline__ void st(double x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, v, s, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, v, s, 2);
+  }
+};
+template <>
+struct BufIO<S_F32> {
+  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, v, s, 2));
+  }
+  static __device__ __forceinline__ void st(float x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, v, s, 0);
+  }
+};
+template <>
+struct BufIO<S_F16> {
+  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0));
+  }
+  static __device__ __forceinline__ void st(float x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (_Float16)x), r, v, s, 0);
+  }
+};
+template <>
+struct BufIO<S_BF16> {
+  static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    return __uint_as_float(uint32_t((uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0)) << 16);
+  }
+  static __device__ __forceinline__ void st(float x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(u >> 16), r, v, s, 0);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // index helpers
 // ---------------------------------------------------------------------------
@@ -133,6 +178,10 @@ struct AddrG {
   __device__ __forceinline__ E* ptr(E* f, int plane, int q) const {
     return f + ((q < 0 ? b : b + off_of<L>(q, o)) + (uint32_t)plane * nx);
   }
+  template <class L, int P>
+  __device__ __forceinline__ typename Stor<P>::T ld(const typename Stor<P>::E* f, int plane, int q) const;
+  template <class L, int P>
+  __device__ __forceinline__ void st(typename Stor<P>::E* f, int plane, int q, typename Stor<P>::T v) const;
 };
 
 // Row-uniform form, used when nx is a multiple of 64: a wavefront then never
@@ -155,7 +204,61 @@ struct AddrR {
     const uint32_t xs = dx < 0 ? xm : (dx > 0 ? xp : x);
     return (E*)((char*)base + xs * (uint32_t)sizeof(E));  // 32-bit byte offset
   }
+  template <class L, int P>
+  __device__ __forceinline__ typename Stor<P>::T ld(const typename Stor<P>::E* f, int plane, int q) const;
+  template <class L, int P>
+  __device__ __forceinline__ void st(typename Stor<P>::E* f, int plane, int q, typename Stor<P>::T v) const;
 };
+
+// Row-uniform buffer form, used when nx is a multiple of 64 and the array
+// is below 4 GiB: the array is a buffer resource (four scalar registers), the
+// row and plane offset a wave-uniform scalar, and each lane adds only its x
+// byte offset; no 64-bit per-lane addresses are formed (they cost two vector
+// registers and a vector add per access in the pointer form).  Only for rows
+// without boundary links (no per-lane choice between slots).
+struct AddrB {
+  __amdgpu_buffer_rsrc_t rs;
+  uint32_t y, z, ny, nz;
+  uint32_t vx, vxm, vxp;  // byte offsets of x, x - 1, x + 1 (periodic), per lane
+  uint32_t nxb, rsb;      // bytes of one plane of a row, of one row block
+  template <class L>
+  __device__ __forceinline__ uint32_t soff(int plane, int q) const {
+    const int dy = q < 0 ? 0 : L::ey(q), dz = q < 0 ? 0 : L::ez(q);
+    const uint32_t yy = dy < 0 ? (y == 0 ? ny - 1 : y - 1) : (dy > 0 ? (y + 1 == ny ? 0 : y + 1) : y);
+    const uint32_t zz = dz < 0 ? (z == 0 ? nz - 1 : z - 1) : (dz > 0 ? (z + 1 == nz ? 0 : z + 1) : z);
+    return (zz * ny + yy) * rsb + (uint32_t)plane * nxb;  // wave-uniform
+  }
+  template <class L>
+  __device__ __forceinline__ uint32_t voff(int q) const {
+    const int dx = q < 0 ? 0 : L::ex(q);
+    return dx < 0 ? vxm : (dx > 0 ? vxp : vx);
+  }
+  template <class L, int P>
+  __device__ __forceinline__ typename Stor<P>::T ld(const typename Stor<P>::E*, int plane, int q) const {
+    return BufIO<P>::ld(rs, voff<L>(q), soff<L>(plane, q));
+  }
+  template <class L, int P>
+  __device__ __forceinline__ void st(typename Stor<P>::E*, int plane, int q, typename Stor<P>::T v) const {
+    BufIO<P>::st(v, rs, voff<L>(q), soff<L>(plane, q));
+  }
+};
+
+template <class L, int P>
+__device__ __forceinline__ typename Stor<P>::T AddrG::ld(const typename Stor<P>::E* f, int plane, int q) const {
+  return Stor<P>::ld(ptr<L>(f, plane, q));
+}
+template <class L, int P>
+__device__ __forceinline__ void AddrG::st(typename Stor<P>::E* f, int plane, int q, typename Stor<P>::T v) const {
+  Stor<P>::st(ptr<L>(f, plane, q), v);
+}
+template <class L, int P>
+__device__ __forceinline__ typename Stor<P>::T AddrR::ld(const typename Stor<P>::E* f, int plane, int q) const {
+  return Stor<P>::ld(ptr<L>(f, plane, q));
+}
+template <class L, int P>
+__device__ __forceinline__ void AddrR::st(typename Stor<P>::E* f, int plane, int q, typename Stor<P>::T v) const {
+  Stor<P>::st(ptr<L>(f, plane, q), v);
+}
 
 __device__ __forceinline__ AddrG addr_g(const Geom& g, uint32_t x, uint32_t y, uint32_t z, uint32_t r, uint32_t P) {
   AddrG a;
@@ -177,6 +280,24 @@ __device__ __forceinline__ AddrR addr_r(const Geom& g, uint32_t x, uint32_t y, u
   a.xp = x + 1 == g.nx ? 0 : x + 1;
   a.nx = g.nx;
   a.rs = (uint64_t)P * g.nx;
+  return a;
+}
+
+// y, z must be wave-uniform; bytes (the whole array) below 4 GiB.
+template <class E>
+__device__ __forceinline__ AddrB addr_b(const Geom& g, uint32_t x, uint32_t y, uint32_t z, uint32_t P, const void* f,
+                                        uint32_t bytes) {
+  AddrB a;
+  a.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(f), 0, bytes, 0x00020000);
+  a.y = y;
+  a.z = z;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.vx = x * (uint32_t)sizeof(E);
+  a.vxm = (x == 0 ? g.nx - 1 : x - 1) * (uint32_t)sizeof(E);
+  a.vxp = (x + 1 == g.nx ? 0 : x + 1) * (uint32_t)sizeof(E);
+  a.nxb = g.nx * (uint32_t)sizeof(E);
+  a.rsb = P * a.nxb;
   return a;
 }
 
@@ -221,15 +342,15 @@ __device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) {
     const int qb = opp(q);
-    const typename S::E* ptr;
-    if (PAR == 0) {
-      ptr = A.template ptr<L>(f, q, -1);
+    T v;
+    if constexpr (PAR == 0) {
+      v = A.template ld<L, P>(f, q, -1);
+    } else if constexpr (BND) {
+      // a wall link: the value was put in the node's own slot q
+      v = S::ld(pick((mask >> qb) & 1u, A.template ptr<L>(f, q, -1), A.template ptr<L>(f, qb, qb)));
     } else {
-      ptr = A.template ptr<L>(f, qb, qb);
+      v = A.template ld<L, P>(f, qb, qb);
     }
-    // a wall link: the value was put in the node's own slot q
-    if (PAR == 1 && BND) ptr = pick((mask >> qb) & 1u, A.template ptr<L>(f, q, -1), ptr);
-    T v = S::ld(ptr);
     if (P == S_F16 || P == S_BF16) v *= (T)p.inv_scale[q];
     d[q] = v;
   }
@@ -239,30 +360,7 @@ __device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f
 // bounce-back value, including the moving-wall term, for wall links):
 //   even parity: slot opp(q) of x;
 //   odd parity: slot q of x + e_q, or slot opp(q) of x for a wall link.
-template <class L, int P, int PAR, bool BND, class AD>
-__device__ __forceinline__ void write_f(typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask, const Phys& p,
-                                        const typename Stor<P>::T (&v)[L::Q]) {
-  using S = Stor<P>;
-  using T = typename S::T;
-#pragma unroll
-  for (int q = 0; q < L::Q; ++q) {
-    const int qb = opp(q);
-    typename S::E* ptr;
-    if (PAR == 0) {
-      ptr = A.template ptr<L>(f, qb, -1);
-    } else {
-      ptr = A.template ptr<L>(f, q, q);
-    }
-    T s = v[q];
-    if (P == S_F16 || P == S_BF16) s *= (T)p.scale[q];
-    if (PAR == 1 && BND && ((mask >> q) & 1u))
-      S::st(A.template ptr<L>(f, qb, -1), s);  // wall link: back into the node's own slot
-    else
-      S::st(ptr, s);
-  }
-}
-
-// One direction of write_f.
+// One direction at a time.
 template <class L, int P, int PAR, bool BND, class AD>
 __device__ __forceinline__ void write_f1(typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask, const Phys& p,
                                          int q, typename Stor<P>::T v) {
@@ -271,13 +369,13 @@ __device__ __forceinline__ void write_f1(typename Stor<P>::E* __restrict__ f, co
   const int qb = opp(q);
   T s = v;
   if (P == S_F16 || P == S_BF16) s *= (T)p.scale[q];
-  if (PAR == 0) {
-    S::st(A.template ptr<L>(f, qb, -1), s);
-  } else if (BND) {
+  if constexpr (PAR == 0) {
+    A.template st<L, P>(f, qb, -1, s);
+  } else if constexpr (BND) {
     // wall link: back into the node's own slot
     S::st(pick((mask >> q) & 1u, A.template ptr<L>(f, qb, -1), A.template ptr<L>(f, q, q)), s);
   } else {
-    S::st(A.template ptr<L>(f, q, q), s);
+    A.template st<L, P>(f, q, q, s);
   }
 }
 
@@ -293,14 +391,14 @@ __device__ __forceinline__ void read_g(const typename Stor<P>::E* __restrict__ g
     const int kb = opp(k);
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const typename S::E* ptr;
-      if (PAR == 0) {
-        ptr = A.template ptr<L>(g, NB * k + i, -1);
+      if constexpr (PAR == 0) {
+        h[k][i] = A.template ld<L, P>(g, NB * k + i, -1);
+      } else if constexpr (BND) {
+        h[k][i] = S::ld(pick((mask >> kb) & 1u, A.template ptr<L>(g, NB * k + i, -1),
+                             A.template ptr<L>(g, NB * kb + i, kb)));
       } else {
-        ptr = A.template ptr<L>(g, NB * kb + i, kb);
+        h[k][i] = A.template ld<L, P>(g, NB * kb + i, kb);
       }
-      if (PAR == 1 && BND) ptr = pick((mask >> kb) & 1u, A.template ptr<L>(g, NB * k + i, -1), ptr);
-      h[k][i] = S::ld(ptr);
     }
   }
 }
@@ -315,14 +413,14 @@ __device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, con
     const int kb = opp(k);
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      typename S::E* ptr;
-      if (PAR == 0) {
-        ptr = A.template ptr<L>(g, NB * kb + i, -1);
+      if constexpr (PAR == 0) {
+        A.template st<L, P>(g, NB * kb + i, -1, h[k][i]);
+      } else if constexpr (BND) {
+        S::st(pick((mask >> k) & 1u, A.template ptr<L>(g, NB * kb + i, -1), A.template ptr<L>(g, NB * k + i, k)),
+              h[k][i]);
       } else {
-        ptr = A.template ptr<L>(g, NB * k + i, k);
+        A.template st<L, P>(g, NB * k + i, k, h[k][i]);
       }
-      if (PAR == 1 && BND) ptr = pick((mask >> k) & 1u, A.template ptr<L>(g, NB * kb + i, -1), ptr);
-      S::st(ptr, h[k][i]);
     }
   }
 }
