@@ -241,6 +241,15 @@ struct AddrB {
   __device__ __forceinline__ void st(typename Stor<P>::E*, int plane, int q, typename Stor<P>::T v) const {
     BufIO<P>::st(v, rs, voff<L>(q), soff<L>(plane, q));
   }
+  // the same rows as ld / st along e_q, but the lane's own x (no x shift)
+  template <class L, int P>
+  __device__ __forceinline__ typename Stor<P>::T ldx(int plane, int q) const {
+    return BufIO<P>::ld(rs, vx, soff<L>(plane, q));
+  }
+  template <class L, int P>
+  __device__ __forceinline__ void stx(int plane, int q, typename Stor<P>::T v) const {
+    BufIO<P>::st(v, rs, vx, soff<L>(plane, q));
+  }
 };
 
 template <class L, int P>

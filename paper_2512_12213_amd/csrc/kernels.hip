@@ -316,16 +316,70 @@ __device__ __forceinline__ void ind_moments(const T (&h)[Ind<L>::K][Ind<L>::NB],
 // ---------------------------------------------------------------------------
 // the fused step
 // ---------------------------------------------------------------------------
-template <class L, int P, int MHD, int PAR, bool DIAG, bool MAC, bool BND, class AD>
+// Directions with e_x != 0, numbered in order (the x-shifted ones of odd steps).
+template <class L>
+__host__ __device__ constexpr int xshift_count() {
+  int c = 0;
+  for (int q = 0; q < L::Q; ++q) c += L::ex(q) != 0;
+  return c;
+}
+template <class L>
+__host__ __device__ constexpr int xshift_index(int q) {
+  int c = 0;
+  for (int p = 0; p < q; ++p) c += L::ex(p) != 0;
+  return c;
+}
+
+// XS (odd steps, tiles of whole rows without boundary links, buffer
+// addressing): the x-shifted directions go through LDS.  The tile loads the
+// source row of such a direction at its own x (aligned, coalesced), and each
+// node takes its element x + e_x(opp q) from LDS; outputs are placed in LDS at
+// x + e_x(q) and the tile stores the destination row at its own x.  A tile
+// holds whole rows and x wraps inside a row, so every slot it loads or stores
+// still belongs to one of its own nodes.  Every thread of the tile takes this
+// path (the choice is per tile), so the two barriers are reached uniformly.
+template <class L, int P, int MHD, int PAR, bool DIAG, bool MAC, bool BND, class AD, bool XS = false>
 __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const AD& Af, const AD& Ag, const uint4& rec,
                                             typename Stor<P>::T (&bal)[NBAL],
-                                            typename Stor<P>::T (&wacc)[MAXBG][NWALL], uint32_t bgrp) {
+                                            typename Stor<P>::T (&wacc)[MAXBG][NWALL], uint32_t bgrp,
+                                            uint32_t x = 0) {
   using S = Stor<P>;
   using T = typename S::T;
   const Geom& g = a.geo;
   const uint32_t mask = rec.x;
   T d[L::Q];
-  read_f<L, P, PAR, BND>((const typename S::E*)a.f, Af, mask, a.p, d);
+  constexpr int NS = xshift_count<L>();
+  [[maybe_unused]] T (*xs_out)[NTHREADS] = nullptr;
+  [[maybe_unused]] uint32_t rb = 0;
+  if constexpr (XS) {
+    static_assert(PAR == 1 && !BND && MHD == 0, "x staging is for odd steps of interior tiles");
+    __shared__ T xs_in[NS][NTHREADS];
+    __shared__ T xs_outb[NS][NTHREADS];
+    xs_out = xs_outb;
+    const uint32_t tid = threadIdx.x;
+    rb = tid - x;  // first thread of this node's row in the tile
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const int qb = opp(q);
+      if (L::ex(qb) == 0)
+        d[q] = Af.template ld<L, P>(nullptr, qb, qb);
+      else
+        xs_in[xshift_index<L>(q)][tid] = Af.template ldx<L, P>(qb, qb);
+    }
+    __syncthreads();
+    const uint32_t nx = g.nx;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const int dx = L::ex(opp(q));
+      if (dx != 0) {
+        const uint32_t xs = dx > 0 ? (x + 1 == nx ? 0 : x + 1) : (x == 0 ? nx - 1 : x - 1);
+        d[q] = xs_in[xshift_index<L>(q)][rb + xs];
+      }
+      if (P == S_F16 || P == S_BF16) d[q] *= (T)a.p.inv_scale[q];
+    }
+  } else {
+    read_f<L, P, PAR, BND>((const typename S::E*)a.f, Af, mask, a.p, d);
+  }
   T Ax, Ay, Az;
   if (a.afield) {
     const T s = par<T>(a.p.afield_scale, a.p.f.afield_scale);
@@ -387,8 +441,26 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
         }
       }
     }
-    write_f1<L, P, PAR, BND>(fo, Af, mask, a.p, q, v);
+    if constexpr (XS) {
+      T s = v;
+      if (P == S_F16 || P == S_BF16) s *= (T)a.p.scale[q];
+      if (L::ex(q) == 0) {
+        Af.template st<L, P>(nullptr, q, q, s);
+      } else {
+        const uint32_t nx = g.nx;
+        const uint32_t xd = L::ex(q) > 0 ? (x + 1 == nx ? 0 : x + 1) : (x == 0 ? nx - 1 : x - 1);
+        xs_out[xshift_index<L>(q)][rb + xd] = s;
+      }
+    } else {
+      write_f1<L, P, PAR, BND>(fo, Af, mask, a.p, q, v);
+    }
   });
+  if constexpr (XS) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q)
+      if (L::ex(q) != 0) Af.template stx<L, P>(q, q, xs_out[xshift_index<L>(q)][threadIdx.x]);
+  }
   if (MHD) {
     collide_g<L, T>(h, m, a.p);
     if (BND) {
@@ -423,7 +495,10 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
 #pragma unroll
       for (int k = 0; k < NWALL; ++k) wacc[s][k] = T(0);
   }
-  const uint32_t bgrp = DIAG ? a.blkgrp[blockIdx.x] : 0u;
+  // LDS x-staging on odd steps: FP32 (odd step -5 %); the 2-byte formats
+  // and the diagnostic variant (register pressure) measured slower with it
+  constexpr bool XS_OK = RU == 2 && MHD == 0 && PAR == 1 && !MAC && !DIAG && P == S_F32;
+  const uint32_t bgrp = (DIAG || XS_OK) ? a.blkgrp[blockIdx.x] : 0u;
   if (active) {
     uint32_t x, y, z, r;
     coords(g, n, x, y, z, r);
@@ -441,7 +516,16 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
         constexpr uint32_t GP = MHD ? Ind<L>::K * Ind<L>::NB : L::Q;
         const AddrB Af = addr_b<E>(g, x, y, z, L::Q, a.f, (uint32_t)((uint64_t)g.N * L::Q * sizeof(E)));
         const AddrB Ag = MHD ? addr_b<E>(g, x, y, z, GP, a.g, (uint32_t)((uint64_t)g.N * GP * sizeof(E))) : Af;
-        node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+        if constexpr (XS_OK) {
+          if ((bgrp >> 27) & 1u) {
+            // tile of whole rows without boundary links (uniform per tile)
+            node_update<L, P, MHD, PAR, DIAG, MAC, false, AddrB, true>(a, n, Af, Ag, rec, bal, wacc, bgrp, x);
+          } else {
+            node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          }
+        } else {
+          node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+        }
       } else if (RU) {
         const AddrR Af = addr_r(g, x, y, z, L::Q);
         const AddrR Ag = addr_r(g, x, y, z, MHD ? Ind<L>::K * Ind<L>::NB : L::Q);

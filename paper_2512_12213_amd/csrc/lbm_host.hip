@@ -331,6 +331,15 @@ int build_geometry(lbm_ctx* h) {
         ++cnt;
       }
     tilegrp[t] = packed | (cnt << 28);
+    // bit 27: the tile holds whole rows, all nodes, and no row with boundary
+    // links (odd steps may then stage their x-shifted directions in LDS)
+    const uint64_t n0 = (uint64_t)t * NTHREADS;
+    if (NTHREADS % h->nx == 0 && n0 + NTHREADS <= (uint64_t)h->N) {
+      bool interior = true;
+      for (uint64_t r = n0 / h->nx; r < (n0 + NTHREADS) / h->nx; ++r)
+        if (rowrec[r] >= 0) interior = false;
+      if (interior) tilegrp[t] |= 1u << 27;
+    }
   }
   HIPCHK(h->rowrec.ensure(rows * sizeof(int)));
   HIPCHK(h->rec.ensure(std::max<size_t>(recs.size(), 1) * sizeof(uint4)));
