@@ -136,6 +136,49 @@ def test_random_state_two_steps(lbm, lattice, model, storage):
     assert rel_inf(sg, so) <= TOL_STRESS[storage] and rel_inf(Sg, So) <= TOL_STRESS[storage]
 
 
+@pytest.mark.parametrize("nx", [256, 512])
+@pytest.mark.parametrize("case", ["walls", "periodic"])
+@pytest.mark.parametrize("lattice", [W.D2Q9, W.D3Q19])
+def test_fp32_rows_staged_through_lds(lbm, lattice, case, nx):
+    """FP32 odd steps stage the x-shifted directions of tiles of whole rows
+    without boundary links through LDS (rows of 256 here); rows of 512 take
+    the unstaged buffer path.  Three- and four-step calls (staged odd steps
+    between others) from a seeded state, with boundary rows (walls, a moving
+    wall, a solid body) mixed in or a fully periodic box, against the
+    oracle."""
+    if lattice == W.D2Q9:
+        ny, nz = 12, 1
+        mask = W.cylinder_mask(nx, ny, 40.3, 6.1, 2.7)
+        walls = ((1, 0, 1),)
+    else:
+        ny, nz = 6, 5
+        mask = W.sphere_mask(nx, ny, nz, 60.4, 2.6, 2.1, 1.6)
+        walls = ((1, 0, 1), (2, 2, 3))
+    if case == "periodic":
+        mask, walls = np.zeros_like(mask), ()
+    w = W.Workload("lds_rows", lattice, nx, ny, nz, 0.62, dx=0.5, dt=0.2, model=W.GUO, storage=W.F32,
+                   body_force=(0.05, -0.02, 0.03 if lattice == W.D3Q19 else 0.0), walls=walls,
+                   wall_velocity=((1, 0.08, 0.0, 0.03),) if walls else (), les_cs=0.1, groups=5)
+    Q = 9 if lattice == W.D2Q9 else 19
+    say("case lds rows", lattice, case, nx)
+    d0 = W.random_state(Q, nx, ny, nz, 2e-3, seed=31) * (1 - mask[None])
+    g = gpu_from(w, lbm, init=False)
+    g.add_solid_mask(mask, 4)
+    g.set_state(d0)
+    o = make_oracle(w, init=False)
+    o.set_solid(mask, 4)
+    o.groups = 5
+    o.set_state(d0)
+    for n in (3, 4):
+        g.step(n)
+        o.step(n)
+        st = rel_inf(g.get_state(), o.get_state())
+        say("  %d steps: state err %.2e" % (n, st))
+        assert st <= TOL_FIELD[W.F32]
+        if walls:
+            compare_all(g, o, W.F32, 5, "  lds rows")
+
+
 def test_couette_cylinder_fp32(lbm):
     """D2Q9 Couette + force + cylinder (reduced 128x32 version, 3000 steps),
     FP32 storage vs FP64 oracle; the momentum-flux correction vanishes."""
