@@ -260,7 +260,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adj(const AdjArgs a) {
       v[s * NWALL + 2] = (double)pu[s][2];
       v[s * NWALL + 3] = 0.0;
     }
-    tile_sum_store<MAXBG * NWALL, true>(v, a.part + (uint64_t)blockIdx.x * NPART + NBAL);
+    tile_sum_store<MAXBG * NWALL, true>(v, a.part + (uint64_t)NBAL * gridDim.x + blockIdx.x, gridDim.x);
   }
 }
 

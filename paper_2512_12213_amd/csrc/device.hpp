@@ -437,11 +437,11 @@ __device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, con
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
-// Sum of v over the 256-thread tile (deterministic order) into out[0..NV),
-// stored (ADD = false) or added to what is there (ADD = true).  Every thread
-// of the tile must call it.
+// Sum of v over the 256-thread tile (deterministic order) into
+// out[k * stride], k < NV, stored (ADD = false) or added to what is there
+// (ADD = true).  Every thread of the tile must call it.
 template <int NV, bool ADD = false>
-__device__ __forceinline__ void tile_sum_store(double (&v)[NV], double* __restrict__ out) {
+__device__ __forceinline__ void tile_sum_store(double (&v)[NV], double* __restrict__ out, uint64_t stride = 1) {
   __shared__ double sh[NTHREADS / 64][NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -459,7 +459,7 @@ __device__ __forceinline__ void tile_sum_store(double (&v)[NV], double* __restri
   if (threadIdx.x < NV) {
     const int k = threadIdx.x;
     const double t = (sh[0][k] + sh[1][k]) + (sh[2][k] + sh[3][k]);
-    out[k] = ADD ? out[k] + t : t;
+    out[k * stride] = ADD ? out[k * stride] + t : t;
   }
 }
 

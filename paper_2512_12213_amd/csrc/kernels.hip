@@ -544,14 +544,23 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
     }
   }
   if (DIAG) {
-    double v[NPART];
+    if (bgrp >> 28) {
+      double v[NPART];
 #pragma unroll
-    for (int k = 0; k < NBAL; ++k) v[k] = (double)bal[k];
+      for (int k = 0; k < NBAL; ++k) v[k] = (double)bal[k];
 #pragma unroll
-    for (int s = 0; s < MAXBG; ++s)
+      for (int s = 0; s < MAXBG; ++s)
 #pragma unroll
-      for (int k = 0; k < NWALL; ++k) v[NBAL + s * NWALL + k] = (double)wacc[s][k];
-    tile_sum_store<NPART>(v, a.part + (uint64_t)blockIdx.x * NPART);
+        for (int k = 0; k < NWALL; ++k) v[NBAL + s * NWALL + k] = (double)wacc[s][k];
+      tile_sum_store<NPART>(v, a.part + blockIdx.x, gridDim.x);
+    } else {
+      // no wall group meets this tile (uniform per tile): its wall slots are
+      // never read, only the balance sums are formed
+      double v[NBAL];
+#pragma unroll
+      for (int k = 0; k < NBAL; ++k) v[k] = (double)bal[k];
+      tile_sum_store<NBAL>(v, a.part + blockIdx.x, gridDim.x);
+    }
   }
 }
 
@@ -727,7 +736,7 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
       }
     }
   }
-  if (a.part) tile_sum_store<NDIAGPART>(part, a.part + (uint64_t)blockIdx.x * NDIAGPART);
+  if (a.part) tile_sum_store<NDIAGPART>(part, a.part + blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1046,25 +1055,32 @@ __global__ __launch_bounds__(NTHREADS) void k_init(const InitArgs a) {
 // ---------------------------------------------------------------------------
 // deterministic reductions of per-tile partial sums
 // ---------------------------------------------------------------------------
-// mode 0: step partials [ntiles][NPART] -> out[NBAL + MAXG * NWALL]
-// mode 1: diagnostic partials [ntiles][NDIAGPART] -> out[NDIAGPART]
+// mode 0: step partials [NPART][ntiles] -> out[NBAL + MAXG * NWALL]
+// mode 1: diagnostic partials [NDIAGPART][ntiles] -> out[NDIAGPART]
+// (partials are quantity-major, so that a block's loads are coalesced; the
+// loop keeps eight independent sums in flight; fixed order, deterministic)
 __global__ __launch_bounds__(NTHREADS) void k_reduce(const double* __restrict__ part, const uint32_t* __restrict__ blkgrp,
                                                      uint32_t ntiles, int mode, double* __restrict__ out) {
   const int o = blockIdx.x;
-  double s = 0.0;
-  if (mode == 1) {
-    for (uint32_t t = threadIdx.x; t < ntiles; t += NTHREADS) s += part[(uint64_t)t * NDIAGPART + o];
-  } else if (o < NBAL) {
-    for (uint32_t t = threadIdx.x; t < ntiles; t += NTHREADS) s += part[(uint64_t)t * NPART + o];
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (mode == 1 || o < NBAL) {
+    const double* row = part + (uint64_t)o * ntiles;
+    uint32_t t = threadIdx.x;
+    for (; t + 7 * NTHREADS < ntiles; t += 8 * NTHREADS) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] += row[t + j * NTHREADS];
+    }
+    for (; t < ntiles; t += NTHREADS) acc[0] += row[t];
   } else {
     const uint32_t grp = (o - NBAL) / NWALL, k = (o - NBAL) % NWALL;
     for (uint32_t t = threadIdx.x; t < ntiles; t += NTHREADS) {
       const uint32_t bg = blkgrp[t];
       const uint32_t cnt = bg >> 28;
       for (uint32_t sl = 0; sl < cnt; ++sl)
-        if (((bg >> (4 * sl)) & 15u) == grp) s += part[(uint64_t)t * NPART + NBAL + sl * NWALL + k];
+        if (((bg >> (4 * sl)) & 15u) == grp) acc[0] += part[(uint64_t)(NBAL + sl * NWALL + k) * ntiles + t];
     }
   }
+  const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   double v[1] = {s};
   tile_sum_store<1>(v, out + o);
 }
