@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and workloads")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--only", choices=["adjoint", "hartmann"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "hartmann", "halfstep"], default=None,
                     help="run only this measurement (for profiling its kernels) and print its record")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a plain copy kernel of known size, "
@@ -143,6 +143,25 @@ def timed_run(lbm, torch, w, steps, warmup, storage=None):
         "balance_residual_rel": float(np.abs(bal[9:12]).max() / max(abs(bal[3]), 1e-300)),
         "wall_force_x_total": float(fw[:, 0, 0].sum()),
     }
+
+
+def halfstep_run(lbm, torch, W, calls=5):
+    """The half-step distribution of the last step (one read-only kernel over
+    the state, FP64 outputs, then the device-to-host copies) on the FP32 duct
+    after 20 steps: whole-call time with density, velocity and stress
+    requested (the kernel's own time is in the rocprofv3 trace)."""
+    w = W.duct_les()
+    lat = lbm.from_workload(w)
+    lat.step(20)
+    lat.halfstep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        lat.halfstep()
+    t = (time.perf_counter() - t0) / calls
+    lat.close()
+    return {"call_ms": t * 1e3, "nodes": w.N,
+            "outputs": "f_bar, rho_bar, u_bar, sigma_bar to host (FP64)"}
 
 
 def adjoint_run(lbm, torch, W, adj_prec, K=40, repeats=3):
@@ -321,6 +340,9 @@ def main():
         rh = timed_run(lbm, torch, W.hartmann_duct(), args.steps, args.warmup)
         print(json.dumps({"hartmann_duct_f32_192x96x96": rh}), flush=True)
         return
+    if args.only == "halfstep":
+        print(json.dumps({"halfstep_duct_les_f32_256x128x128": halfstep_run(lbm, torch, W)}), flush=True)
+        return
 
     w = W.duct_les()
     print("bench: headline FP32 duct, warmup %d, timed %d steps" % (args.warmup, args.steps),
@@ -374,6 +396,10 @@ def main():
         variants["duct_no_les_f32"] = timed_run(lbm, torch, wn, half, min(args.warmup, 10))
         print("bench: variant large duct (beyond the last-level cache)", file=sys.stderr, flush=True)
         variants["duct_les_f32_512x256x256"] = timed_run(lbm, torch, W.duct_les(nx=512, ny=256, nz=256), 60, 5)
+        print("bench: variant duct with the Stokes equilibrium and porous resistance", file=sys.stderr, flush=True)
+        wsd = W.duct_les()
+        wsd.stokes, wsd.darcy = True, 1e-4
+        variants["duct_stokes_darcy_f32"] = timed_run(lbm, torch, wsd, half, min(args.warmup, 10))
         print("bench: variant hartmann duct", file=sys.stderr, flush=True)
         variants["hartmann_duct_f32_192x96x96"] = timed_run(lbm, torch, W.hartmann_duct(), half, 10)
         print("bench: variant hartmann duct, Lorentz-force coupling", file=sys.stderr, flush=True)

@@ -1060,8 +1060,13 @@ __global__ __launch_bounds__(NTHREADS) void k_init(const InitArgs a) {
 // (partials are quantity-major, so that a block's loads are coalesced; the
 // loop keeps eight independent sums in flight; fixed order, deterministic)
 __global__ __launch_bounds__(NTHREADS) void k_reduce(const double* __restrict__ part, const uint32_t* __restrict__ blkgrp,
-                                                     uint32_t ntiles, int mode, double* __restrict__ out) {
+                                                     uint32_t ntiles, int mode, int G, double* __restrict__ out) {
   const int o = blockIdx.x;
+  if (mode == 0 && o >= NBAL && (o - NBAL) / NWALL >= G) {
+    // a group that is not in use (uniform per block)
+    if (threadIdx.x == 0) out[o] = 0.0;
+    return;
+  }
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (mode == 1 || o < NBAL) {
     const double* row = part + (uint64_t)o * ntiles;
@@ -1073,11 +1078,17 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(const double* __restrict__ 
     for (; t < ntiles; t += NTHREADS) acc[0] += row[t];
   } else {
     const uint32_t grp = (o - NBAL) / NWALL, k = (o - NBAL) % NWALL;
-    for (uint32_t t = threadIdx.x; t < ntiles; t += NTHREADS) {
-      const uint32_t bg = blkgrp[t];
-      const uint32_t cnt = bg >> 28;
-      for (uint32_t sl = 0; sl < cnt; ++sl)
-        if (((bg >> (4 * sl)) & 15u) == grp) acc[0] += part[(uint64_t)(NBAL + sl * NWALL + k) * ntiles + t];
+    uint32_t t = threadIdx.x;
+    for (; t < ntiles; t += 8 * NTHREADS) {
+      uint32_t bg[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bg[j] = t + j * NTHREADS < ntiles ? blkgrp[t + j * NTHREADS] : 0u;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t cnt = bg[j] >> 28;
+        for (uint32_t sl = 0; sl < cnt; ++sl)
+          if (((bg[j] >> (4 * sl)) & 15u) == grp) acc[j] += part[(uint64_t)(NBAL + sl * NWALL + k) * ntiles + t + j * NTHREADS];
+      }
     }
   }
   const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
@@ -1253,9 +1264,9 @@ hipError_t launch_init(int lattice, int prec, int mhd, const InitArgs& a, hipStr
   LBM_DISPATCH(launch_init_t, lattice, prec, mhd, a, st);
 }
 
-hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t ntiles, int mode, int nout, double* out,
+hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t ntiles, int mode, int G, int nout, double* out,
                          hipStream_t st) {
-  k_reduce<<<nout, NTHREADS, 0, st>>>(part, blkgrp, ntiles, mode, out);
+  k_reduce<<<nout, NTHREADS, 0, st>>>(part, blkgrp, ntiles, mode, G, out);
   return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ namespace lbm {
 hipError_t launch_step(int lattice, int prec, int mhd, const StepArgs& a, int parity, bool diag, hipStream_t st);
 hipError_t launch_diag(int lattice, int prec, int mhd, const DiagArgs& a, hipStream_t st);
 hipError_t launch_init(int lattice, int prec, int mhd, const InitArgs& a, hipStream_t st);
-hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t ntiles, int mode, int nout, double* out,
+hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t ntiles, int mode, int G, int nout, double* out,
                          hipStream_t st);
 hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, bool diag, hipStream_t st);
 hipError_t launch_half(int lattice, int prec, int mhd, const HalfArgs& a, hipStream_t st);
@@ -810,7 +810,7 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
     if (h->timing) HIPCHK(hipEventRecord(h->ev[i + 1], h->stream));
     h->parity ^= 1;
   }
-  HIPCHK(launch_reduce((const double*)h->part.p, (const uint32_t*)h->blkgrp.p, h->ntiles, 0, NBAL + MAXG * NWALL,
+  HIPCHK(launch_reduce((const double*)h->part.p, (const uint32_t*)h->blkgrp.p, h->ntiles, 0, h->G, NBAL + MAXG * NWALL,
                        (double*)h->red.p, h->stream));
   HIPCHK(hipMemcpyAsync(h->hred, h->red.p, (NBAL + MAXG * NWALL) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   double* ibb_host = h->hred + 2 * (NBAL + MAXG * NWALL) + NDIAGPART;
@@ -1018,7 +1018,7 @@ int lbm_force_balance(lbm_ctx* h, double* out) {
   a.part = (double*)h->dpart.p;
   rc = run_diag(h, a);
   if (rc) return rc;
-  HIPCHK(launch_reduce((const double*)h->dpart.p, nullptr, h->ntiles, 1, NDIAGPART, (double*)h->dred.p, h->stream));
+  HIPCHK(launch_reduce((const double*)h->dpart.p, nullptr, h->ntiles, 1, 0, NDIAGPART, (double*)h->dred.p, h->stream));
   double* dr = h->hred + NBAL + MAXG * NWALL;
   HIPCHK(hipMemcpyAsync(dr, h->dred.p, NDIAGPART * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -1178,7 +1178,7 @@ int lbm_adjoint_backward(lbm_ctx* h, double gJ, void* grad_a_dev, int grad_f64, 
     }
   }
   double* hr = h->hred + NBAL + MAXG * NWALL + NDIAGPART;
-  HIPCHK(launch_reduce((const double*)h->adjpart.p, (const uint32_t*)h->blkgrp.p, h->ntiles, 0, NBAL + MAXG * NWALL,
+  HIPCHK(launch_reduce((const double*)h->adjpart.p, (const uint32_t*)h->blkgrp.p, h->ntiles, 0, h->G, NBAL + MAXG * NWALL,
                        (double*)h->adjred.p, h->stream));
   HIPCHK(hipMemcpyAsync(hr, h->adjred.p, (NBAL + MAXG * NWALL) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
