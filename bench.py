@@ -313,7 +313,7 @@ def errors_vs_oracle(lbm, W):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the distributed slab decomposition is design-only); "
+        print("bench.py: runs on one GPU only (the decomposition over several GPUs is not implemented); "
               "got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
