@@ -50,11 +50,9 @@ struct Stor<S_BF16> {
   static __device__ __forceinline__ T ld(const E* p) {
     return __uint_as_float(uint32_t(*p) << 16);
   }
-  static __device__ __forceinline__ void st(E* p, T v) {
-    uint32_t u = __float_as_uint(v);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    *p = uint16_t(u >> 16);
-  }
+  // round to nearest even (the hardware conversion; the same bits as the
+  // integer form u + 0x7FFF + lsb for every finite value)
+  static __device__ __forceinline__ void st(E* p, T v) { *p = __builtin_bit_cast(uint16_t, (__bf16)v); }
 };
 
 // A parameter in the arithmetic type T: the FP64 value, or its FP32 copy
@@ -75,6 +73,17 @@ __device__ __forceinline__ T rcp(T x) {
 template <>
 __device__ __forceinline__ float rcp<float>(float x) {
   return __builtin_amdgcn_rcpf(x);
+}
+
+// Square root: FP64 correctly rounded; FP32 the hardware instruction (within
+// 1 ulp, without the correction steps of the correctly rounded expansion).
+template <class T>
+__device__ __forceinline__ T vsqrt(T x) {
+  return sqrt(x);
+}
+template <>
+__device__ __forceinline__ float vsqrt<float>(float x) {
+  return __builtin_amdgcn_sqrtf(x);
 }
 
 // The same formats through a buffer resource (scalar base and range,
@@ -116,9 +125,7 @@ struct BufIO<S_BF16> {
     return __uint_as_float(uint32_t((uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, v, s, 0)) << 16);
   }
   static __device__ __forceinline__ void st(float x, __amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t s) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)(u >> 16), r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, (__bf16)x), r, v, s, 0);
   }
 };
 
@@ -319,9 +326,14 @@ __device__ __forceinline__ E* pick(bool c, E* a, E* b) {
   return (E*)(((uint64_t)a & m) | ((uint64_t)b & ~m));
 }
 
+// Sums start from -0, the exact additive identity (x + -0 = x for every x,
+// while 0 + -0 = +0), so that the compiler can drop the first addition.
+template <class T>
+constexpr T ZERO = T(-0.0);
+
 template <class L, class T>
 __device__ __forceinline__ T edot(int q, T vx, T vy, T vz) {
-  T s = T(0);
+  T s = ZERO<T>;
   if (L::ex(q) > 0) s += vx;
   if (L::ex(q) < 0) s -= vx;
   if (L::ey(q) > 0) s += vy;

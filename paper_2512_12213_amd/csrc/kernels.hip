@@ -58,7 +58,7 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
     ps[k] = d[2 * k + 1] + d[2 * k + 2];
     pt[k] = d[2 * k + 1] - d[2 * k + 2];
   }
-  T drho = d[0], jx = T(0), jy = T(0), jz = T(0);
+  T drho = d[0], jx = ZERO<T>, jy = ZERO<T>, jz = ZERO<T>;
 #pragma unroll
   for (int k = 0; k < (L::Q - 1) / 2; ++k) {
     const int q = 2 * k + 1;
@@ -112,7 +112,7 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
   m.tau = par<T>(p.tau0, p.f.tau0);
   m.itau = par<T>(p.inv_tau0, p.f.inv_tau0);
   if (NEED_PI || p.les_K > 0.0) {
-    T sxx = T(0), syy = T(0), szz = T(0), sxy = T(0), sxz = T(0), syz = T(0);
+    T sxx = ZERO<T>, syy = ZERO<T>, szz = ZERO<T>, sxy = ZERO<T>, sxz = ZERO<T>, syz = ZERO<T>;
 #pragma unroll
     for (int k = 0; k < (L::Q - 1) / 2; ++k) {
       const int q = 2 * k + 1;  // e_q e_q is the same for q and its opposite
@@ -153,9 +153,9 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
       // (dimensionless form; dx / (c dt) = 1).
       const T pp = m.pi[0] * m.pi[0] + m.pi[1] * m.pi[1] + m.pi[2] * m.pi[2] +
                    T(2) * (m.pi[3] * m.pi[3] + m.pi[4] * m.pi[4] + m.pi[5] * m.pi[5]);
-      const T qn = sqrt(pp);
+      const T qn = vsqrt(pp);
       const T t0 = par<T>(p.tau0, p.f.tau0);
-      m.tau = T(0.5) * (t0 + sqrt(t0 * t0 + par<T>(p.les_K, p.f.les_K) * qn * m.irho));
+      m.tau = T(0.5) * (t0 + vsqrt(t0 * t0 + par<T>(p.les_K, p.f.les_K) * qn * m.irho));
       m.itau = rcp(m.tau);
     }
   }
@@ -295,7 +295,7 @@ __device__ __forceinline__ void ind_moments(const T (&h)[Ind<L>::K][Ind<L>::NB],
   constexpr int NB = Ind<L>::NB;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    T s = T(0);
+    T s = ZERO<T>;
     if (i < NB) {
 #pragma unroll
       for (int k = 0; k < Ind<L>::K; ++k) s += h[k][i < NB ? i : 0];
@@ -342,7 +342,7 @@ template <class L, int P, int MHD, int PAR, bool DIAG, bool MAC, bool BND, class
 __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const AD& Af, const AD& Ag, const uint4& rec,
                                             typename Stor<P>::T (&bal)[NBAL],
                                             typename Stor<P>::T (&wacc)[MAXBG][NWALL], uint32_t bgrp,
-                                            uint32_t x = 0) {
+                                            uint32_t x = 0, const typename Stor<P>::T* uwl = nullptr) {
   using S = Stor<P>;
   using T = typename S::T;
   const Geom& g = a.geo;
@@ -424,7 +424,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
       // exchange per link is proportional to e_q (2 d_rel + ladd) beyond the
       // constant rest-state part, which the host adds from link counts.
       const uint32_t gr = nibble(rec, q);
-      const T ux = (T)a.uw[3 * gr], uy = (T)a.uw[3 * gr + 1], uz = (T)a.uw[3 * gr + 2];  // u_w / c
+      const T ux = uwl[3 * gr], uy = uwl[3 * gr + 1], uz = uwl[3 * gr + 2];  // u_w / c, from LDS
       const T ladd = T(-6) * (T)L::w(q) * m.rho * edot<L>(q, ux, uy, uz);
       const T out = v;
       v = out + ladd;
@@ -498,7 +498,15 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   // LDS x-staging on odd steps: FP32 (odd step -5 %); the 2-byte formats
   // and the diagnostic variant (register pressure) measured slower with it
   constexpr bool XS_OK = RU == 2 && MHD == 0 && PAR == 1 && !MAC && !DIAG && P == S_F32;
-  const uint32_t bgrp = (DIAG || XS_OK) ? a.blkgrp[blockIdx.x] : 0u;
+  const uint32_t bgrp = a.blkgrp[blockIdx.x];
+  // Tiles that a wall group meets (uniform per tile) put the wall velocities
+  // in LDS: each wall link reads its group's velocity behind its own branch,
+  // and from memory those reads would wait one link after the other.
+  __shared__ T suw[3 * MAXG];
+  if (bgrp >> 28) {
+    if (threadIdx.x < 3 * MAXG) suw[threadIdx.x] = (T)a.uw[threadIdx.x];
+    __syncthreads();
+  }
   if (active) {
     uint32_t x, y, z, r;
     coords(g, n, x, y, z, r);
@@ -532,14 +540,14 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
         if (rr < 0)
           node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
         else
-          node_update<L, P, MHD, PAR, DIAG, MAC, true>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          node_update<L, P, MHD, PAR, DIAG, MAC, true>(a, n, Af, Ag, rec, bal, wacc, bgrp, 0u, suw);
       } else {
         const AddrG Af = addr_g(g, x, y, z, r, L::Q);
         const AddrG Ag = addr_g(g, x, y, z, r, MHD ? Ind<L>::K * Ind<L>::NB : L::Q);
         if (rr < 0)
           node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
         else
-          node_update<L, P, MHD, PAR, DIAG, MAC, true>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          node_update<L, P, MHD, PAR, DIAG, MAC, true>(a, n, Af, Ag, rec, bal, wacc, bgrp, 0u, suw);
       }
     }
   }
@@ -760,8 +768,14 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
 // other thread of this pass writes.
 // One wavefront per block: the list is short (boundary nodes only) and its
 // gathers are scattered, so spreading it over as many compute units as
-// possible is what shortens the pass.
+// possible is what shortens the pass.  The pass is bound by the latency of
+// its chains of dependent loads, so it keeps them short: the list carries
+// each node's boundary record (no lookup through the row table), and the
+// wall velocities, indexed by each link's group, are read from LDS (a load
+// per wall link, each behind its own branch, would otherwise wait for memory
+// one link after the other).
 constexpr int IBB_THREADS = 64;
+static_assert(IBB_THREADS >= 3 * MAXG, "one thread per wall-velocity component");
 
 template <class L, int P, int PAR>
 __global__ __launch_bounds__(IBB_THREADS) void k_ibb(const IbbArgs a) {
@@ -769,6 +783,9 @@ __global__ __launch_bounds__(IBB_THREADS) void k_ibb(const IbbArgs a) {
   using E = typename S::E;
   using TS = typename S::T;
   const Geom& g = a.geo;
+  __shared__ double suw[MAXG][3];
+  if (threadIdx.x < 3 * MAXG) (&suw[0][0])[threadIdx.x] = (&a.uw[0][0])[threadIdx.x];
+  __syncthreads();
   const uint32_t i = blockIdx.x * IBB_THREADS + threadIdx.x;
   if (i >= a.M) return;
   // every read comes before the first store (the stores could alias the
@@ -777,10 +794,10 @@ __global__ __launch_bounds__(IBB_THREADS) void k_ibb(const IbbArgs a) {
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) qv[q] = a.qf[(uint64_t)i * L::Q + q];
   const uint32_t n = a.node[i];
+  const uint4 rec = a.nrec[i];
   uint32_t x, y, z, r;
   coords(g, n, x, y, z, r);
   const AddrG Af = addr_g(g, x, y, z, r, L::Q);
-  const uint4 rec = a.rec[a.rowrec[r] + x];
   const uint32_t mask = rec.x;
   E* f = (E*)a.f;
   TS d1[L::Q];
@@ -797,7 +814,7 @@ __global__ __launch_bounds__(IBB_THREADS) void k_ibb(const IbbArgs a) {
     sV += v;
     if (wall) {
       const uint32_t gr = nibble(rec, q);
-      K += 6.0 * L::w(q) * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
+      K += 6.0 * L::w(q) * edot<L>(q, suw[gr][0], suw[gr][1], suw[gr][2]);
     }
   }
   const double rho_t = (a.p.rho0 + sV) / (1.0 - K);
@@ -808,7 +825,7 @@ __global__ __launch_bounds__(IBB_THREADS) void k_ibb(const IbbArgs a) {
     R[q] = V[q];
     if (q > 0 && ((mask >> q) & 1u)) {
       const uint32_t gr = nibble(rec, q);
-      R[q] += 6.0 * L::w(q) * rho_t * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
+      R[q] += 6.0 * L::w(q) * rho_t * edot<L>(q, suw[gr][0], suw[gr][1], suw[gr][2]);
     }
   }
   double dnew[L::Q];
@@ -818,7 +835,7 @@ __global__ __launch_bounds__(IBB_THREADS) void k_ibb(const IbbArgs a) {
     if (q == 0 || !((mask >> q) & 1u) || qv[q] == 0.5) continue;
     const int qb = opp(q);
     const uint32_t gr = nibble(rec, q);
-    const double ladd = -6.0 * L::w(q) * rho_t * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
+    const double ladd = -6.0 * L::w(q) * rho_t * edot<L>(q, suw[gr][0], suw[gr][1], suw[gr][2]);
     if (qv[q] < 0.5) {
       if (!((mask >> qb) & 1u)) dnew[q] = 2.0 * qv[q] * R[q] + (1.0 - 2.0 * qv[q]) * (double)d1[q] + ladd;
     } else {
@@ -883,6 +900,10 @@ __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
   using E = typename S::E;
   using TS = typename S::T;
   const Geom& g = a.geo;
+  // wall velocities by group, read per wall link from LDS
+  __shared__ double suw[MAXG][3];
+  if (threadIdx.x < 3 * MAXG) (&suw[0][0])[threadIdx.x] = (&a.uw[0][0])[threadIdx.x];
+  __syncthreads();
   const uint32_t n = blockIdx.x * NTHREADS + threadIdx.x;
   if (n >= g.N) return;
   uint32_t x, y, z, r;
@@ -911,7 +932,7 @@ __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
       sV += v;
       if (wall) {
         const uint32_t gr = nibble(rec, q);
-        K += 6.0 * L::w(q) * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
+        K += 6.0 * L::w(q) * edot<L>(q, suw[gr][0], suw[gr][1], suw[gr][2]);
       }
     }
     const double rho_t = (a.p.rho0 + sV) / (1.0 - K);
@@ -920,7 +941,7 @@ __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
       double rel = V[q];
       if (q > 0 && ((mask >> q) & 1u)) {
         const uint32_t gr = nibble(rec, q);
-        rel += 6.0 * L::w(q) * rho_t * edot<L>(q, a.uw[gr][0], a.uw[gr][1], a.uw[gr][2]);
+        rel += 6.0 * L::w(q) * rho_t * edot<L>(q, suw[gr][0], suw[gr][1], suw[gr][2]);
       }
       db[q] = 0.5 * (rel + (double)d1[q]);
     }

@@ -109,8 +109,7 @@ struct IbbArgs {
   const double* qf;        // [M][Q] wall distance / link length (1/2: halfway, left as is)
   const uint8_t* grp;      // [M][Q] wall group of each link
   double* delta;           // [M][Q] change of the returning value (diagnostic steps), or null
-  const uint4* rec;
-  const int* rowrec;
+  const uint4* nrec;       // [M] boundary record of each listed node (wall mask, group nibbles)
   double uw[MAXG][3];      // wall velocities / c of the step
   uint32_t M;
   Geom geo;

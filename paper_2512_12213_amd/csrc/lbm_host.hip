@@ -120,7 +120,7 @@ struct lbm_ctx {
   // walls that are not halfway: link fractions (host, [Q][N]) and the list of
   // nodes whose links are interpolated after each step
   std::vector<double> qlink;
-  DevBuf ibb_node, ibb_q, ibb_grp, ibb_delta, ibb_part, ibb_red;
+  DevBuf ibb_node, ibb_rec, ibb_q, ibb_grp, ibb_delta, ibb_part, ibb_red;
   uint32_t nibb = 0;
   double* hred = nullptr;  // pinned [NBAL + MAXG * NWALL]
   bool uw_dirty = true;
@@ -297,6 +297,7 @@ int build_geometry(lbm_ctx* h) {
   std::vector<uint32_t> inode;
   std::vector<double> iq;
   std::vector<uint8_t> igrp;
+  std::vector<uint4> irec;
   if (!h->qlink.empty()) {
     for (size_t row = 0; row < rows; ++row) {
       if (rowrec[row] < 0) continue;
@@ -309,6 +310,7 @@ int build_geometry(lbm_ctx* h) {
           if (((r.x >> q) & 1u) && h->qlink[(size_t)q * h->N + n] != 0.5) any = true;
         if (!any) continue;
         inode.push_back((uint32_t)n);
+        irec.push_back(r);
         for (int q = 0; q < Q; ++q) {
           const bool wall = q > 0 && ((r.x >> q) & 1u);
           const uint32_t wv = q < 8 ? r.y : (q < 16 ? r.z : r.w);
@@ -354,12 +356,14 @@ int build_geometry(lbm_ctx* h) {
   HIPCHK(h->uwdev.ensure(MAXG * 3 * sizeof(double)));
   if (h->nibb) {
     HIPCHK(h->ibb_node.ensure(inode.size() * sizeof(uint32_t)));
+    HIPCHK(h->ibb_rec.ensure(irec.size() * sizeof(uint4)));
     HIPCHK(h->ibb_q.ensure(iq.size() * sizeof(double)));
     HIPCHK(h->ibb_grp.ensure(igrp.size()));
     HIPCHK(h->ibb_delta.ensure(iq.size() * sizeof(double)));
     HIPCHK(h->ibb_red.ensure(MAXG * 4 * sizeof(double)));
     HIPCHK(h->ibb_part.ensure(((iq.size() + NTHREADS - 1) / NTHREADS) * MAXG * 4 * sizeof(double)));
     HIPCHK(hipMemcpy(h->ibb_node.p, inode.data(), inode.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->ibb_rec.p, irec.data(), irec.size() * sizeof(uint4), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(h->ibb_q.p, iq.data(), iq.size() * sizeof(double), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(h->ibb_grp.p, igrp.data(), igrp.size(), hipMemcpyHostToDevice));
   }
@@ -773,8 +777,7 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
     ib.node = (const uint32_t*)h->ibb_node.p;
     ib.qf = (const double*)h->ibb_q.p;
     ib.grp = (const uint8_t*)h->ibb_grp.p;
-    ib.rec = (const uint4*)h->rec.p;
-    ib.rowrec = (const int*)h->rowrec.p;
+    ib.nrec = (const uint4*)h->ibb_rec.p;
     for (int gr = 0; gr < MAXG; ++gr)
       for (int k = 0; k < 3; ++k) ib.uw[gr][k] = h->uw[gr][k] / h->c;
     ib.M = h->nibb;
