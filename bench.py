@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and workloads")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--only", choices=["adjoint", "hartmann", "halfstep"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "hartmann", "halfstep", "sphere"], default=None,
                     help="run only this measurement (for profiling its kernels) and print its record")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a plain copy kernel of known size, "
@@ -342,6 +342,16 @@ def main():
         return
     if args.only == "halfstep":
         print(json.dumps({"halfstep_duct_les_f32_256x128x128": halfstep_run(lbm, torch, W)}), flush=True)
+        return
+    if args.only == "sphere":
+        # the duct with a sphere, halfway and interpolated walls
+        rs = {}
+        for curved in (False, True):
+            ws = W.duct_sphere()
+            ws.curved = curved
+            rs["duct_sphere_%sf32_128x64x64" % ("curved_" if curved else "")] = timed_run(
+                lbm, torch, ws, args.steps, args.warmup)
+        print(json.dumps(rs), flush=True)
         return
 
     w = W.duct_les()

@@ -40,8 +40,7 @@ namespace lbm {
 
 template <class L, int PS, int PL, int PAR, bool SEED, bool BND, class AD>
 __device__ __forceinline__ void adj_node(const AdjArgs& a, uint32_t n, const AD& Al, const uint4& rec,
-                                         typename Stor<PL>::T (&pu)[MAXBG][3], uint32_t bgrp,
-                                         const typename Stor<PL>::T* uwl = nullptr) {
+                                         typename Stor<PL>::T (&pu)[MAXBG][3], uint32_t bgrp) {
   using S = Stor<PL>;
   using T = typename S::T;
   using E = typename S::E;
@@ -164,7 +163,7 @@ __device__ __forceinline__ void adj_node(const AdjArgs& a, uint32_t n, const AD&
     for (int q = 1; q < L::Q; ++q) {
       if ((mask >> q) & 1u) {
         const uint32_t gr = nibble(rec, q);
-        const T ux = uwl[3 * gr], uy = uwl[3 * gr + 1], uz = uwl[3 * gr + 2];  // from LDS
+        const T ux = (T)a.uw[3 * gr], uy = (T)a.uw[3 * gr + 1], uz = (T)a.uw[3 * gr + 2];
         const T muL = SEED ? T(0.5) * mu[q] : mu[q];
         const T c6 = T(-6) * (T)L::w(q) * muL;
         Mrho += c6 * edot<L>(q, ux, uy, uz);
@@ -221,13 +220,6 @@ __global__ __launch_bounds__(NTHREADS) void k_adj(const AdjArgs a) {
   const Geom& g = a.geo;
   const uint32_t n = blockIdx.x * NTHREADS + threadIdx.x;
   const uint32_t bgrp = a.blkgrp[blockIdx.x];
-  // wall velocities in LDS for tiles with wall links (uniform per tile), as
-  // in the forward step
-  __shared__ T suw[3 * MAXG];
-  if (bgrp >> 28) {
-    if (threadIdx.x < 3 * MAXG) suw[threadIdx.x] = (T)a.uw[threadIdx.x];
-    __syncthreads();
-  }
   T pu[MAXBG][3];
 #pragma unroll
   for (int s = 0; s < MAXBG; ++s) pu[s][0] = pu[s][1] = pu[s][2] = T(0);
@@ -247,13 +239,13 @@ __global__ __launch_bounds__(NTHREADS) void k_adj(const AdjArgs a) {
         if (rr < 0)
           adj_node<L, PS, PL, PAR, SEED, false>(a, n, Al, rec, pu, bgrp);
         else
-          adj_node<L, PS, PL, PAR, SEED, true>(a, n, Al, rec, pu, bgrp, suw);
+          adj_node<L, PS, PL, PAR, SEED, true>(a, n, Al, rec, pu, bgrp);
       } else {
         const AddrG Al = addr_g(g, x, y, z, r, L::Q);
         if (rr < 0)
           adj_node<L, PS, PL, PAR, SEED, false>(a, n, Al, rec, pu, bgrp);
         else
-          adj_node<L, PS, PL, PAR, SEED, true>(a, n, Al, rec, pu, bgrp, suw);
+          adj_node<L, PS, PL, PAR, SEED, true>(a, n, Al, rec, pu, bgrp);
       }
     }
   }
