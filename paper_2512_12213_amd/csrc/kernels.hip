@@ -495,9 +495,10 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
 #pragma unroll
       for (int k = 0; k < NWALL; ++k) wacc[s][k] = T(0);
   }
-  // LDS x-staging on odd steps: FP32 (odd step -5 %); the 2-byte formats
-  // and the diagnostic variant (register pressure) measured slower with it
-  constexpr bool XS_OK = RU == 2 && MHD == 0 && PAR == 1 && !MAC && !DIAG && P == S_F32;
+  // LDS x-staging on odd steps: FP32 (odd step -5 %) and FP64 (odd step
+  // -7 %, 40 KB of LDS per tile); the 2-byte formats and the diagnostic
+  // variant (register pressure) measured slower with it
+  constexpr bool XS_OK = RU == 2 && MHD == 0 && PAR == 1 && !MAC && !DIAG && (P == S_F32 || P == S_F64);
   const uint32_t bgrp = a.blkgrp[blockIdx.x];
   // Tiles that a wall group meets (uniform per tile) put the wall velocities
   // in LDS: each wall link reads its group's velocity behind its own branch,
@@ -1141,9 +1142,9 @@ static hipError_t launch_step_t(const StepArgs& a, int parity, bool diag, hipStr
   using E = typename Stor<P>::E;
   const uint64_t fb = (uint64_t)a.geo.N * L::Q * sizeof(E);
   const uint64_t gb = MHD ? (uint64_t)a.geo.N * Ind<L>::K * Ind<L>::NB * sizeof(E) : 0;
-  // buffer form for the 4- and 2-byte formats (measured: FP32 -1 %, FP16 and
-  // BF16 -6 to -8 %); FP64 keeps the pointer form (+2 % with buffers)
-  if (P != S_F64 && a.geo.nx % 64 == 0 && fb < (1ull << 32) && gb < (1ull << 32))
+  // buffer form (measured: FP32 -1 %, FP16 and BF16 -6 to -8 %; FP64 +2 %
+  // alone, but it carries the LDS staging of odd steps, and with it -4 %)
+  if (a.geo.nx % 64 == 0 && fb < (1ull << 32) && gb < (1ull << 32))
     launch_step_ru<L, P, MHD, 2>(a, parity, diag, nb, st);
   else if (a.geo.nx % 64 == 0)
     launch_step_ru<L, P, MHD, 1>(a, parity, diag, nb, st);

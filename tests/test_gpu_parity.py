@@ -136,16 +136,17 @@ def test_random_state_two_steps(lbm, lattice, model, storage):
     assert rel_inf(sg, so) <= TOL_STRESS[storage] and rel_inf(Sg, So) <= TOL_STRESS[storage]
 
 
+@pytest.mark.parametrize("storage", [W.F32, W.F64])
 @pytest.mark.parametrize("nx", [256, 512])
 @pytest.mark.parametrize("case", ["walls", "periodic"])
 @pytest.mark.parametrize("lattice", [W.D2Q9, W.D3Q19])
-def test_fp32_rows_staged_through_lds(lbm, lattice, case, nx):
-    """FP32 odd steps stage the x-shifted directions of tiles of whole rows
-    without boundary links through LDS (rows of 256 here); rows of 512 take
-    the unstaged buffer path.  Three- and four-step calls (staged odd steps
-    between others) from a seeded state, with boundary rows (walls, a moving
-    wall, a solid body) mixed in or a fully periodic box, against the
-    oracle."""
+def test_rows_staged_through_lds(lbm, lattice, case, nx, storage):
+    """FP32 and FP64 odd steps stage the x-shifted directions of tiles of
+    whole rows without boundary links through LDS (rows of 256 here); rows of
+    512 take the unstaged buffer path.  Three- and four-step calls (staged
+    odd steps between others) from a seeded state, with boundary rows (walls,
+    a moving wall, a solid body) mixed in or a fully periodic box, against
+    the oracle."""
     if lattice == W.D2Q9:
         ny, nz = 12, 1
         mask = W.cylinder_mask(nx, ny, 40.3, 6.1, 2.7)
@@ -156,11 +157,11 @@ def test_fp32_rows_staged_through_lds(lbm, lattice, case, nx):
         walls = ((1, 0, 1), (2, 2, 3))
     if case == "periodic":
         mask, walls = np.zeros_like(mask), ()
-    w = W.Workload("lds_rows", lattice, nx, ny, nz, 0.62, dx=0.5, dt=0.2, model=W.GUO, storage=W.F32,
+    w = W.Workload("lds_rows", lattice, nx, ny, nz, 0.62, dx=0.5, dt=0.2, model=W.GUO, storage=storage,
                    body_force=(0.05, -0.02, 0.03 if lattice == W.D3Q19 else 0.0), walls=walls,
                    wall_velocity=((1, 0.08, 0.0, 0.03),) if walls else (), les_cs=0.1, groups=5)
     Q = 9 if lattice == W.D2Q9 else 19
-    say("case lds rows", lattice, case, nx)
+    say("case lds rows", lattice, case, nx, storage)
     d0 = W.random_state(Q, nx, ny, nz, 2e-3, seed=31) * (1 - mask[None])
     g = gpu_from(w, lbm, init=False)
     g.add_solid_mask(mask, 4)
@@ -174,9 +175,9 @@ def test_fp32_rows_staged_through_lds(lbm, lattice, case, nx):
         o.step(n)
         st = rel_inf(g.get_state(), o.get_state())
         say("  %d steps: state err %.2e" % (n, st))
-        assert st <= TOL_FIELD[W.F32]
+        assert st <= TOL_FIELD[storage]
         if walls:
-            compare_all(g, o, W.F32, 5, "  lds rows")
+            compare_all(g, o, storage, 5, "  lds rows")
 
 
 def test_couette_cylinder_fp32(lbm):
