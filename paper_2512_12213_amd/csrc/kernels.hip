@@ -479,11 +479,32 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
 // RU: 0 generic addressing; 1 row-uniform pointers; 2 row-uniform pointers
 // for rows with boundary links and buffer resources for the other rows
 // (arrays below 4 GiB).
+// Tile of a workgroup on odd steps.  Workgroups are dealt to the eight XCDs
+// in turn (workgroup b to XCD b mod 8), each with its own L2.  When a row
+// spans k > 1 tiles, the odd step's x-shifted loads and stores at the tiles'
+// ends share 128-byte lines with the neighbouring tile of the same row; the
+// mapping gives the k tiles of a row to consecutive workgroups of one XCD, so
+// that these lines meet in one L2 (even steps, without x-shifted accesses,
+// keep the identity).  Groups of 8 k workgroups: j-th workgroup of a
+// group -> row (j mod 8) of the group's 8 rows, piece j / 8; the remainder
+// of the grid (fewer than 8 k tiles) keeps the identity.
+constexpr uint32_t NXCD = 8;
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles, uint32_t nx) {
+  const uint32_t k = (nx > NTHREADS && nx % NTHREADS == 0) ? nx / NTHREADS : 1u;
+  if (k == 1u) return b;
+  const uint32_t chunk = NXCD * k;
+  const uint32_t c = b / chunk;
+  if ((c + 1) * chunk > ntiles) return b;
+  const uint32_t j = b - c * chunk;
+  return c * chunk + (j % NXCD) * k + j / NXCD;
+}
+
 template <class L, int P, int MHD, int PAR, bool DIAG, int RU, bool MAC = false>
 __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   using T = typename Stor<P>::T;
   const Geom& g = a.geo;
-  const uint32_t n = blockIdx.x * NTHREADS + threadIdx.x;
+  const uint32_t tile = PAR == 1 ? xcd_tile(blockIdx.x, gridDim.x, g.nx) : blockIdx.x;
+  const uint32_t n = tile * NTHREADS + threadIdx.x;
   const bool active = n < g.N;
   T bal[NBAL];
   T wacc[MAXBG][NWALL];
@@ -499,7 +520,7 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   // -7 %, 40 KB of LDS per tile); the 2-byte formats and the diagnostic
   // variant (register pressure) measured slower with it
   constexpr bool XS_OK = RU == 2 && MHD == 0 && PAR == 1 && !MAC && !DIAG && (P == S_F32 || P == S_F64);
-  const uint32_t bgrp = a.blkgrp[blockIdx.x];
+  const uint32_t bgrp = a.blkgrp[tile];
   // Tiles that a wall group meets (uniform per tile) put the wall velocities
   // in LDS: each wall link reads its group's velocity behind its own branch,
   // and from memory those reads would wait one link after the other.
@@ -561,14 +582,14 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
       for (int s = 0; s < MAXBG; ++s)
 #pragma unroll
         for (int k = 0; k < NWALL; ++k) v[NBAL + s * NWALL + k] = (double)wacc[s][k];
-      tile_sum_store<NPART>(v, a.part + blockIdx.x, gridDim.x);
+      tile_sum_store<NPART>(v, a.part + tile, gridDim.x);
     } else {
       // no wall group meets this tile (uniform per tile): its wall slots are
       // never read, only the balance sums are formed
       double v[NBAL];
 #pragma unroll
       for (int k = 0; k < NBAL; ++k) v[k] = (double)bal[k];
-      tile_sum_store<NBAL>(v, a.part + blockIdx.x, gridDim.x);
+      tile_sum_store<NBAL>(v, a.part + tile, gridDim.x);
     }
   }
 }

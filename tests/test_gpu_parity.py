@@ -137,16 +137,19 @@ def test_random_state_two_steps(lbm, lattice, model, storage):
 
 
 @pytest.mark.parametrize("storage", [W.F32, W.F64])
-@pytest.mark.parametrize("nx", [256, 512])
+@pytest.mark.parametrize("nx", [256, 512, 768])
 @pytest.mark.parametrize("case", ["walls", "periodic"])
 @pytest.mark.parametrize("lattice", [W.D2Q9, W.D3Q19])
 def test_rows_staged_through_lds(lbm, lattice, case, nx, storage):
     """FP32 and FP64 odd steps stage the x-shifted directions of tiles of
     whole rows without boundary links through LDS (rows of 256 here); rows of
-    512 take the unstaged buffer path.  Three- and four-step calls (staged
-    odd steps between others) from a seeded state, with boundary rows (walls,
-    a moving wall, a solid body) mixed in or a fully periodic box, against
-    the oracle."""
+    512 and 768 take the unstaged buffer path, with the odd steps' tiles
+    dealt to workgroups so that a row's tiles share an XCD (30 or 12 rows:
+    whole groups of 8 rows and a remainder that keeps the identity).  Three-
+    and four-step calls (staged odd steps between others, the last one with
+    diagnostics) from a seeded state, with boundary rows (walls, a moving
+    wall, a solid body) mixed in or a fully periodic box, against the
+    oracle."""
     if lattice == W.D2Q9:
         ny, nz = 12, 1
         mask = W.cylinder_mask(nx, ny, 40.3, 6.1, 2.7)
