@@ -452,17 +452,39 @@ __device__ __forceinline__ void write_g(typename Stor<P>::E* __restrict__ g, con
 // Sum of v over the 256-thread tile (deterministic order) into
 // out[k * stride], k < NV, stored (ADD = false) or added to what is there
 // (ADD = true).  Every thread of the tile must call it.
+// x from another lane of the same row of 16 (DPP lane pattern CTRL), both
+// 32-bit halves moved by the vector ALU (no LDS round trip).  Every lane of
+// the wavefront must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+// Sum over the 64 lanes (the same value in every lane, fixed order): pairs,
+// quads and halves of each row of 16 by DPP (lane i with i ^ 1, i ^ 2, then
+// the mirrored lane of its half row and of its row), then the four row sums.
+__device__ __forceinline__ double wave_sum_f64(double s) {
+  s += dpp_f64<0xB1>(s);   // quad_perm [1,0,3,2]
+  s += dpp_f64<0x4E>(s);   // quad_perm [2,3,0,1]
+  s += dpp_f64<0x141>(s);  // row_half_mirror
+  s += dpp_f64<0x140>(s);  // row_mirror
+  return (readlane_f64(s, 0) + readlane_f64(s, 16)) + (readlane_f64(s, 32) + readlane_f64(s, 48));
+}
+
 template <int NV, bool ADD = false>
 __device__ __forceinline__ void tile_sum_store(double (&v)[NV], double* __restrict__ out, uint64_t stride = 1) {
   __shared__ double sh[NTHREADS / 64][NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = v[k];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    v[k] = s;
-  }
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum_f64(v[k]);
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) sh[wave][k] = v[k];
