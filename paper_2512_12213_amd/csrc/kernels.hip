@@ -1100,9 +1100,13 @@ __global__ __launch_bounds__(NTHREADS) void k_init(const InitArgs a) {
 // ---------------------------------------------------------------------------
 // mode 0: step partials [NPART][ntiles] -> out[NBAL + MAXG * NWALL]
 // mode 1: diagnostic partials [NDIAGPART][ntiles] -> out[NDIAGPART]
-// (partials are quantity-major, so that a block's loads are coalesced; the
-// loop keeps eight independent sums in flight; fixed order, deterministic)
-__global__ __launch_bounds__(NTHREADS) void k_reduce(const double* __restrict__ part, const uint32_t* __restrict__ blkgrp,
+// (partials are quantity-major, so that a block's loads are coalesced; fixed
+// order, deterministic).  The reduction is bound by the latency of its
+// loads, so each thread keeps 8 or 16 independent loads in flight, and a wall
+// group's sums visit only the tiles it meets: wlist holds, per group g, the
+// entries wlist[wlist[g]] .. wlist[wlist[g + 1] - 1], each a tile index
+// (bits 0-27) and the group's slot in that tile (bits 28-31), in tile order.
+__global__ __launch_bounds__(NTHREADS) void k_reduce(const double* __restrict__ part, const uint32_t* __restrict__ wlist,
                                                      uint32_t ntiles, int mode, int G, double* __restrict__ out) {
   const int o = blockIdx.x;
   if (mode == 0 && o >= NBAL && (o - NBAL) / NWALL >= G) {
@@ -1110,30 +1114,38 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(const double* __restrict__ 
     if (threadIdx.x == 0) out[o] = 0.0;
     return;
   }
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double acc[16] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (mode == 1 || o < NBAL) {
+    // a whole row: sixteen loads in flight per thread
     const double* row = part + (uint64_t)o * ntiles;
     uint32_t t = threadIdx.x;
-    for (; t + 7 * NTHREADS < ntiles; t += 8 * NTHREADS) {
+    for (; t + 15 * NTHREADS < ntiles; t += 16 * NTHREADS) {
+      double v[16];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) acc[j] += row[t + j * NTHREADS];
+      for (int j = 0; j < 16; ++j) v[j] = row[t + j * NTHREADS];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[j] += v[j];
     }
     for (; t < ntiles; t += NTHREADS) acc[0] += row[t];
   } else {
     const uint32_t grp = (o - NBAL) / NWALL, k = (o - NBAL) % NWALL;
-    uint32_t t = threadIdx.x;
-    for (; t < ntiles; t += 8 * NTHREADS) {
-      uint32_t bg[8];
+    const uint32_t b = wlist[grp], e = wlist[grp + 1];
+    uint32_t i = b + threadIdx.x;
+    for (; i + 7 * NTHREADS < e; i += 8 * NTHREADS) {
+      uint32_t en[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) bg[j] = t + j * NTHREADS < ntiles ? blkgrp[t + j * NTHREADS] : 0u;
+      for (int j = 0; j < 8; ++j) en[j] = wlist[i + j * NTHREADS];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const uint32_t cnt = bg[j] >> 28;
-        for (uint32_t sl = 0; sl < cnt; ++sl)
-          if (((bg[j] >> (4 * sl)) & 15u) == grp) acc[j] += part[(uint64_t)(NBAL + sl * NWALL + k) * ntiles + t + j * NTHREADS];
-      }
+      for (int j = 0; j < 8; ++j)
+        acc[j] += part[(uint64_t)(NBAL + (en[j] >> 28) * NWALL + k) * ntiles + (en[j] & 0x0FFFFFFFu)];
+    }
+    for (; i < e; i += NTHREADS) {
+      const uint32_t en = wlist[i];
+      acc[0] += part[(uint64_t)(NBAL + (en >> 28) * NWALL + k) * ntiles + (en & 0x0FFFFFFFu)];
     }
   }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] += acc[j + 8];
   const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   double v[1] = {s};
   tile_sum_store<1>(v, out + o);
@@ -1307,9 +1319,9 @@ hipError_t launch_init(int lattice, int prec, int mhd, const InitArgs& a, hipStr
   LBM_DISPATCH(launch_init_t, lattice, prec, mhd, a, st);
 }
 
-hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t ntiles, int mode, int G, int nout, double* out,
+hipError_t launch_reduce(const double* part, const uint32_t* wlist, uint32_t ntiles, int mode, int G, int nout, double* out,
                          hipStream_t st) {
-  k_reduce<<<nout, NTHREADS, 0, st>>>(part, blkgrp, ntiles, mode, G, out);
+  k_reduce<<<nout, NTHREADS, 0, st>>>(part, wlist, ntiles, mode, G, out);
   return hipGetLastError();
 }
 

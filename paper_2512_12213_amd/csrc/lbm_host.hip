@@ -18,7 +18,7 @@ namespace lbm {
 hipError_t launch_step(int lattice, int prec, int mhd, const StepArgs& a, int parity, bool diag, hipStream_t st);
 hipError_t launch_diag(int lattice, int prec, int mhd, const DiagArgs& a, hipStream_t st);
 hipError_t launch_init(int lattice, int prec, int mhd, const InitArgs& a, hipStream_t st);
-hipError_t launch_reduce(const double* part, const uint32_t* blkgrp, uint32_t ntiles, int mode, int G, int nout, double* out,
+hipError_t launch_reduce(const double* part, const uint32_t* wlist, uint32_t ntiles, int mode, int G, int nout, double* out,
                          hipStream_t st);
 hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, bool diag, hipStream_t st);
 hipError_t launch_half(int lattice, int prec, int mhd, const HalfArgs& a, hipStream_t st);
@@ -116,7 +116,7 @@ struct lbm_ctx {
   uint32_t nfluid = 0;
   std::vector<long> nlink;  // [MAXG][Q]
 
-  DevBuf f, g, rec, rowrec, blkgrp, uwdev, part, red, dpart, dred, tmp;
+  DevBuf f, g, rec, rowrec, blkgrp, wlist, uwdev, part, red, dpart, dred, tmp;
   // walls that are not halfway: link fractions (host, [Q][N]) and the list of
   // nodes whose links are interpolated after each step
   std::vector<double> qlink;
@@ -343,6 +343,21 @@ int build_geometry(lbm_ctx* h) {
       if (interior) tilegrp[t] |= 1u << 27;
     }
   }
+  // per wall group, the tiles it meets with its slot there, in tile order
+  // (offsets of the MAXG lists first): the reduction of the group's sums
+  // visits only these tiles
+  std::vector<uint32_t> wlist(MAXG + 1, 0);
+  for (int gr = 0; gr < MAXG; ++gr) {
+    wlist[gr] = (uint32_t)wlist.size();
+    for (uint32_t t = 0; t < h->ntiles; ++t) {
+      const uint32_t cnt = tilegrp[t] >> 28;
+      for (uint32_t sl = 0; sl < cnt; ++sl)
+        if (((tilegrp[t] >> (4 * sl)) & 15u) == (uint32_t)gr) wlist.push_back(t | (sl << 28));
+    }
+  }
+  wlist[MAXG] = (uint32_t)wlist.size();
+  HIPCHK(h->wlist.ensure(wlist.size() * sizeof(uint32_t)));
+  HIPCHK(hipMemcpy(h->wlist.p, wlist.data(), wlist.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
   HIPCHK(h->rowrec.ensure(rows * sizeof(int)));
   HIPCHK(h->rec.ensure(std::max<size_t>(recs.size(), 1) * sizeof(uint4)));
   HIPCHK(h->blkgrp.ensure((size_t)h->ntiles * sizeof(uint32_t)));
@@ -813,7 +828,7 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
     if (h->timing) HIPCHK(hipEventRecord(h->ev[i + 1], h->stream));
     h->parity ^= 1;
   }
-  HIPCHK(launch_reduce((const double*)h->part.p, (const uint32_t*)h->blkgrp.p, h->ntiles, 0, h->G, NBAL + MAXG * NWALL,
+  HIPCHK(launch_reduce((const double*)h->part.p, (const uint32_t*)h->wlist.p, h->ntiles, 0, h->G, NBAL + MAXG * NWALL,
                        (double*)h->red.p, h->stream));
   HIPCHK(hipMemcpyAsync(h->hred, h->red.p, (NBAL + MAXG * NWALL) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   double* ibb_host = h->hred + 2 * (NBAL + MAXG * NWALL) + NDIAGPART;
@@ -1181,7 +1196,7 @@ int lbm_adjoint_backward(lbm_ctx* h, double gJ, void* grad_a_dev, int grad_f64, 
     }
   }
   double* hr = h->hred + NBAL + MAXG * NWALL + NDIAGPART;
-  HIPCHK(launch_reduce((const double*)h->adjpart.p, (const uint32_t*)h->blkgrp.p, h->ntiles, 0, h->G, NBAL + MAXG * NWALL,
+  HIPCHK(launch_reduce((const double*)h->adjpart.p, (const uint32_t*)h->wlist.p, h->ntiles, 0, h->G, NBAL + MAXG * NWALL,
                        (double*)h->adjred.p, h->stream));
   HIPCHK(hipMemcpyAsync(hr, h->adjred.p, (NBAL + MAXG * NWALL) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
