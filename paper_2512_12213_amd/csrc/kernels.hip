@@ -476,9 +476,6 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
   }
 }
 
-// RU: 0 generic addressing; 1 row-uniform pointers; 2 row-uniform pointers
-// for rows with boundary links and buffer resources for the other rows
-// (arrays below 4 GiB).
 // Tile of a workgroup on odd steps.  Workgroups are dealt to the eight XCDs
 // in turn (workgroup b to XCD b mod 8), each with its own L2.  When a row
 // spans k > 1 tiles, the odd step's x-shifted loads and stores at the tiles'
@@ -499,6 +496,9 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles, uint32
   return c * chunk + (j % NXCD) * k + j / NXCD;
 }
 
+// RU: 0 generic addressing; 1 row-uniform pointers; 2 row-uniform pointers
+// for rows with boundary links and buffer resources for the other rows
+// (arrays below 4 GiB).
 template <class L, int P, int MHD, int PAR, bool DIAG, int RU, bool MAC = false>
 __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   using T = typename Stor<P>::T;
