@@ -355,7 +355,9 @@ __device__ __forceinline__ uint32_t nibble(const uint4& r, int q) {
 //   even parity (natural layout): slot q of x;
 //   odd parity: slot opp(q) of x - e_q, or, when the link from x along
 //   -e_q ends in a wall, slot q of x (where the bounce-back value was put).
-template <class L, int P, int PAR, bool BND, class AD>
+// (SCALE = false: 16-bit values are returned as stored, without the
+// per-direction factor of their format.)
+template <class L, int P, int PAR, bool BND, class AD, bool SCALE = true>
 __device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask,
                                        const Phys& p, typename Stor<P>::T (&d)[L::Q]) {
   using S = Stor<P>;
@@ -372,7 +374,7 @@ __device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f
     } else {
       v = A.template ld<L, P>(f, qb, qb);
     }
-    if (P == S_F16 || P == S_BF16) v *= (T)p.inv_scale[q];
+    if (SCALE && (P == S_F16 || P == S_BF16)) v *= (T)p.inv_scale[q];
     d[q] = v;
   }
 }
@@ -382,14 +384,15 @@ __device__ __forceinline__ void read_f(const typename Stor<P>::E* __restrict__ f
 //   even parity: slot opp(q) of x;
 //   odd parity: slot q of x + e_q, or slot opp(q) of x for a wall link.
 // One direction at a time.
-template <class L, int P, int PAR, bool BND, class AD>
+// (SCALE = false: v is already in the stored units of a 16-bit format.)
+template <class L, int P, int PAR, bool BND, class AD, bool SCALE = true>
 __device__ __forceinline__ void write_f1(typename Stor<P>::E* __restrict__ f, const AD& A, uint32_t mask, const Phys& p,
                                          int q, typename Stor<P>::T v) {
   using S = Stor<P>;
   using T = typename S::T;
   const int qb = opp(q);
   T s = v;
-  if (P == S_F16 || P == S_BF16) s *= (T)p.scale[q];
+  if (SCALE && (P == S_F16 || P == S_BF16)) s *= (T)p.scale[q];
   if constexpr (PAR == 0) {
     A.template st<L, P>(f, qb, -1, s);
   } else if constexpr (BND) {

@@ -44,7 +44,11 @@ struct Macro {
 // (the rest equilibrium in the uniform field); db = b - b0 is the induced
 // field and lam (coupling 2) the antisymmetric first moment of the induction
 // distributions, lam_i = eps_ilm sum_k e_kl h_km.
-template <class L, class T, int MHD, bool NEED_PI>
+//
+// RAW (16-bit formats, interior nodes): d holds the values in their stored
+// units (d_q / isc_q); a direction and its opposite share the factor isc_q,
+// so each pair's sum and difference are scaled once.
+template <class L, class T, int MHD, bool NEED_PI, bool RAW = false>
 __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T Ay, T Az, const T (&db)[3],
                                       const T (&lam)[3], Macro<T>& m) {
   // Moments from sums and differences of opposite populations (q odd, q + 1):
@@ -57,8 +61,12 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
   for (int k = 0; k < (L::Q - 1) / 2; ++k) {
     ps[k] = d[2 * k + 1] + d[2 * k + 2];
     pt[k] = d[2 * k + 1] - d[2 * k + 2];
+    if (RAW) {
+      ps[k] *= (T)p.inv_scale[2 * k + 1];
+      pt[k] *= (T)p.inv_scale[2 * k + 1];
+    }
   }
-  T drho = d[0], jx = ZERO<T>, jy = ZERO<T>, jz = ZERO<T>;
+  T drho = RAW ? d[0] * (T)p.inv_scale[0] : d[0], jx = ZERO<T>, jy = ZERO<T>, jz = ZERO<T>;
 #pragma unroll
   for (int k = 0; k < (L::Q - 1) / 2; ++k) {
     const int q = 2 * k + 1;
@@ -186,7 +194,12 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
 // part's moments are not scaled by the weights' own rounding.
 // sink(q, value) receives each post-collision value as soon as it is formed,
 // so that it can be stored at once and its register freed.
-template <class L, class T, int MHD, class Sink>
+//
+// RAW (16-bit formats, interior nodes): d and the values handed to sink are
+// in the stored units (d_q / isc_q, isc_q = the format's factor); the
+// increment is scaled once onto the stored value, and the weights are not
+// split (the format's own rounding is far coarser than theirs).
+template <class L, class T, int MHD, class Sink, bool RAW = false>
 __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, const T (&db)[3], const Phys& p,
                                         Sink&& sink) {
   const T rho = m.rho;
@@ -217,11 +230,12 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
     const T w = (T)L::w(0);
     const T wlo = (T)(L::w(0) - (double)w);
     const T Rb = m.drho - rq * usq;
-    const T neq = (w * Rb + wlo * Rb) - d[0];
+    const T neq = RAW ? w * Rb - d[0] * (T)p.inv_scale[0] : (w * Rb + wlo * Rb) - d[0];
     T Rs = rlq * (T(-3) * ua) + rl2q * (T(-1.5) * aa);
     if (MHD == 1) Rs += T(-4.5) * last;
     const T F = cr * w * (T(-3) * ufa);
-    sink(0, d[0] + ((neq + w * Rs) * itau + F));
+    const T X = (neq + w * Rs) * itau + F;
+    sink(0, RAW ? d[0] + X * (T)p.scale[0] : d[0] + X);
   }
   // direction q and its opposite q + 1 (q odd, e_{q+1} = -e_q): the parts even
   // in e are formed once, the odd ones change sign
@@ -252,15 +266,28 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
     const T cw = cr * w;
     const T EF = cw * (T(9) * euf * ea - T(3) * ufa);
     const T OF = cw * (T(3) * ea);
-    {
-      const T Rb = Eb + Ob;
-      const T neq = (w * Rb + wlo * Rb) - d[q];
-      sink(q, d[q] + ((neq + w * (Es + Os)) * itau + (EF + OF)));
-    }
-    {
-      const T Rb = Eb - Ob;
-      const T neq = (w * Rb + wlo * Rb) - d[q + 1];
-      sink(q + 1, d[q + 1] + ((neq + w * (Es - Os)) * itau + (EF - OF)));
+    if (RAW) {
+      // opposite directions share the format's factor
+      const T isc = (T)p.inv_scale[q], sc = (T)p.scale[q];
+      {
+        const T neq = w * (Eb + Ob) - d[q] * isc;
+        sink(q, d[q] + ((neq + w * (Es + Os)) * itau + (EF + OF)) * sc);
+      }
+      {
+        const T neq = w * (Eb - Ob) - d[q + 1] * isc;
+        sink(q + 1, d[q + 1] + ((neq + w * (Es - Os)) * itau + (EF - OF)) * sc);
+      }
+    } else {
+      {
+        const T Rb = Eb + Ob;
+        const T neq = (w * Rb + wlo * Rb) - d[q];
+        sink(q, d[q] + ((neq + w * (Es + Os)) * itau + (EF + OF)));
+      }
+      {
+        const T Rb = Eb - Ob;
+        const T neq = (w * Rb + wlo * Rb) - d[q + 1];
+        sink(q + 1, d[q + 1] + ((neq + w * (Es - Os)) * itau + (EF - OF)));
+      }
     }
   }
 }
@@ -345,6 +372,8 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
                                             uint32_t x = 0, const typename Stor<P>::T* uwl = nullptr) {
   using S = Stor<P>;
   using T = typename S::T;
+  // 16-bit formats at interior nodes work in the stored units
+  constexpr bool RAW = (P == S_F16 || P == S_BF16) && !BND && MHD == 0 && !XS;
   const Geom& g = a.geo;
   const uint32_t mask = rec.x;
   T d[L::Q];
@@ -378,7 +407,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
       if (P == S_F16 || P == S_BF16) d[q] *= (T)a.p.inv_scale[q];
     }
   } else {
-    read_f<L, P, PAR, BND>((const typename S::E*)a.f, Af, mask, a.p, d);
+    read_f<L, P, PAR, BND, AD, !RAW>((const typename S::E*)a.f, Af, mask, a.p, d);
   }
   T Ax, Ay, Az;
   if (a.afield) {
@@ -398,7 +427,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
     ind_moments<L, T>(h, db, lam);  // B - B0 = sum_k (g_k - W_k B0)
   }
   Macro<T> m;
-  macro<L, T, MHD, false>(d, a.p, Ax, Ay, Az, db, lam, m);
+  macro<L, T, MHD, false, RAW>(d, a.p, Ax, Ay, Az, db, lam, m);
   if (MAC) {
     // density and velocity of the pre-step state, for the adjoint
     T* mo = (T*)a.mac;
@@ -417,7 +446,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
     bal[6] += m.rho * m.A[2];
   }
   typename S::E* fo = (typename S::E*)a.f;
-  collide<L, T, MHD>(d, m, db, a.p, [&](int q, T v) __attribute__((always_inline)) {
+  auto sink = [&](int q, T v) __attribute__((always_inline)) {
     if (BND && q > 0 && ((mask >> q) & 1u)) {
       // halfway bounce-back link: the returning population is d_rel plus the
       // moving-wall term 6 w rho (e_opp . u_w) / c^2; the Eq. (25) momentum
@@ -452,9 +481,10 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
         xs_out[xshift_index<L>(q)][rb + xd] = s;
       }
     } else {
-      write_f1<L, P, PAR, BND>(fo, Af, mask, a.p, q, v);
+      write_f1<L, P, PAR, BND, AD, !RAW>(fo, Af, mask, a.p, q, v);
     }
-  });
+  };
+  collide<L, T, MHD, decltype(sink)&, RAW>(d, m, db, a.p, sink);
   if constexpr (XS) {
     __syncthreads();
 #pragma unroll
