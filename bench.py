@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and workloads")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--only", choices=["adjoint", "hartmann", "halfstep", "sphere"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "hartmann", "halfstep", "sphere", "formats"], default=None,
                     help="run only this measurement (for profiling its kernels) and print its record")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a plain copy kernel of known size, "
@@ -342,6 +342,13 @@ def main():
         return
     if args.only == "halfstep":
         print(json.dumps({"halfstep_duct_les_f32_256x128x128": halfstep_run(lbm, torch, W)}), flush=True)
+        return
+    if args.only == "formats":
+        # the duct in the other storage formats (FP16, BF16, FP64)
+        rs = {}
+        for name, st in (("duct_f16", W.F16), ("duct_bf16", W.BF16), ("duct_f64", W.F64)):
+            rs[name] = timed_run(lbm, torch, W.duct_les(), args.steps, args.warmup, storage=st)
+        print(json.dumps(rs), flush=True)
         return
     if args.only == "sphere":
         # the duct with a sphere, halfway and interpolated walls
