@@ -144,3 +144,68 @@ def brinkman_channel(n, nu, sigma, a):
     y = node_positions(n, 1.0)
     L = np.sqrt(nu / sigma)
     return a / sigma * (1.0 - np.cosh(y / L) / np.cosh(0.5 * n / L))
+
+
+def channel_stress_recurrence(ny, tau0, a, steps, model=4, stokes=False, cs=0.0):
+    """Non-equilibrium second moments of the force-driven D2Q9 channel of
+    `channel_recurrence` (lattice units, rho = 1, static halfway walls),
+    with either equilibrium (Eq. 1, or the Stokes form of the text after
+    Eq. 11) and, for cs > 0, a Smagorinsky relaxation time per node.
+
+    Classes by e_y = s in {+1, 0, -1}: x momentum m_s = sum_{e_y = s} e_x f
+    (as in `channel_recurrence`) and xx energy n_s = sum_{e_y = s} e_x^2 f.
+    For u = (u, 0) and a = (a, 0) the collision acts on them as
+      m*_s = (1 - 1/tau) m_s + k_s (u^eq / tau + C a)        k = 1/6, 2/3, 1/6
+      n*_s = (1 - 1/tau) n_s + c_s (1 + 3 q u^eq^2) / tau + k'_s C u^F a
+                                                             c = 1/18, 2/9, 1/18
+                                                             k' = 1/3, 4/3, 1/3
+    (q = 1 for Eq. 1, 0 for the Stokes form; the force classes follow from
+    Eq. 3 summed over e_x = +-1; He's force term [a] has no xx part), then
+    the s = +-1 classes stream along y and a static wall returns them with
+    e_x kept (m changes sign, n does not).  n is carried less its rest value
+    c_s (the c_s / tau parts cancel), which keeps the small non-equilibrium
+    part free of the rounding of 1/3.  Pi^neq_xx = sum_s n_s - 1/3 -
+    q u^eq^2, Pi^neq_xy = m_+1 - m_-1 (Pi^neq_yy = 0: the e_y classes of the
+    density stay at equilibrium).  The Smagorinsky tau is the positive root of
+    tau^2 - tau0 tau - 9 sqrt(2) cs^2 |Pi| / 2 = 0, |Pi|^2 = Pi_xx^2 +
+    2 Pi_xy^2, from the pre-step state.
+
+    Returns, for the state after `steps` steps, per row: Pi_xx, Pi_xy, tau,
+    u, v, u^eq, u^F, C (the last four as the force model defines them)."""
+    q = 0.0 if stokes else 1.0
+    kmo = np.array([1 / 6, 2 / 3, 1 / 6])
+    cen = np.array([1 / 18, 2 / 9, 1 / 18])
+    ken = np.array([1 / 3, 4 / 3, 1 / 3])
+    m = np.zeros((3, ny))                  # classes s = +1, 0, -1
+    n = np.zeros((3, ny))                  # xx classes less their rest values c_s
+    out = None
+    for it in range(steps + 1):
+        u = m.sum(0)                       # rho = 1: u = sum e_x f
+        pxy = m[0] - m[2]
+        # Pi_xx needs u^eq, which needs tau ([c] does not enter u^eq)
+        ueq = u + 0.5 * a if model == 4 else u
+        pxx = n.sum(0) - q * ueq ** 2       # sum_s c_s = 1/3
+        if cs > 0:
+            Qn = np.sqrt(pxx ** 2 + 2 * pxy ** 2)
+            tau = 0.5 * (tau0 + np.sqrt(tau0 ** 2 + 18 * np.sqrt(2) * cs ** 2 * Qn))
+        else:
+            tau = np.full(ny, tau0)
+        C = 1 - 1 / (2 * tau) if model == 4 else np.ones(ny)
+        v = u + 0.5 * a
+        uF = {0: 0 * u, 1: u, 2: u + 0.5 * tau * a, 3: v, 4: v}[model]
+        if it == steps:
+            out = dict(pxx=pxx, pxy=pxy, tau=tau, u=u, v=v, ueq=ueq, uF=uF, C=C)
+            break
+        ms = (1 - 1 / tau) * m + kmo[:, None] * (ueq / tau + C * a)
+        ns = (1 - 1 / tau) * n + cen[:, None] * 3 * q * ueq ** 2 / tau
+        if model != 0:
+            ns = ns + ken[:, None] * C * uF * a
+        m2 = np.empty_like(m)
+        n2 = np.empty_like(n)
+        m2[1], n2[1] = ms[1], ns[1]
+        m2[0, 1:], n2[0, 1:] = ms[0, :-1], ns[0, :-1]
+        m2[2, :-1], n2[2, :-1] = ms[2, 1:], ns[2, 1:]
+        m2[0, 0], n2[0, 0] = -ms[2, 0], ns[2, 0]
+        m2[2, -1], n2[2, -1] = -ms[0, -1], ns[0, -1]
+        m, n = m2, n2
+    return out
