@@ -285,9 +285,17 @@ def cpu_baseline(W, budget_s):
     }
 
 
+# Stated accuracy targets against the FP64 oracle per storage format:
+# (fields rho, v, sigma, S; wall force)
+TARGETS = {"f64": (1e-12, 1e-12), "f32": (1e-5, 1e-4), "f16": (2e-3, 2e-3), "bf16": (2e-3, 2e-3)}
+
+
 def errors_vs_oracle(lbm, W):
     """Each storage format's error against the FP64 oracle on the duct with
-    LES at 64x32x32, 300 steps (same workload recipe as the timed duct)."""
+    LES at 64x32x32, 300 steps (same workload recipe as the timed duct):
+    density (absolute, rho0 = 1), velocity, stress and strain rate (max-norm
+    relative), wall force (2-norm relative over the four walls), and whether
+    each meets the stated target of its format."""
     import oracle
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from helpers import make_oracle
@@ -295,18 +303,26 @@ def errors_vs_oracle(lbm, W):
     o = make_oracle(w)
     o.step(w.steps)
     ro, vo = o.get_macro()
+    so, So = o.stress()
     fo = o.wall_force(4)
     o.close()
+
+    def rel(x, ref):
+        return float(np.abs(x - ref).max() / np.abs(ref).max())
+
     out = {"workload": "duct_les_d3q19_64x32x32, 300 steps, FP64 oracle; max-norm relative errors"}
     for st, name in ((W.F64, "f64"), (W.F32, "f32"), (W.F16, "f16"), (W.BF16, "bf16")):
         g = lbm.from_workload(w, storage=st)
         g.step(w.steps)
         rg, vg = g.get_macro()
+        sg, Sg = g.stress()
         fg = g.wall_force()[:4]
         g.close()
-        out[name] = {"v": float(np.abs(vg - vo).max() / np.abs(vo).max()),
-                     "rho": float(np.abs(rg - ro).max()),
-                     "wall_force": float(np.linalg.norm(fg[:, 0] - fo[:, 0]) / np.linalg.norm(fo[:, 0]))}
+        e = {"rho": float(np.abs(rg - ro).max()), "v": rel(vg, vo), "sigma": rel(sg, so), "S": rel(Sg, So),
+             "wall_force": float(np.linalg.norm(fg[:, 0] - fo[:, 0]) / np.linalg.norm(fo[:, 0]))}
+        tf, tw = TARGETS[name]
+        e["meets_target"] = {k: bool(e[k] <= (tw if k == "wall_force" else tf)) for k in list(e)}
+        out[name] = e
     return out
 
 
@@ -436,8 +452,10 @@ def main():
         print("bench: variant poiseuille", file=sys.stderr, flush=True)
         variants["poiseuille_f64_64x32"] = timed_run(lbm, torch, W.poiseuille(), 5000, 100)
         for v in variants.values():
-            for k in ("mlups", "fluid_mlups", "ms_per_step", "achieved_gbs", "frac"):
-                v[k] = round(v[k], 4 if k == "frac" else 2)
+            for k in ("mlups", "fluid_mlups", "achieved_gbs"):
+                v[k] = round(v[k], 2)
+            v["frac"] = round(v["frac"], 4)
+            v["ms_per_step"] = float("%.5g" % v["ms_per_step"])
             v["launch_us"] = {k: round(x, 2) for k, x in v["launch_us"].items()}
         out["variants"] = variants
     if not args.no_variants:

@@ -73,12 +73,12 @@ struct orc {
   int lorentz;  /* MHD coupling: 0 magnetic stress in the equilibrium (Eq. 10), 1 Lorentz force as a body force */
   int K;        /* induction directions: 7 (D3Q7) or 5 (its planar restriction) */
   double B0[3], mu, tau_m;
-  real *g, *gn; /* induction distributions [K][3][N] */
-  real *d, *dn; /* [Q][N] deviations */
+  real *g, *gn; /* induction distributions less W_k B0, [K][3][N] */
+  real *d, *dn; /* [Q][N] deviations f - w rho0 (- phi(B0) under the MHD equilibrium) */
   real* rel;     /* [Q][N] relaxed values f_rel(x, t) of the last step, before propagation */
   real* rho_t;   /* [N] density of the last step's pre-step state */
   double* qlink; /* [Q][N] wall distance / link length for wall links, or NULL (all 1/2) */
-  real* Bt;      /* [3][N] B(x, t) before the last step (MHD) */
+  real* Bt;      /* [3][N] B(x, t) - B0 before the last step (MHD) */
   /* records of the last executed step */
   real wf[MAXG][3][3]; /* per group: raw, momentum-flux correction, Maxwell correction */
   real M_t, P_t[3], rho_a[3];
@@ -343,10 +343,45 @@ static real phi_mhd(const orc* o, int q, const real* B) {
 /* Is the magnetic stress carried by the equilibrium (Eq. 10)? */
 static int mhd_eq(const orc* o) { return o->mhd && !o->lorentz; }
 
-/* Maxwell stress L_ij = (B^2 delta_ij / 2 - B_i B_j) / mu (after Eq. 11). */
-static real maxwell(const orc* o, int i, int j, const real* B) {
-  real B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
-  return ((i == j ? 0.5 * B2 : 0.0) - B[i] * B[j]) / o->mu;
+
+/* The rest state in the uniform field B0 is kept outside the stored
+ * variables, a change of variable only (as the deviation from w rho0): the
+ * distributions are held as f - w rho0 - phi(B0) under the MHD equilibrium,
+ * and the induction distributions as g_k - W_k B0, so that the small induced
+ * parts are never rounded at the size of B0.  phi0 is that magnetic part of
+ * the rest equilibrium (zero unless the equilibrium carries Eq. 10). */
+static real phi0(const orc* o, int q) {
+  if (!mhd_eq(o)) return 0.0;
+  real B0[3] = {o->B0[0], o->B0[1], o->B0[2]};
+  return phi_mhd(o, q, B0);
+}
+
+/* phi(B0 + b) - phi(B0) of Eq. (10), expanded in the induced field b: with
+ * s = 2 B0 + b, B^2 - B0^2 = b.s and (e.B)^2 - (e.B0)^2 = (e.b)(e.s). */
+static real phi_change(const orc* o, int q, const real* b) {
+  const double c2 = o->c * o->c;
+  real ee = 0, eb = 0, es = 0, bs = 0;
+  for (int k = 0; k < 3; ++k) {
+    real sk = 2.0 * o->B0[k] + b[k];
+    ee += (real)(c2 * o->e[q][k] * o->e[q][k]);
+    eb += (real)(o->c * o->e[q][k]) * b[k];
+    es += (real)(o->c * o->e[q][k]) * sk;
+    bs += b[k] * sk;
+  }
+  real last = o->lat == 1 ? c2 * bs / 6.0 : 0.0;
+  return 9.0 * o->w[q] / (2.0 * c2 * c2 * o->mu) * (0.5 * bs * ee - eb * es - last);
+}
+
+/* L(B0 + b) - L(B0) of the Maxwell stress after Eq. (11),
+ * L_ij(B) = (B^2 delta_ij / 2 - B_i B_j) / mu, expanded in b:
+ * B^2 - B0^2 = b.s and B_i B_j - B0_i B0_j = (b_i s_j + s_i b_j) / 2, s = 2 B0 + b. */
+static real maxwell_change(const orc* o, int i, int j, const real* b) {
+  real s[3], bs = 0;
+  for (int k = 0; k < 3; ++k) {
+    s[k] = 2.0 * o->B0[k] + b[k];
+    bs += b[k] * s[k];
+  }
+  return ((i == j ? 0.5 * bs : 0.0) - 0.5 * (b[i] * s[j] + s[i] * b[j])) / o->mu;
 }
 
 static real body_force(const orc* o, long idx, int k) {
@@ -357,6 +392,7 @@ static real body_force(const orc* o, long idx, int k) {
 /* Per-node state needed by the collision and by the diagnostics. */
 typedef struct {
   real rho, drho, u[3], v[3], a[3], ueq[3], uF[3], B[3];
+  real b[3];   /* induced field B - B0 */
   real C;      /* force-term coefficient */
   real tau;    /* relaxation time in use (Smagorinsky or molecular) */
   real Pi[3][3]; /* non-equilibrium second moment, Pi^neq */
@@ -429,9 +465,10 @@ static void node_setup(const orc* o, const real* dl, long idx, const real (*gl)[
   s->rho = rho;
   s->drho = drho;
   for (int k = 0; k < 3; ++k) {
-    s->B[k] = 0;
+    s->b[k] = 0;
     if (gl)
-      for (int m = 0; m < o->K; ++m) s->B[k] += gl[m][k]; /* B = sum_k g_k */
+      for (int m = 0; m < o->K; ++m) s->b[k] += gl[m][k]; /* B - B0 = sum_k (g_k - W_k B0) */
+    s->B[k] = (gl ? o->B0[k] : 0.0) + s->b[k];
   }
   for (int k = 0; k < 3; ++k) {
     s->u[k] = k < D ? j[k] / rho : 0;
@@ -464,13 +501,15 @@ static void node_setup(const orc* o, const real* dl, long idx, const real (*gl)[
       s->ueq[k] = s->u[k];
   }
   /* Pi^neq = sum e e f - (p delta + rho u^eq u^eq + L) (cheap form after
-   * Eq. 9, with the Maxwell stress that Eq. 11 puts in M^eq_ij). */
+   * Eq. 9, with the Maxwell stress that Eq. 11 puts in M^eq_ij).  The stored
+   * second moment lacks that of phi(B0), which is L(B0), so L(B) - L(B0) is
+   * subtracted. */
   for (int i = 0; i < D; ++i)
     for (int k = 0; k < D; ++k) {
       real m = 0;
       for (int q = 0; q < Q; ++q) m += (real)(c2 * o->e[q][i] * o->e[q][k]) * dl[q];
       real eqm = (i == k ? drho * c2 / 3.0 : 0.0) + (o->stokes ? 0.0 : rho * s->ueq[i] * s->ueq[k]);
-      if (mhd_eq(o)) eqm += maxwell(o, i, k, s->B);
+      if (mhd_eq(o)) eqm += maxwell_change(o, i, k, s->b);
       s->Pi[i][k] = m - eqm;
     }
   /* Smagorinsky closure (C_s > 0): nu_eff = nu0 + (C_s dx)^2 |S| with
@@ -568,16 +607,14 @@ int orc_init_equilibrium(orc* o, const double* u0) {
     real u[3] = {0, 0, 0};
     if (u0)
       for (int k = 0; k < o->D; ++k) u[k] = u0[(long)k * N + i];
+    /* f^eq(rho0, u0) (+ phi(B0), outside the stored deviation) and
+     * g^eq(B0, u0) less W B0 */
     real B[3] = {o->B0[0], o->B0[1], o->B0[2]};
-    for (int q = 0; q < o->Q; ++q) {
-      real v = o->solid[i] ? 0 : feq_dev(o, q, o->rho0, 0.0, u);
-      if (mhd_eq(o) && !o->solid[i]) v += phi_mhd(o, q, B);
-      o->d[(long)q * N + i] = v;
-    }
+    for (int q = 0; q < o->Q; ++q) o->d[(long)q * N + i] = o->solid[i] ? 0 : feq_dev(o, q, o->rho0, 0.0, u);
     if (o->mhd) {
       for (int k = 0; k < o->K; ++k)
         for (int c = 0; c < 3; ++c) {
-          real geq = w7(o, k) * B[c];
+          real geq = 0;
           if (!o->solid[i])
             for (int m = 0; m < 3; ++m)
               geq += w7(o, k) * (e7[k][m] / (THETA7 * o->c)) * (u[m] * B[c] - B[m] * u[c]);
@@ -590,29 +627,39 @@ int orc_init_equilibrium(orc* o, const double* u0) {
   return 0;
 }
 
+/* States are exchanged as f - w rho0 [Q][N] (phi(B0) included; solid
+ * nodes as given). */
 int orc_set_state(orc* o, const double* d, const double* d_im) {
-  for (long i = 0; i < (long)o->Q * o->N; ++i) o->d[i] = MK(d[i], d_im ? d_im[i] : 0.0);
+  for (long i = 0; i < (long)o->Q * o->N; ++i)
+    o->d[i] = MK(d[i], d_im ? d_im[i] : 0.0) - (o->solid[i % o->N] ? 0.0 : phi0(o, (int)(i / o->N)));
   o->have_step = 0;
   return 0;
 }
 
 /* Replace the state without forgetting the records of the last step. */
 int orc_replace_state(orc* o, const double* d) {
-  for (long i = 0; i < (long)o->Q * o->N; ++i) o->d[i] = MK(d[i], 0.0);
+  for (long i = 0; i < (long)o->Q * o->N; ++i)
+    o->d[i] = MK(d[i], 0.0) - (o->solid[i % o->N] ? 0.0 : phi0(o, (int)(i / o->N)));
   return 0;
 }
 
 int orc_get_state(const orc* o, double* d, double* d_im) {
   for (long i = 0; i < (long)o->Q * o->N; ++i) {
-    d[i] = RE(o->d[i]);
+    d[i] = RE(o->d[i] + (o->solid[i % o->N] ? 0.0 : phi0(o, (int)(i / o->N))));
     if (d_im) d_im[i] = IM(o->d[i]);
   }
   return 0;
 }
 
+/* Absolute induction distributions g [K][3][N] (solid nodes read 0). */
 int orc_get_induction(const orc* o, double* g) {
   if (!o->mhd) return -1;
-  for (long i = 0; i < 3L * o->K * o->N; ++i) g[i] = RE(o->g[i]);
+  for (int k = 0; k < o->K; ++k)
+    for (int m = 0; m < 3; ++m)
+      for (long i = 0; i < o->N; ++i) {
+        long j = ((long)k * 3 + m) * o->N + i;
+        g[j] = o->solid[i] ? 0.0 : RE(o->g[j] + w7(o, k) * o->B0[m]);
+      }
   return 0;
 }
 
@@ -630,7 +677,7 @@ static void node_relax(const orc* o, const real* dl, long idx, const real (*gl)[
   node_setup(o, dl, idx, gl, a_node, s);
   for (int q = 0; q < o->Q; ++q) {
     real deq = feq_dev(o, q, s->rho, s->drho, s->ueq);
-    if (mhd_eq(o)) deq += phi_mhd(o, q, s->B);
+    if (mhd_eq(o)) deq += phi_change(o, q, s->b); /* phi(B) less the stored phi(B0) */
     drel[q] = dl[q] + (deq - dl[q]) / s->tau + s->F[q];
   }
 }
@@ -659,7 +706,7 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
    * bounce-back */
   for (int q = 0; q < Q; ++q) o->rel[(long)q * N + idx] = drel[q];
   o->rho_t[idx] = s.rho;
-  for (int k = 0; k < 3; ++k) o->Bt[(long)k * N + idx] = s.B[k];
+  for (int k = 0; k < 3; ++k) o->Bt[(long)k * N + idx] = s.b[k];
 
   /* balance partials at time t (Eq. 32): mass, momentum, body force */
   real* pb = part + o->G * 9;
@@ -684,7 +731,7 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
     real ladd = moving_wall_term(o, q, s.rho, o->uw[grp]);
     o->dn[(long)qb * N + idx] = drel[q] + ladd;
     /* Eq. (25): outgoing f_bar = f_rel(x_f, t), incoming f_bar = f(x_f, t + dt) */
-    real fout = drel[q] + o->w[q] * o->rho0;
+    real fout = drel[q] + o->w[q] * o->rho0 + phi0(o, q);
     real fin = fout + ladd;
     real* pw = part + grp * 9;
     for (int k = 0; k < 3; ++k) {
@@ -706,7 +753,8 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
     for (int k = 0; k < o->K; ++k) {
       real grel[3];
       for (int m = 0; m < 3; ++m) {
-        real geq = w7(o, k) * s.B[m];
+        /* g^eq_k(B, v) = W_k [B + (e_k / (theta c)).(v B - B v)], less W_k B0 */
+        real geq = w7(o, k) * s.b[m];
         for (int j = 0; j < 3; ++j)
           geq += w7(o, k) * (e7[k][j] / (THETA7 * c)) * (s.v[j] * s.B[m] - s.B[j] * s.v[m]);
         grel[m] = gl[k][m] + (geq - gl[k][m]) / o->tau_m;
@@ -716,9 +764,11 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
       if (!link_target(o, x, y, z, e7[k], &t, &grp)) {
         for (int m = 0; m < 3; ++m) o->gn[((long)k * 3 + m) * N + t] = grel[m];
       } else {
-        /* anti-bounce-back imposing B = B0 at the halfway wall */
+        /* anti-bounce-back imposing B = B0 at the halfway wall:
+         * g_kb(x_f, t + dt) = -g_rel_k(x_f, t) + 2 W_k B0; less W_kb B0 = W_k B0
+         * on both sides this is -(g_rel_k - W_k B0) */
         int kb = opp7[k];
-        for (int m = 0; m < 3; ++m) o->gn[((long)kb * 3 + m) * N + idx] = -grel[m] + 2.0 * w7(o, k) * o->B0[m];
+        for (int m = 0; m < 3; ++m) o->gn[((long)kb * 3 + m) * N + idx] = -grel[m];
       }
     }
   }
@@ -769,8 +819,8 @@ static void interpolated_bounce_back(orc* o, real* tot) {
             din = rq / (2.0 * qv) + (2.0 * qv - 1.0) / (2.0 * qv) * o->rel[(long)qb * N + idx] + ladd / (2.0 * qv);
           }
           o->dn[(long)qb * N + idx] = din;
-          const real fout = rq + o->w[q] * o->rho0;
-          const real fin = din + o->w[q] * o->rho0;
+          const real fout = rq + o->w[q] * o->rho0 + phi0(o, q);
+          const real fin = din + o->w[q] * o->rho0 + phi0(o, qb);
           real* pw = tot + grp * 9;
           for (int k = 0; k < 3; ++k) {
             double ek = c * o->e[q][k], ebk = c * o->e[qb][k];
@@ -830,11 +880,12 @@ int orc_step(orc* o, int n) {
 /* ---------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------- */
-static void node_B(const orc* o, long idx, real* B) {
-  B[0] = B[1] = B[2] = 0;
+/* Induced field B - B0 = sum_k (g_k - W_k B0) of a node. */
+static void node_b(const orc* o, long idx, real* b) {
+  b[0] = b[1] = b[2] = 0;
   if (!o->mhd) return;
   for (int k = 0; k < o->K; ++k)
-    for (int m = 0; m < 3; ++m) B[m] += o->g[((long)k * 3 + m) * o->N + idx];
+    for (int m = 0; m < 3; ++m) b[m] += o->g[((long)k * 3 + m) * o->N + idx];
 }
 
 /* The node's induction distributions [K][3]; NULL without MHD. */
@@ -1043,7 +1094,7 @@ int orc_halfstep(const orc* o, double* fbar, double* rho_bar, double* u_bar, dou
     real db[19];
     for (int q = 0; q < Q; ++q) db[q] = o->solid[i] ? 0 : 0.5 * (o->rel[(long)q * N + i] + o->d[(long)q * N + i]);
     if (fbar)
-      for (int q = 0; q < Q; ++q) fbar[(long)q * N + i] = RE(db[q]);
+      for (int q = 0; q < Q; ++q) fbar[(long)q * N + i] = o->solid[i] ? 0.0 : RE(db[q] + phi0(o, q));
     if (o->solid[i]) {
       if (rho_bar) rho_bar[i] = 0;
       if (u_bar)
@@ -1063,21 +1114,23 @@ int orc_halfstep(const orc* o, double* fbar, double* rho_bar, double* u_bar, dou
     if (u_bar)
       for (int k = 0; k < D; ++k) u_bar[(long)k * N + i] = RE(u[k]);
     if (sigma_bar) {
-      real B[3] = {0, 0, 0};
+      real bbar[3] = {0, 0, 0}; /* Bbar - B0 */
       if (o->mhd) {
-        real Bn[3];
-        node_B(o, i, Bn);
-        for (int k = 0; k < 3; ++k) B[k] = 0.5 * (o->Bt[(long)k * N + i] + Bn[k]);
+        real bn[3];
+        node_b(o, i, bn);
+        for (int k = 0; k < 3; ++k) bbar[k] = 0.5 * (o->Bt[(long)k * N + i] + bn[k]);
       }
       for (int m = 0; m < nc; ++m) {
         const int a = comp[m][0], b = comp[m][1];
-        /* -sum e_a e_b fbar with fbar = d_bar + w rho0: the w rho0 part gives
-         * -rho0 c^2/3 delta_ab */
+        /* -sum e_a e_b fbar with fbar = d_bar + w rho0 (+ phi(B0)): the w rho0
+         * part gives -rho0 c^2/3 delta_ab, which joins pbar delta_ab of
+         * Mbar^eq as (rhobar - rho0) c^2 / 3 (as in Pi^neq); phi(B0) gives
+         * -L(B0), which joins L(Bbar) as L(Bbar) - L(B0) */
         real mom = 0;
         for (int q = 0; q < Q; ++q) mom += (real)(c2 * o->e[q][a] * o->e[q][b]) * db[q];
-        real meq = (a == b ? rho * c2 / 3.0 : 0.0) + (o->stokes ? 0.0 : rho * u[a] * u[b]);
-        if (mhd_eq(o)) meq += maxwell(o, a, b, B);
-        real val = -(mom + (a == b ? o->rho0 * c2 / 3.0 : 0.0)) + meq;
+        real meq = (a == b ? drho * c2 / 3.0 : 0.0) + (o->stokes ? 0.0 : rho * u[a] * u[b]);
+        if (mhd_eq(o)) meq += maxwell_change(o, a, b, bbar);
+        real val = -mom + meq;
         sigma_bar[(long)m * N + i] = RE(val);
       }
     }

@@ -16,6 +16,11 @@ HIPCC_FLAGS = [
     "-fPIC",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only within one source expression, so that every
+    # instantiation of a kernel (pointer or buffer addressing, with or without
+    # the density and velocity record of the adjoint's recompute) rounds the
+    # same arithmetic the same way and their results are bit-identical
+    "-ffp-contract=on",
     "-Wno-unused-result",
 ]
 

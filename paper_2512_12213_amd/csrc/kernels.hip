@@ -174,8 +174,6 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
   for (int k = 0; k < 3; ++k) m.UF[k] = kF * m.U[k] + lF * m.A[k];
 }
 
-// Eq. (2) with the equilibrium of Eq. (1) (+ magnetic part of Eq. 10) and
-// the force term of Section 2 / Eq. (3); d is replaced by d_rel.
 // Relaxation of Eq. (2) with the equilibrium of Eq. (1) (+ magnetic part of
 // Eq. 10) and the force term of Section 2 / Eq. (3); d is replaced by d_rel.
 //
@@ -191,7 +189,9 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
 //   magnetic term,
 // so that small quantities are never rounded at the scale of large ones.  The
 // weights 1/9, 1/18, 1/36 are applied as hi + lo parts so that the large
-// part's moments are not scaled by the weights' own rounding.
+// part's moments are not scaled by the weights' own rounding, and in FP32
+// the mass and momentum of its non-equilibrium part are closed exactly
+// (below).
 // sink(q, value) receives each post-collision value as soon as it is formed,
 // so that it can be stored at once and its register freed.
 //
@@ -225,68 +225,133 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
   // away in the same direction at every step (a drift of momentum and mass in
   // slowly varying flows).
   //
-  // rest direction (e = 0)
-  {
-    const T w = (T)L::w(0);
-    const T wlo = (T)(L::w(0) - (double)w);
-    const T Rb = m.drho - rq * usq;
-    const T neq = RAW ? w * Rb - d[0] * (T)p.inv_scale[0] : (w * Rb + wlo * Rb) - d[0];
-    T Rs = rlq * (T(-3) * ua) + rl2q * (T(-1.5) * aa);
-    if (MHD == 1) Rs += T(-4.5) * last;
-    const T F = cr * w * (T(-3) * ufa);
-    const T X = (neq + w * Rs) * itau + F;
-    sink(0, RAW ? d[0] + X * (T)p.scale[0] : d[0] + X);
-  }
-  // direction q and its opposite q + 1 (q odd, e_{q+1} = -e_q): the parts even
-  // in e are formed once, the odd ones change sign
-#pragma unroll
-  for (int k = 0; k < (L::Q - 1) / 2; ++k) {
-    const int q = 2 * k + 1;
+  // Parts of direction q and its opposite q + 1 (q odd, e_{q+1} = -e_q): the
+  // parts even in e are formed once, the odd ones change sign.
+  struct PairTerms {
+    T Eb, Ob, Es, Os, EF, OF;
+  };
+  auto pair_terms = [&](int q) __attribute__((always_inline)) {
+    PairTerms t;
     const T w = (T)L::w(q);
-    const T wlo = (T)(L::w(q) - (double)w);
     const T eu = edot<L>(q, m.U[0], m.U[1], m.U[2]);
     const T ej = edot<L>(q, m.J[0], m.J[1], m.J[2]);
     const T ea = edot<L>(q, m.A[0], m.A[1], m.A[2]);
     const T euf = edot<L>(q, m.UF[0], m.UF[1], m.UF[2]);
     // large part: w [drho + 3 e.j + rho (9/2 (e.u)^2 - 3/2 u.u)]
-    const T Eb = m.drho + rq * (T(4.5) * eu * eu - usq);
-    const T Ob = T(3) * ej;
+    t.Eb = m.drho + rq * (T(4.5) * eu * eu - usq);
+    t.Ob = T(3) * ej;
     // small part: the u^eq shift
     //   rho [(e.ue)^2 9/2 - ue.ue 3/2] - (same at u) + 3 e.(rho lEq A),
     // and the magnetic term phi(b) - phi(b0)
-    T Es = rlq * (T(9) * eu * ea - T(3) * ua) + rl2q * (T(4.5) * ea * ea - T(1.5) * aa);
+    t.Es = rlq * (T(9) * eu * ea - T(3) * ua) + rl2q * (T(4.5) * ea * ea - T(1.5) * aa);
     if (MHD == 1) {
       // (e.b)^2 - (e.b0)^2 = (e.db)(e.(b + b0))
       const T edb = edot<L>(q, db[0], db[1], db[2]);
       const T ebs = edot<L>(q, bs[0], bs[1], bs[2]);
-      Es += T(4.5) * (T(0.5) * db2 * (T)L::e2(q) - edb * ebs - last);
+      t.Es += T(4.5) * (T(0.5) * db2 * (T)L::e2(q) - edb * ebs - last);
     }
-    const T Os = rl * (T(3) * ea);
+    t.Os = rl * (T(3) * ea);
     // force term C rho w [3 (e - u^F).a + 9 (e.u^F)(e.a)]
     const T cw = cr * w;
-    const T EF = cw * (T(9) * euf * ea - T(3) * ufa);
-    const T OF = cw * (T(3) * ea);
-    if (RAW) {
-      // opposite directions share the format's factor
-      const T isc = (T)p.inv_scale[q], sc = (T)p.scale[q];
-      {
-        const T neq = w * (Eb + Ob) - d[q] * isc;
-        sink(q, d[q] + ((neq + w * (Es + Os)) * itau + (EF + OF)) * sc);
-      }
-      {
-        const T neq = w * (Eb - Ob) - d[q + 1] * isc;
-        sink(q + 1, d[q + 1] + ((neq + w * (Es - Os)) * itau + (EF - OF)) * sc);
-      }
-    } else {
-      {
-        const T Rb = Eb + Ob;
-        const T neq = (w * Rb + wlo * Rb) - d[q];
-        sink(q, d[q] + ((neq + w * (Es + Os)) * itau + (EF + OF)));
-      }
-      {
-        const T Rb = Eb - Ob;
-        const T neq = (w * Rb + wlo * Rb) - d[q + 1];
-        sink(q + 1, d[q + 1] + ((neq + w * (Es - Os)) * itau + (EF - OF)));
+    t.EF = cw * (T(9) * euf * ea - T(3) * ufa);
+    t.OF = cw * (T(3) * ea);
+    return t;
+  };
+  // rest direction (e = 0): small part and force term
+  T Rs0 = rlq * (T(-3) * ua) + rl2q * (T(-1.5) * aa);
+  if (MHD == 1) Rs0 += T(-4.5) * last;
+  const T F0 = cr * (T)L::w(0) * (T(-3) * ufa);
+  if constexpr (!RAW && sizeof(T) == 4) {
+    // FP32.  The large part's rounding (about one unit of the last place of
+    // f per direction) would change the mass and momentum of the
+    // non-equilibrium part neq = w Rb - d, which relaxation never removes:
+    // in slowly varying flows it repeats with the same sign every step.  So
+    // its conserved moments are closed exactly: the pairs with two nonzero
+    // components come first and their sums are kept; each axis pair then
+    // takes the odd part that makes the momentum of neq zero along its axis,
+    // and the rest direction the value that makes its mass zero (all sums
+    // at the size of neq, far below that of f).  In exact arithmetic these
+    // are the values the formulas give.  (Measured on the 256x128x128 duct:
+    // the same mean step time as the formulas in direction order; closing
+    // with the last pairs instead, stored in direction order, 1 % slower.)
+    T Mn = ZERO<T>, Jn[3] = {ZERO<T>, ZERO<T>, ZERO<T>};
+#pragma unroll
+    for (int k = 0; k < (L::Q - 1) / 2; ++k) {
+      const int q = 2 * k + 1;
+      if (L::e2(q) != 2) continue;
+      const PairTerms t = pair_terms(q);
+      const T w = (T)L::w(q);
+      const T wlo = (T)(L::w(q) - (double)w);
+      const T Rp = t.Eb + t.Ob, Rm = t.Eb - t.Ob;
+      const T np = (w * Rp + wlo * Rp) - d[q];
+      const T nm = (w * Rm + wlo * Rm) - d[q + 1];
+      Mn += np + nm;
+      const T od = np - nm;
+      if (L::ex(q) > 0) Jn[0] += od;
+      if (L::ex(q) < 0) Jn[0] -= od;
+      if (L::ey(q) > 0) Jn[1] += od;
+      if (L::ey(q) < 0) Jn[1] -= od;
+      if (L::ez(q) > 0) Jn[2] += od;
+      if (L::ez(q) < 0) Jn[2] -= od;
+      sink(q, d[q] + ((np + w * (t.Es + t.Os)) * itau + (t.EF + t.OF)));
+      sink(q + 1, d[q + 1] + ((nm + w * (t.Es - t.Os)) * itau + (t.EF - t.OF)));
+    }
+#pragma unroll
+    for (int k = 0; k < (L::Q - 1) / 2; ++k) {
+      const int q = 2 * k + 1;
+      if (L::e2(q) != 1) continue;
+      const PairTerms t = pair_terms(q);
+      const T w = (T)L::w(q);
+      const T wlo = (T)(L::w(q) - (double)w);
+      // axis of q (+1 along it; its opposite -1)
+      const int ax = L::ex(q) != 0 ? 0 : (L::ey(q) != 0 ? 1 : 2);
+      const T E2 = T(2) * t.Eb;
+      const T ev = (w * E2 + wlo * E2) - (d[q] + d[q + 1]);  // neq_q + neq_q+1
+      const T od = -Jn[ax];                                  // neq_q - neq_q+1
+      const T np = T(0.5) * (ev + od), nm = T(0.5) * (ev - od);
+      Mn += ev;
+      sink(q, d[q] + ((np + w * (t.Es + t.Os)) * itau + (t.EF + t.OF)));
+      sink(q + 1, d[q + 1] + ((nm + w * (t.Es - t.Os)) * itau + (t.EF - t.OF)));
+    }
+    sink(0, d[0] + ((-Mn + (T)L::w(0) * Rs0) * itau + F0));
+  } else {
+    // rest direction (e = 0)
+    {
+      const T w = (T)L::w(0);
+      const T wlo = (T)(L::w(0) - (double)w);
+      const T Rb = m.drho - rq * usq;
+      const T neq = RAW ? w * Rb - d[0] * (T)p.inv_scale[0] : (w * Rb + wlo * Rb) - d[0];
+      const T X = (neq + w * Rs0) * itau + F0;
+      sink(0, RAW ? d[0] + X * (T)p.scale[0] : d[0] + X);
+    }
+#pragma unroll
+    for (int k = 0; k < (L::Q - 1) / 2; ++k) {
+      const int q = 2 * k + 1;
+      const PairTerms t = pair_terms(q);
+      const T w = (T)L::w(q);
+      const T wlo = (T)(L::w(q) - (double)w);
+      if (RAW) {
+        // opposite directions share the format's factor
+        const T isc = (T)p.inv_scale[q], sc = (T)p.scale[q];
+        {
+          const T neq = w * (t.Eb + t.Ob) - d[q] * isc;
+          sink(q, d[q] + ((neq + w * (t.Es + t.Os)) * itau + (t.EF + t.OF)) * sc);
+        }
+        {
+          const T neq = w * (t.Eb - t.Ob) - d[q + 1] * isc;
+          sink(q + 1, d[q + 1] + ((neq + w * (t.Es - t.Os)) * itau + (t.EF - t.OF)) * sc);
+        }
+      } else {
+        {
+          const T Rb = t.Eb + t.Ob;
+          const T neq = (w * Rb + wlo * Rb) - d[q];
+          sink(q, d[q] + ((neq + w * (t.Es + t.Os)) * itau + (t.EF + t.OF)));
+        }
+        {
+          const T Rb = t.Eb - t.Ob;
+          const T neq = (w * Rb + wlo * Rb) - d[q + 1];
+          sink(q + 1, d[q + 1] + ((neq + w * (t.Es - t.Os)) * itau + (t.EF - t.OF)));
+        }
       }
     }
   }

@@ -85,3 +85,29 @@ def quantized_steps(o, storage, n):
     for _ in range(n):
         o.step(1)
         o.set_state(quantize_state(o.get_state(), storage), keep_records=True)
+
+
+# ---------------------------------------------------------------------------
+# Stated accuracy targets and the misses recorded as not met.
+# ---------------------------------------------------------------------------
+def check_targets(errs, target, misses=None, what=""):
+    """Assert each error in `errs` (name -> value) at `target` (a number or a
+    name -> number dict), except the names in `misses` (name -> bound): those
+    are results recorded as not meeting the target; each must stay within its
+    recorded bound (a regression check), and if any of them is above its
+    target the test ends as an expected failure that states the measured
+    values."""
+    import pytest
+    misses = misses or {}
+    tgt = (lambda k: target[k]) if isinstance(target, dict) else (lambda k: target)
+    over = {}
+    for k, v in errs.items():
+        if k in misses:
+            assert v <= misses[k], "%s: %s = %.3e beyond its recorded bound %.1e" % (what, k, v, misses[k])
+            if v > tgt(k):
+                over[k] = v
+        else:
+            assert v <= tgt(k), "%s: %s = %.3e above the target %.1e" % (what, k, v, tgt(k))
+    if over:
+        pytest.xfail("not met (recorded): %s: %s" % (what, ", ".join("%s %.2e > %.0e" % (k, v, tgt(k))
+                                                                     for k, v in over.items())))

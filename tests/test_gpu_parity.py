@@ -7,7 +7,10 @@ wall forces: 2-norm per group and variant): FP64 storage 1e-12; FP32 storage
 16-bit storage is compared with the oracle's FP64 arithmetic carrying the
 same documented storage rounding (d*2^10/w in FP16, d/w in BF16, applied
 wherever the library stores a state).  Its accuracy against the unquantized
-FP64 oracle is stated separately (test_16bit_accuracy_vs_fp64).
+FP64 oracle is stated separately (test_16bit_accuracy_vs_fp64).  Results
+that miss their target are recorded as not met (MISS_QUANT, MISS_VS_FP64):
+the test then ends as an expected failure stating the measured values, each
+held to a recorded bound.
 """
 import sys
 
@@ -15,19 +18,23 @@ import numpy as np
 import pytest
 
 from closed_forms import channel_recurrence
-from helpers import make_oracle, quantize_state, quantized_steps, rel_inf
+from helpers import check_targets, make_oracle, quantize_state, quantized_steps, rel_inf
 from paper_2512_12213_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-# BF16 keeps 8 significant bits: its rounding unit 2^-8 = 3.9e-3 is larger
-# than the 2e-3 target, so one rounding that lands on the other side already
-# exceeds it.  It is held to two of its own rounding units.
-# The stress is a small difference of stored values, so under BF16 its error
-# is the storage unit times |d| / |Pi^neq| (about 2-4 in these flows).
-TOL_FIELD = {W.F64: 1e-12, W.F32: 1e-5, W.F16: 2e-3, W.BF16: 8e-3}
-TOL_STRESS = {W.F64: 1e-12, W.F32: 1e-5, W.F16: 2e-3, W.BF16: 2e-2}
-TOL_WALL = {W.F64: 1e-12, W.F32: 1e-4, W.F16: 2e-3, W.BF16: 8e-3}
+TOL_FIELD = {W.F64: 1e-12, W.F32: 1e-5, W.F16: 2e-3, W.BF16: 2e-3}
+TOL_STRESS = {W.F64: 1e-12, W.F32: 1e-5, W.F16: 2e-3, W.BF16: 2e-3}
+TOL_WALL = {W.F64: 1e-12, W.F32: 1e-4, W.F16: 2e-3, W.BF16: 2e-3}
+
+# Recorded as not met: BF16 keeps 8 significant bits, so its rounding unit
+# 2^-8 = 3.9e-3 exceeds the 2e-3 target and a single rounding that lands on
+# the other side of a tie than in the quantized oracle already misses it; the
+# stress, a small difference of stored values, carries that unit times
+# |d| / |Pi^neq|.  Bounds (regression checks): two rounding units on fields
+# and wall forces, 2e-2 on the stress.
+MISS_QUANT = {W.F64: {}, W.F32: {}, W.F16: {},
+              W.BF16: {"rho": 8e-3, "v": 8e-3, "sigma": 2e-2, "S": 2e-2, "wall": 8e-3, "state": 8e-3}}
 
 
 def say(*a):
@@ -61,12 +68,10 @@ def compare_all(g, o, storage, groups, what=""):
     e_f = max(np.linalg.norm(fg[k, var] - fo[k, var]) / max(np.linalg.norm(fo[k, var]), 1e-300)
               for k in range(groups) for var in range(4) if np.linalg.norm(fo[k, var]) > 0)
     say("%s rho %.2e v %.2e sigma %.2e S %.2e wall %.2e" % (what, e_rho, e_v, e_s, e_S, e_f))
-    assert e_rho <= tf
-    assert e_v <= tf
-    assert e_s <= TOL_STRESS[storage]
-    assert e_S <= TOL_STRESS[storage]
-    assert e_f <= TOL_WALL[storage]
-    return dict(rho=e_rho, v=e_v, sigma=e_s, strain=e_S, wall=e_f)
+    errs = dict(rho=e_rho, v=e_v, sigma=e_s, S=e_S, wall=e_f)
+    check_targets(errs, dict(rho=tf, v=tf, sigma=TOL_STRESS[storage], S=TOL_STRESS[storage],
+                             wall=TOL_WALL[storage]), MISS_QUANT[storage], what)
+    return errs
 
 
 @pytest.mark.parametrize("model", [0, 1, 2, 3, 4])
@@ -127,13 +132,14 @@ def test_random_state_two_steps(lbm, lattice, model, storage):
             o.step(1)
         st = rel_inf(g.get_state(), o.get_state())
         say("  step", k + 1, "state err %.2e" % st)
-        assert st <= TOL_FIELD[storage]
+        check_targets(dict(state=st), TOL_FIELD[storage], MISS_QUANT[storage], "state")
         compare_all(g, o, storage, 5, "  step %d" % (k + 1))
     g.set_artefact(True)
     o.set_artefact(True)
     sg, Sg = g.stress()
     so, So = o.stress()
-    assert rel_inf(sg, so) <= TOL_STRESS[storage] and rel_inf(Sg, So) <= TOL_STRESS[storage]
+    check_targets(dict(sigma=rel_inf(sg, so), S=rel_inf(Sg, So)), TOL_STRESS[storage], MISS_QUANT[storage],
+                  "with the artefact term")
 
 
 @pytest.mark.parametrize("storage", [W.F32, W.F64])
@@ -219,14 +225,21 @@ def test_duct_les_small(lbm, storage):
     compare_all(g, o, storage, 4, "duct %d" % storage)
 
 
+# Recorded as not met against the unquantized FP64 oracle: the stress and
+# strain rate under FP16 (the format's 11 significant bits; the quantized
+# oracle, FP64 arithmetic with the same storage rounding, shows the same
+# floor, so it is the format and not the kernel), and every result under
+# BF16.  Bounds (regression checks) about 1.5 times the largest measured.
+MISS_VS_FP64 = {W.F16: {"sigma": 1e-2, "S": 1e-2},
+                W.BF16: {"rho": 8e-3, "v": 2e-2, "sigma": 1e-1, "S": 1e-1, "wall": 8e-3}}
+
+
 @pytest.mark.parametrize("storage", [W.F16, W.BF16])
 def test_16bit_accuracy_vs_fp64(lbm, storage):
     """Accuracy of 16-bit storage against the unquantized FP64 oracle
-    (duct, 300 steps).  FP16 meets 2e-3 on density, velocity and wall force;
-    the stress, a small difference of stored values, carries the storage
-    format's own rounding (about 5e-3 for FP16), which the quantized oracle
-    shows to be the format's floor, not the kernel's.  BF16 (8-bit
-    significand) is reported with its larger floor."""
+    (duct, 300 steps), at the 2e-3 target: FP16 meets it on density,
+    velocity and wall force; its stress and strain rate, and BF16, are
+    recorded as not met (MISS_VS_FP64)."""
     w = W.duct_les(nx=40, ny=24, nz=20, steps=300)
     g = gpu_from(w, lbm, storage=storage)
     o = make_oracle(w)
@@ -234,18 +247,14 @@ def test_16bit_accuracy_vs_fp64(lbm, storage):
     o.step(w.steps)
     rg, vg = g.get_macro()
     ro, vo = o.get_macro()
-    sg, _ = g.stress()
-    so, _ = o.stress()
+    sg, Sg = g.stress()
+    so, So = o.stress()
     fg = g.wall_force()[:4, 0]
     fo = o.wall_force(4)[:, 0]
-    e = dict(rho=np.abs(rg - ro).max(), v=rel_inf(vg, vo), sigma=rel_inf(sg, so),
+    e = dict(rho=np.abs(rg - ro).max(), v=rel_inf(vg, vo), sigma=rel_inf(sg, so), S=rel_inf(Sg, So),
              wall=np.linalg.norm(fg - fo) / np.linalg.norm(fo))
     say("16-bit %d vs FP64: %s" % (storage, {k: "%.2e" % v for k, v in e.items()}))
-    if storage == W.F16:
-        assert e["rho"] <= 2e-3 and e["v"] <= 2e-3 and e["wall"] <= 2e-3
-        assert e["sigma"] <= 1e-2
-    else:
-        assert e["v"] <= 2e-2 and e["sigma"] <= 1e-1
+    check_targets(e, 2e-3, MISS_VS_FP64[storage], "storage %d vs FP64" % storage)
 
 
 def test_duct_les_full_size_fp32(lbm):
@@ -275,10 +284,17 @@ def test_mhd_small(lbm):
         compare_all(g, o, storage, 4, "mhd %d" % storage)
         Bg = g.get_field_B()
         _, _, Bo = o.get_macro(with_B=True)
-        assert rel_inf(Bg - np.array(w.mhd[:3])[:, None, None, None],
-                       Bo - np.array(w.mhd[:3])[:, None, None, None]) <= max(TOL_FIELD[storage], 1e-4)
-        rg, ro = g.force_balance(), o.force_balance()
-        assert abs(rg[12:15] - ro[12:15]).max() <= 1e-10 * max(np.abs(ro[12:15]).max(), 1.0)
+        b0 = np.array(w.mhd[:3])[:, None, None, None]
+        e_b = rel_inf(Bg - b0, Bo - b0)
+        # the total Maxwell correction of a closed insulating duct is zero
+        # (Eq. 36): compare it with the per-wall corrections it sums
+        fo = o.wall_force(4)
+        per_wall = np.abs(fo[:, 2] - fo[:, 0]).max()
+        rg = g.force_balance()
+        e_mx = np.abs(rg[12:15]).max() / per_wall
+        say("  induced field B %.2e, total Maxwell correction / per wall %.2e" % (e_b, e_mx))
+        assert e_b <= TOL_FIELD[storage]
+        assert e_mx <= 1e-12
 
 
 def test_determinism(lbm):
@@ -368,11 +384,7 @@ def test_halfstep_mhd(lbm):
             e = dict(f=rel_inf(fg, fo), rho=np.abs(rg - ro).max(), u=rel_inf(ug, uo), sigma=rel_inf(sg, so))
             say("  %s" % {n: "%.2e" % v for n, v in e.items()})
             assert e["f"] <= TOL_FIELD[storage] and e["rho"] <= TOL_FIELD[storage]
-            # the oracle keeps phi(B0) in its deviations: the magnetic parts of
-            # -sum e e f_bar and of L(B_bar) (size B0^2 ~ 0.06) cancel in the
-            # stress (~1e-5) with its FP64 rounding, about 3e-12 of the stress
-            tol_s = 1e-11 if storage == W.F64 else TOL_STRESS[storage]
-            assert e["u"] <= TOL_FIELD[storage] and e["sigma"] <= tol_s
+            assert e["u"] <= TOL_FIELD[storage] and e["sigma"] <= TOL_STRESS[storage]
 
 
 def test_halfstep_needs_a_step(lbm):
@@ -421,3 +433,11 @@ def test_stokes_equilibrium_and_darcy_resistance(lbm, lattice, model, storage):
     assert rel_inf(sg, so) <= TOL_STRESS[storage]
     rg, ro = g.force_balance(), o.force_balance()
     assert np.abs(rg[3:6] - ro[3:6]).max() <= TOL_WALL[storage] * np.abs(ro[3:6]).max()
+    # the artefact term of Eq. (9) under the Stokes form (only -tau Theta)
+    g.set_artefact(True)
+    o.set_artefact(True)
+    sg, Sg = g.stress()
+    so, So = o.stress()
+    e_s, e_S = rel_inf(sg, so), rel_inf(Sg, So)
+    say("  with the artefact term: sigma %.2e S %.2e" % (e_s, e_S))
+    assert e_s <= TOL_STRESS[storage] and e_S <= TOL_STRESS[storage]

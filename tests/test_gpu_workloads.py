@@ -10,8 +10,9 @@ FP64 oracle and the closed forms and balances the paper fixes.
   Hartmann channel (192x96x1) to the closed form, and the Hartmann duct
       192x96x96 against the oracle, with the per-step balance (Eq. 32).
 Tolerances as in test_gpu_parity (FP64 1e-12, FP32 1e-5 fields / 1e-4 wall
-force); the 16-bit formats against the unquantized oracle are held to what
-their rounding allows, stated per test.
+force, 16-bit 2e-3); the 16-bit results that miss 2e-3 against the
+unquantized oracle are recorded as not met (expected failures stating the
+measured values, each within a recorded bound).
 """
 import sys
 
@@ -19,7 +20,7 @@ import numpy as np
 import pytest
 
 from closed_forms import hartmann, poiseuille_steady
-from helpers import make_oracle, rel_inf
+from helpers import check_targets, make_oracle, rel_inf
 from paper_2512_12213_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -42,13 +43,14 @@ def lbm():
 def errors(g, o, groups):
     rg, vg = g.get_macro()
     ro, vo = o.get_macro()
-    sg, _ = g.stress()
-    so, _ = o.stress()
+    sg, Sg = g.stress()
+    so, So = o.stress()
     fg = g.wall_force()[:groups]
     fo = o.wall_force(groups)
     ef = max(np.linalg.norm(fg[k, v] - fo[k, v]) / np.linalg.norm(fo[k, v])
              for k in range(groups) for v in range(4) if np.linalg.norm(fo[k, v]) > 0)
-    return dict(rho=float(np.abs(rg - ro).max()), v=rel_inf(vg, vo), sigma=rel_inf(sg, so), wall=ef)
+    return dict(rho=float(np.abs(rg - ro).max()), v=rel_inf(vg, vo), sigma=rel_inf(sg, so), S=rel_inf(Sg, So),
+                wall=ef)
 
 
 @pytest.mark.parametrize("model", [0, 1, 2, 3, 4])
@@ -89,10 +91,10 @@ def test_couette_cylinder_full_20000_steps(lbm, storage):
     tol = 1e-12 if storage == W.F64 else 1e-5
     assert e["rho"] <= tol and e["v"] <= tol
     # The stress is the non-equilibrium part of the state, a small difference
-    # of stored values.  FP32 storage alone (the oracle with its state rounded
+    # of stored values: FP32 storage alone (the oracle with its state rounded
     # to FP32 after every step) leaves 3e-6 to 1e-5 on it over this run (1e-5
-    # at step 9000, 3e-6 at 20 000); the FP32 arithmetic adds about as much.
-    assert e["sigma"] <= (1e-12 if storage == W.F64 else 2e-5)
+    # at step 9000, 3e-6 at 20 000)
+    assert e["sigma"] <= tol and e["S"] <= tol
     assert e["wall"] <= (1e-12 if storage == W.F64 else 1e-4)
     # tangentially moving lid and static walls: no momentum-flux correction
     assert np.abs(fw[:3, 1] - fw[:3, 0]).max() <= 1e-6 * np.abs(fw[:3, 0]).max()
@@ -129,14 +131,15 @@ def test_duct_les_full_size_1000_steps_every_format(lbm):
         say("storage %d: %s" % (st, {k: "%.2e" % x for k, x in res[st].items()}))
         g.close()
     e = res[W.F64]
-    assert max(e["rho"], e["v"], e["sigma"], e["wall"]) <= 1e-12
+    assert max(e["rho"], e["v"], e["sigma"], e["S"], e["wall"]) <= 1e-12
     e = res[W.F32]
-    assert max(e["rho"], e["v"], e["sigma"]) <= 1e-5 and e["wall"] <= 1e-4
-    e = res[W.F16]
-    assert max(e["rho"], e["v"], e["wall"]) <= 2e-3
-    # BF16 keeps 8 significant bits: reported above, held to its own rounding scale
-    e = res[W.BF16]
-    assert e["v"] <= 5e-2 and e["wall"] <= 2e-2
+    assert max(e["rho"], e["v"], e["sigma"], e["S"]) <= 1e-5 and e["wall"] <= 1e-4
+    # 16-bit formats at 2e-3; recorded as not met (format floors; bounds about
+    # 1.5 times the largest measured): FP16 stress and strain rate, BF16 all
+    errs = {"f16 %s" % k: res[W.F16][k] for k in ("rho", "v", "sigma", "S", "wall")}
+    errs.update({"bf16 %s" % k: res[W.BF16][k] for k in ("rho", "v", "sigma", "S", "wall")})
+    check_targets(errs, 2e-3, {"f16 sigma": 1.2e-2, "f16 S": 1.2e-2, "bf16 rho": 8e-3, "bf16 v": 1.2e-2,
+                               "bf16 sigma": 1e-1, "bf16 S": 1e-1, "bf16 wall": 8e-3}, "duct 1000 steps")
 
 
 def test_hartmann_channel_full_size_closed_form(lbm):
@@ -179,8 +182,8 @@ def test_hartmann_duct_full_size_vs_oracle(lbm):
     b0 = np.array(w.mhd[:3])[:, None, None, None]
     e["b"] = rel_inf(Bg - b0, Bo - b0)
     say("Hartmann duct: %s" % {k: "%.2e" % x for k, x in e.items()})
-    assert e["rho"] <= 1e-5 and e["v"] <= 1e-5 and e["sigma"] <= 1e-5 and e["wall"] <= 1e-4
-    assert e["b"] <= 1e-4
+    assert e["rho"] <= 1e-5 and e["v"] <= 1e-5 and e["sigma"] <= 1e-5 and e["S"] <= 1e-5 and e["wall"] <= 1e-4
+    assert e["b"] <= 1e-5
     g.step(w.steps - 200)
     rec = g.force_balance()
     say("after %d steps: residual %.2e, F_wall / sum rho a %.6f, Maxwell total %.2e"
