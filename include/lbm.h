@@ -52,6 +52,8 @@ enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3 };
 enum { LBM_EQ_NS = 0, LBM_EQ_STOKES = 1 };
 enum { LBM_OK = 0, LBM_EINVAL = -1, LBM_ENOMEM = -2, LBM_EHIP = -3, LBM_ESTATE = -4, LBM_EUNSTABLE = -5 };
 enum { LBM_MAX_GROUPS = 16, LBM_NREC = 24 };
+/* Bytes of the fixed device scratch array of lbm_step_noalloc (8 MiB). */
+enum { LBM_SCRATCH_BYTES = 8 << 20 };
 
 /* Create a lattice.  Section 2: uniform grid with spacing dx, time step dt,
  * relaxation time tau (tau > 1/2), D2Q9 (nz must be 1) or D3Q19.  All axes
@@ -191,6 +193,25 @@ int lbm_get_induction(lbm_ctx* ctx, double* g_host);
  * stream synchronisation and a finiteness check of the total mass:
  * LBM_EUNSTABLE if it is NaN or infinite. */
 int lbm_step(lbm_ctx* ctx, int n);
+
+/* lbm_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same steps and records as lbm_step(ctx, n), with the step's scratch (the
+ * per-tile partial sums of the last step, the reduced records, and with walls
+ * that are not halfway the changes of their returning values and their sums)
+ * taken from a fixed array of LBM_SCRATCH_BYTES bytes in device memory, one
+ * copy per GPU, held until the process ends; it calls no hipMalloc, hipFree
+ * or allocating routine (the context's own buffers are allocated by its
+ * set-up and state calls).  Fits lattices whose scratch is at most that size,
+ * about 184 bytes per 256 nodes plus 152 bytes per node with links to walls
+ * that are not halfway (e.g. 11 M nodes with halfway walls); larger ones
+ * give LBM_EINVAL before any work.  Every call on one GPU uses that GPU's
+ * single array and leaves its contents there; nothing in it has to start at
+ * zero (each step writes every entry it later reads).  Calls that overlap on
+ * one GPU (contexts used from several host threads or on streams that run
+ * concurrently) race on the array.  Per-launch timing (lbm_set_timing) is
+ * not recorded. */
+int lbm_step_noalloc(lbm_ctx* ctx, int n);
 
 /* Density rho [nz][ny][nx] and flow velocity v = u + dt a / 2 [D][nz][ny][nx]
  * (Section 2) of the current state, into caller-owned host buffers (either

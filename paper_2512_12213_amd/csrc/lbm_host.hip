@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -29,6 +30,13 @@ hipError_t launch_adj(int lattice, int prec, int adj_prec, const AdjArgs& a, int
 }  // namespace lbm
 
 using namespace lbm;
+
+// Fixed scratch for lbm_step_noalloc: a file-scope device array, one copy on
+// each GPU the library runs on, held until the process ends.  In host code
+// its name is not a device address: the address is looked up once per device
+// (with that device current, device_scratch below) and only that pointer is
+// ever handed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[LBM_SCRATCH_BYTES];
 
 namespace {
 
@@ -123,6 +131,7 @@ struct lbm_ctx {
   DevBuf ibb_node, ibb_rec, ibb_q, ibb_grp, ibb_delta, ibb_part, ibb_red;
   uint32_t nibb = 0;
   double* hred = nullptr;  // pinned [NBAL + MAXG * NWALL]
+  void* scratch = nullptr;  // this device's fixed scratch array (lbm_step_noalloc), or null
   bool uw_dirty = true;
   bool have_state = false;
   long steps = 0;
@@ -444,6 +453,68 @@ int setup_guard(lbm_ctx* h) {
   return LBM_OK;
 }
 
+// Device scratch of the step (per-tile partial sums, the reduced records, the
+// interpolated-wall changes and their sums), from the context's own buffers
+// or carved from the fixed array below.
+struct Scratch {
+  double* part;       // [NPART][ntiles]
+  double* red;        // [NBAL + MAXG NWALL]
+  double* ibb_delta;  // [nibb Q]
+  double* ibb_part;   // [ceil(nibb Q / NTHREADS)][MAXG][4]
+  double* ibb_red;    // [MAXG][4]
+};
+
+Scratch own_scratch(lbm_ctx* h) {
+  return Scratch{(double*)h->part.p, (double*)h->red.p, (double*)h->ibb_delta.p, (double*)h->ibb_part.p,
+                 (double*)h->ibb_red.p};
+}
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of the current device's array (looked up on the first call for the
+// device), or null with the HIP error.
+void* device_scratch(int dev, hipError_t* err) {
+  *err = hipSuccess;
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// The step's scratch carved from the fixed array; bytes needed in *need.
+Scratch fixed_scratch(const lbm_ctx* h, size_t* need) {
+  char* base = (char*)h->scratch;
+  size_t off = 0;
+  auto carve = [&](size_t bytes) {
+    char* p = base + off;
+    off += round256(bytes);
+    return (double*)p;
+  };
+  Scratch sc = {};
+  sc.part = carve((size_t)h->ntiles * NPART * sizeof(double));
+  sc.red = carve((NBAL + MAXG * NWALL) * sizeof(double));
+  if (h->nibb) {
+    const size_t entries = (size_t)h->nibb * h->Q;
+    sc.ibb_delta = carve(entries * sizeof(double));
+    sc.ibb_part = carve(((entries + NTHREADS - 1) / NTHREADS) * MAXG * 4 * sizeof(double));
+    sc.ibb_red = carve(MAXG * 4 * sizeof(double));
+  }
+  *need = off;
+  return sc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -501,6 +572,12 @@ lbm_ctx* lbm_create(int lattice, int nx, int ny, int nz, double tau, double dx, 
     return nullptr;
   }
   h->stream = h->own;
+  {
+    // the fixed scratch of lbm_step_noalloc: its address on this device
+    // (a failed lookup only disables that entry point)
+    hipError_t e;
+    h->scratch = device_scratch(h->device, &e);
+  }
   if (hipHostMalloc((void**)&h->hred, (2 * (NBAL + MAXG * NWALL) + NDIAGPART + MAXG * 4) * sizeof(double)) !=
       hipSuccess) {
     fail(LBM_ENOMEM, "pinned host buffer");
@@ -780,11 +857,16 @@ static int upload_uw(lbm_ctx* h) {
 // n >= 1 steps; the last one with diagnostics.  With ckpt_every > 0 the state
 // before step i is copied to checkpoint i / ckpt_every whenever
 // i % ckpt_every == 0; with a tape, every step also records rho and U of its
-// pre-step state at tape + i * 4 N values.
-static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
+// pre-step state at tape + i * 4 N values.  sc: the scratch buffers of the
+// step (the context's own when null); timing events are recorded only with
+// the context's own buffers (creating events may allocate).
+static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, const Scratch* scp = nullptr) {
   int rc = upload_uw(h);
   if (rc) return rc;
+  const Scratch sc = scp ? *scp : own_scratch(h);
+  const bool timing = h->timing && !scp;
   StepArgs a = step_args(h);
+  a.part = sc.part;
   const size_t mbytes = (size_t)4 * h->N * elem_bytes(h->prec);
   IbbArgs ib = {};
   if (h->nibb) {
@@ -800,7 +882,7 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
     ib.p = a.p;
   }
   const size_t sbytes = (size_t)h->Q * h->N * elem_bytes(h->prec);
-  if (h->timing) {
+  if (timing) {
     while (h->ev.size() < (size_t)n + 2) {
       hipEvent_t e;
       HIPCHK(hipEventCreate(&e));
@@ -808,7 +890,7 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
     }
   }
   const int par0 = h->parity;
-  if (h->timing) HIPCHK(hipEventRecord(h->ev[0], h->stream));
+  if (timing) HIPCHK(hipEventRecord(h->ev[0], h->stream));
   for (int i = 0; i < n; ++i) {
     if (ckpt_every > 0 && i % ckpt_every == 0)
       HIPCHK(hipMemcpyAsync((char*)h->ckpt.p + (size_t)(i / ckpt_every) * sbytes, h->f.p, sbytes,
@@ -822,24 +904,24 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr) {
     }
     if (h->nibb) {
       ib.parity = h->parity ^ 1;
-      ib.delta = diag ? (double*)h->ibb_delta.p : nullptr;
+      ib.delta = diag ? sc.ibb_delta : nullptr;
       HIPCHK(launch_ibb(h->lattice, h->prec, ib, h->stream));
     }
-    if (h->timing) HIPCHK(hipEventRecord(h->ev[i + 1], h->stream));
+    if (timing) HIPCHK(hipEventRecord(h->ev[i + 1], h->stream));
     h->parity ^= 1;
   }
-  HIPCHK(launch_reduce((const double*)h->part.p, (const uint32_t*)h->wlist.p, h->ntiles, 0, h->G, NBAL + MAXG * NWALL,
-                       (double*)h->red.p, h->stream));
-  HIPCHK(hipMemcpyAsync(h->hred, h->red.p, (NBAL + MAXG * NWALL) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(launch_reduce(sc.part, (const uint32_t*)h->wlist.p, h->ntiles, 0, h->G, NBAL + MAXG * NWALL, sc.red,
+                       h->stream));
+  HIPCHK(hipMemcpyAsync(h->hred, sc.red, (NBAL + MAXG * NWALL) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   double* ibb_host = h->hred + 2 * (NBAL + MAXG * NWALL) + NDIAGPART;
   if (h->nibb) {
-    HIPCHK(launch_ibb_reduce(h->lattice, (const double*)h->ibb_delta.p, (const uint8_t*)h->ibb_grp.p, h->nibb, h->G,
-                             (double*)h->ibb_part.p, (double*)h->ibb_red.p, h->stream));
-    HIPCHK(hipMemcpyAsync(ibb_host, h->ibb_red.p, (size_t)h->G * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(launch_ibb_reduce(h->lattice, sc.ibb_delta, (const uint8_t*)h->ibb_grp.p, h->nibb, h->G, sc.ibb_part,
+                             sc.ibb_red, h->stream));
+    HIPCHK(hipMemcpyAsync(ibb_host, sc.ibb_red, (size_t)h->G * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   }
-  if (h->timing) HIPCHK(hipEventRecord(h->ev[n + 1], h->stream));
+  if (timing) HIPCHK(hipEventRecord(h->ev[n + 1], h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
-  if (h->timing) {
+  if (timing) {
     double se = 0, so = 0;
     int ne = 0, no = 0;
     for (int i = 0; i < n; ++i) {
@@ -882,6 +964,21 @@ int lbm_step(lbm_ctx* h, int n) {
   if (n == 0) return LBM_OK;
   h->tape = false;
   return step_loop(h, n, 0);
+}
+
+int lbm_step_noalloc(lbm_ctx* h, int n) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (n < 0) return fail(LBM_EINVAL, "negative step count");
+  if (!h->scratch) return fail(LBM_EHIP, "the fixed scratch array of this device could not be located");
+  size_t need = 0;
+  const Scratch sc = fixed_scratch(h, &need);
+  if (need > (size_t)LBM_SCRATCH_BYTES)
+    return fail(LBM_EINVAL, "lbm_step_noalloc: this lattice needs %zu bytes of step scratch, above the fixed %d",
+                need, (int)LBM_SCRATCH_BYTES);
+  if (n == 0) return LBM_OK;
+  h->tape = false;
+  return step_loop(h, n, 0, nullptr, &sc);
 }
 
 int lbm_get_macro(lbm_ctx* h, double* rho, double* v) {

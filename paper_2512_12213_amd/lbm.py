@@ -20,6 +20,7 @@ LBM_EQ_NS, LBM_EQ_STOKES = 0, 1
 LBM_MHD_EQUILIBRIUM, LBM_MHD_LORENTZ_FORCE = 0, 1
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_EUNSTABLE = 0, -1, -2, -3, -4, -5
 LBM_MAX_GROUPS, LBM_NREC = 16, 24
+LBM_SCRATCH_BYTES = 8 << 20
 
 # (name, restype, argtypes)
 _P = C.c_void_p
@@ -48,6 +49,7 @@ _SIGS = [
     ("lbm_get_state", C.c_int, [_P, _D]),
     ("lbm_get_induction", C.c_int, [_P, _D]),
     ("lbm_step", C.c_int, [_P, C.c_int]),
+    ("lbm_step_noalloc", C.c_int, [_P, C.c_int]),
     ("lbm_get_macro", C.c_int, [_P, _D, _D]),
     ("lbm_get_field_B", C.c_int, [_P, _D]),
     ("lbm_stress", C.c_int, [_P, _D, _D]),
@@ -230,6 +232,10 @@ class Lattice:
     # hot path and outputs
     def step(self, n=1):
         _chk(self.L.lbm_step(self.h, n))
+
+    def step_noalloc(self, n=1):
+        """lbm_step with the step's scratch in the library's fixed device array."""
+        _chk(self.L.lbm_step_noalloc(self.h, n))
 
     def get_macro(self):
         rho = np.empty((self.nz, self.ny, self.nx))
