@@ -189,17 +189,15 @@ __device__ __forceinline__ void macro(const T (&d)[L::Q], const Phys& p, T Ax, T
 //   magnetic term,
 // so that small quantities are never rounded at the scale of large ones.  The
 // weights 1/9, 1/18, 1/36 are applied as hi + lo parts so that the large
-// part's moments are not scaled by the weights' own rounding, and in FP32
-// the mass and momentum of its non-equilibrium part are closed exactly
-// (below).
+// part's moments are not scaled by the weights' own rounding, and with
+// FP32 storage (CLOSE) the mass and momentum of its non-equilibrium part are
+// closed exactly (below; under 16-bit storage, at boundary nodes, the
+// format's rounding is far coarser and the closure is left out).
 // sink(q, value) receives each post-collision value as soon as it is formed,
 // so that it can be stored at once and its register freed.
 //
-// RAW (16-bit formats, interior nodes): d and the values handed to sink are
-// in the stored units (d_q / isc_q, isc_q = the format's factor); the
-// increment is scaled once onto the stored value, and the weights are not
-// split (the format's own rounding is far coarser than theirs).
-template <class L, class T, int MHD, class Sink, bool RAW = false>
+// (16-bit formats at interior nodes use collide_raw below.)
+template <class L, class T, int MHD, class Sink, bool CLOSE>
 __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, const T (&db)[3], const Phys& p,
                                         Sink&& sink) {
   const T rho = m.rho;
@@ -261,7 +259,7 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
   T Rs0 = rlq * (T(-3) * ua) + rl2q * (T(-1.5) * aa);
   if (MHD == 1) Rs0 += T(-4.5) * last;
   const T F0 = cr * (T)L::w(0) * (T(-3) * ufa);
-  if constexpr (!RAW && sizeof(T) == 4) {
+  if constexpr (CLOSE) {
     // FP32.  The large part's rounding (about one unit of the last place of
     // f per direction) would change the mass and momentum of the
     // non-equilibrium part neq = w Rb - d, which relaxation never removes:
@@ -320,9 +318,8 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
       const T w = (T)L::w(0);
       const T wlo = (T)(L::w(0) - (double)w);
       const T Rb = m.drho - rq * usq;
-      const T neq = RAW ? w * Rb - d[0] * (T)p.inv_scale[0] : (w * Rb + wlo * Rb) - d[0];
-      const T X = (neq + w * Rs0) * itau + F0;
-      sink(0, RAW ? d[0] + X * (T)p.scale[0] : d[0] + X);
+      const T neq = (w * Rb + wlo * Rb) - d[0];
+      sink(0, d[0] + ((neq + w * Rs0) * itau + F0));
     }
 #pragma unroll
     for (int k = 0; k < (L::Q - 1) / 2; ++k) {
@@ -330,30 +327,83 @@ __device__ __forceinline__ void collide(const T (&d)[L::Q], const Macro<T>& m, c
       const PairTerms t = pair_terms(q);
       const T w = (T)L::w(q);
       const T wlo = (T)(L::w(q) - (double)w);
-      if (RAW) {
-        // opposite directions share the format's factor
-        const T isc = (T)p.inv_scale[q], sc = (T)p.scale[q];
-        {
-          const T neq = w * (t.Eb + t.Ob) - d[q] * isc;
-          sink(q, d[q] + ((neq + w * (t.Es + t.Os)) * itau + (t.EF + t.OF)) * sc);
-        }
-        {
-          const T neq = w * (t.Eb - t.Ob) - d[q + 1] * isc;
-          sink(q + 1, d[q + 1] + ((neq + w * (t.Es - t.Os)) * itau + (t.EF - t.OF)) * sc);
-        }
-      } else {
-        {
-          const T Rb = t.Eb + t.Ob;
-          const T neq = (w * Rb + wlo * Rb) - d[q];
-          sink(q, d[q] + ((neq + w * (t.Es + t.Os)) * itau + (t.EF + t.OF)));
-        }
-        {
-          const T Rb = t.Eb - t.Ob;
-          const T neq = (w * Rb + wlo * Rb) - d[q + 1];
-          sink(q + 1, d[q + 1] + ((neq + w * (t.Es - t.Os)) * itau + (t.EF - t.OF)));
-        }
+      {
+        const T Rb = t.Eb + t.Ob;
+        const T neq = (w * Rb + wlo * Rb) - d[q];
+        sink(q, d[q] + ((neq + w * (t.Es + t.Os)) * itau + (t.EF + t.OF)));
+      }
+      {
+        const T Rb = t.Eb - t.Ob;
+        const T neq = (w * Rb + wlo * Rb) - d[q + 1];
+        sink(q + 1, d[q + 1] + ((neq + w * (t.Es - t.Os)) * itau + (t.EF - t.OF)));
       }
     }
+  }
+}
+
+// The same relaxation in the stored units of a 16-bit format at interior
+// nodes (no MHD): v = K d / w with K = 2^10 (FP16) or 1 (BF16).  Eq. (1) and
+// the force term of Eq. (3) are both quadratic in e, so
+//   w R(e) = f^eq - w rho0,  R(e) = drho + rho [3 e.ue + quad (9/2 (e.ue)^2 - 3/2 ue.ue)],
+//   F(e) = w C rho [3 (e - uF).a + 9 (e.uF)(e.a)],
+// and the relaxed value d + (w R - d) / tau + F becomes, in stored units,
+//   v' = v (1 - 1/tau) + K P(e),  P(e) = R(e) / tau + F(e) / w = a0 + b.e + e.Cm.e,
+// whose ten coefficients are formed once per node; a direction and its
+// opposite then share the even part a0 + e.Cm.e and differ in the sign of
+// b.e.  The format's rounding (2^-11 or 2^-8 relative) is far coarser than
+// that of this FP32 form, so the splitting of the FP32 path is not needed.
+template <class L, int P, class Sink>
+__device__ __forceinline__ void collide_raw(const float (&v)[L::Q], const Macro<float>& m, const Phys& p,
+                                            Sink&& sink) {
+  using T = float;
+  constexpr T K = P == S_F16 ? T(1024) : T(1);
+  const T rho = m.rho, itau = m.itau;
+  const T kq = K * rho * par<T>(p.quad, p.f.quad);  // K rho quad
+  const T kc = K * m.C * rho;                        // K C rho
+  const T kt = kq * itau;
+  const T* ue = m.Ue;
+  const T* uf = m.UF;
+  const T* A = m.A;
+  const T uu = ue[0] * ue[0] + ue[1] * ue[1] + ue[2] * ue[2];
+  const T ufa = uf[0] * A[0] + uf[1] * A[1] + uf[2] * A[2];
+  const T a0 = (K * m.drho - T(1.5) * kq * uu) * itau - T(3) * kc * ufa;
+  T b[3], Cm[3], Cd[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    b[i] = T(3) * (K * rho * itau * ue[i] + kc * A[i]);
+    Cm[i] = T(4.5) * kt * ue[i] * ue[i] + T(9) * kc * uf[i] * A[i];
+    Cd[i] = a0 + Cm[i];
+  }
+  // twice the off-diagonal coefficients, xy, xz, yz
+  const int ci[3] = {0, 0, 1}, cj[3] = {1, 2, 2};
+  T C2[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int i = ci[c], j = cj[c];
+    C2[c] = T(9) * kt * ue[i] * ue[j] + T(9) * kc * (uf[i] * A[j] + uf[j] * A[i]);
+  }
+  const T om = T(1) - itau;
+  sink(0, v[0] * om + a0);
+#pragma unroll
+  for (int k = 0; k < (L::Q - 1) / 2; ++k) {
+    const int q = 2 * k + 1;
+    const int e[3] = {L::ex(q), L::ey(q), L::ez(q)};
+    T E, O;
+    if (L::e2(q) == 1) {
+      const int i = e[0] != 0 ? 0 : (e[1] != 0 ? 1 : 2);
+      E = Cd[i];
+      O = e[i] > 0 ? b[i] : -b[i];
+    } else {
+      // two nonzero components i < j
+      const int i = e[0] != 0 ? 0 : 1;
+      const int j = e[2] != 0 ? 2 : 1;
+      const int c = i == 0 ? (j == 1 ? 0 : 1) : 2;
+      const T base = Cd[i] + Cm[j];  // a0 + Cm_ii + Cm_jj
+      E = e[i] * e[j] > 0 ? base + C2[c] : base - C2[c];
+      O = (e[i] > 0 ? b[i] : -b[i]) + (e[j] > 0 ? b[j] : -b[j]);
+    }
+    sink(q, v[q] * om + (E + O));
+    sink(q + 1, v[q + 1] * om + (E - O));
   }
 }
 
@@ -549,7 +599,10 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
       write_f1<L, P, PAR, BND, AD, !RAW>(fo, Af, mask, a.p, q, v);
     }
   };
-  collide<L, T, MHD, decltype(sink)&, RAW>(d, m, db, a.p, sink);
+  if constexpr (RAW)
+    collide_raw<L, P>(d, m, a.p, sink);
+  else
+    collide<L, T, MHD, decltype(sink)&, P == S_F32>(d, m, db, a.p, sink);
   if constexpr (XS) {
     __syncthreads();
 #pragma unroll
