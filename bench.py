@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and workloads")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--only", choices=["adjoint", "hartmann", "halfstep", "sphere", "formats"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "hartmann", "halfstep", "sphere", "formats", "stress"], default=None,
                     help="run only this measurement (for profiling its kernels) and print its record")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a plain copy kernel of known size, "
@@ -104,11 +104,19 @@ def copy_ceiling(torch, nbytes, repeats=20):
     return 2 * n * 4 / t / 1e9
 
 
-def timed_run(lbm, torch, w, steps, warmup, storage=None):
-    """Warm up, then time one lbm_step(steps) call; returns a result dict."""
+def timed_run(lbm, torch, w, steps, warmup, storage=None, stress_every_step=False):
+    """Warm up, then time one lbm_step(steps) call; returns a result dict.
+    stress_every_step: every step also stores the stress and strain rate of
+    the state it starts from (lbm_set_step_stress, FP32, 2 x 4 x ncomp bytes
+    per node more)."""
     lat = lbm.from_workload(w, storage=storage)
     stream = torch.cuda.current_stream()
     lat.set_stream(stream.cuda_stream)
+    nc = 3 if w.D == 2 else 6
+    if stress_every_step:
+        sig = torch.empty((nc, w.nz, w.ny, w.nx), dtype=torch.float32, device="cuda")
+        strain = torch.empty_like(sig)
+        lat.set_step_stress(sig.data_ptr(), strain.data_ptr(), 1)
     if warmup:
         lat.step(warmup)
     lat.set_timing(True)
@@ -129,6 +137,8 @@ def timed_run(lbm, torch, w, steps, warmup, storage=None):
     nfluid = w.N if mask is None else int((mask == 0).sum())
     ind_planes = 21 if w.Q == 19 else 10  # induction directions x field components
     bpn = 2 * w.Q * BYTES[st] + (2 * ind_planes * BYTES[st] if w.mhd is not None else 0)
+    if stress_every_step:
+        bpn += 2 * nc * 4
     n_even = (steps - 1 + 1) // 2
     launch = (tim["even"] * n_even + tim["odd"] * (steps - 1 - n_even)) / max(steps - 1, 1)
     return {
@@ -366,6 +376,12 @@ def main():
             rs[name] = timed_run(lbm, torch, W.duct_les(), args.steps, args.warmup, storage=st)
         print(json.dumps(rs), flush=True)
         return
+    if args.only == "stress":
+        rs = {"duct_les_f32_stress_every_step": timed_run(lbm, torch, W.duct_les(), args.steps, args.warmup,
+                                                           stress_every_step=True),
+              "duct_les_f32": timed_run(lbm, torch, W.duct_les(), args.steps, args.warmup)}
+        print(json.dumps(rs), flush=True)
+        return
     if args.only == "sphere":
         # the duct with a sphere, halfway and interpolated walls
         rs = {}
@@ -423,6 +439,9 @@ def main():
         for name, st in (("duct_f16", W.F16), ("duct_bf16", W.BF16), ("duct_f64", W.F64)):
             print("bench: variant %s" % name, file=sys.stderr, flush=True)
             variants[name] = timed_run(lbm, torch, w, half, min(args.warmup, 10), storage=st)
+        print("bench: variant duct storing the stress and strain rate every step", file=sys.stderr, flush=True)
+        variants["duct_les_f32_stress_every_step"] = timed_run(lbm, torch, w, half, min(args.warmup, 10),
+                                                               stress_every_step=True)
         print("bench: variant duct without LES", file=sys.stderr, flush=True)
         wn = W.duct_les()
         wn.les_cs = 0.0

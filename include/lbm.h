@@ -136,6 +136,18 @@ int lbm_set_darcy(lbm_ctx* ctx, double sigma);
  * outputs (0 = off, the default).  Any time. */
 int lbm_set_artefact(lbm_ctx* ctx, int include_Eij);
 
+/* Stress and strain rate written by the steps themselves (Eqs. 8-9, the
+ * values lbm_stress gives, with the artefact term when lbm_set_artefact is
+ * on): during lbm_step, each step whose index i (steps taken since the state
+ * was set, before that step) is a multiple of `every` >= 1 writes sigma and
+ * S of the state f(t_i) it starts from, as FP32 in physical units, into the
+ * borrowed device buffers sigma_dev and strain_dev (float [ncomp][nz][ny][nx],
+ * component order of lbm_stress; either may be NULL), at 4 ncomp bytes per
+ * node and buffer on top of the step's own traffic.  The buffers are zeroed
+ * by this call (solid nodes keep 0) and must stay valid while steps run.
+ * Both NULL turns it off.  Any time. */
+int lbm_set_step_stress(lbm_ctx* ctx, void* sigma_dev, void* strain_dev, int every);
+
 /* MHD (Section 4; F32/F64 storage) with a vector-distribution induction
  * lattice (relaxation time tau_m > 1/2, magnetic diffusivity
  * dt c^2 (tau_m - 1/2) / 4): D3Q7 with three field components on D3Q19; on

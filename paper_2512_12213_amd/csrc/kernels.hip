@@ -472,6 +472,41 @@ __host__ __device__ constexpr int xshift_index(int q) {
   return c;
 }
 
+// Shear stress sigma = 2 rho nu S (Eq. 8) and strain rate
+// S = -3 / (2 tau dt c^2 rho) (Pi^neq [+ E]) (Eq. 9) of the node's pre-step
+// state, in physical units, stored as FP32 [NC][N] (2D: xx, xy, yy; 3D: xx,
+// yy, zz, xy, xz, yz).  m.pi holds Pi^neq / c^2 and tau the closure's.  The
+// artefact term E / c^2 = tau rho [quad (ue_i A_j + ue_j A_i) - thC C (uF_i A_j
+// + uF_j A_i)] (Eq. 9 with Theta of Eq. 4; the Stokes form has no ue A part).
+template <class L, class T>
+__device__ __forceinline__ void store_stress(const StepArgs& a, uint32_t n, const Macro<T>& m) {
+  T Pn[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) Pn[c] = m.pi[c];
+  if (a.st_artefact) {
+    const int ci[6] = {0, 1, 2, 0, 0, 1}, cj[6] = {0, 1, 2, 1, 2, 2};
+    const T quad = par<T>(a.p.quad, a.p.f.quad);
+    const T thc = par<T>(a.p.thC, a.p.f.thC) * m.C;
+    const T tr = m.tau * m.rho;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const int i = ci[c], j = cj[c];
+      Pn[c] += tr * (quad * (m.Ue[i] * m.A[j] + m.Ue[j] * m.A[i]) - thc * (m.UF[i] * m.A[j] + m.UF[j] * m.A[i]));
+    }
+  }
+  // sigma = -c^2 (1 - 1 / (2 tau)) Pn, S = -(3 / (2 dt)) Pn / (tau rho)
+  const T cs = -(T)a.st_c2 * (T(1) - T(0.5) * m.itau);
+  const T cS = -(T)a.st_hdt * m.itau * m.irho;
+  const int map2[3] = {0, 3, 1};
+  const uint64_t N = a.geo.N;
+#pragma unroll
+  for (int c = 0; c < L::NC; ++c) {
+    const T v = Pn[L::D == 2 ? map2[c] : c];
+    if (a.sig) __builtin_nontemporal_store((float)(cs * v), a.sig + (c * N + n));
+    if (a.strain) __builtin_nontemporal_store((float)(cS * v), a.strain + (c * N + n));
+  }
+}
+
 // XS (odd steps, tiles of whole rows without boundary links, buffer
 // addressing): the x-shifted directions go through LDS.  The tile loads the
 // source row of such a direction at its own x (aligned, coalesced), and each
@@ -480,7 +515,8 @@ __host__ __device__ constexpr int xshift_index(int q) {
 // holds whole rows and x wraps inside a row, so every slot it loads or stores
 // still belongs to one of its own nodes.  Every thread of the tile takes this
 // path (the choice is per tile), so the two barriers are reached uniformly.
-template <class L, int P, int MHD, int PAR, bool DIAG, bool MAC, bool BND, class AD, bool XS = false>
+// ST: the step also stores the stress and strain rate of the pre-step state.
+template <class L, int P, int MHD, int PAR, bool DIAG, bool MAC, bool BND, class AD, bool XS = false, bool ST = false>
 __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const AD& Af, const AD& Ag, const uint4& rec,
                                             typename Stor<P>::T (&bal)[NBAL],
                                             typename Stor<P>::T (&wacc)[MAXBG][NWALL], uint32_t bgrp,
@@ -542,7 +578,8 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
     ind_moments<L, T>(h, db, lam);  // B - B0 = sum_k (g_k - W_k B0)
   }
   Macro<T> m;
-  macro<L, T, MHD, false, RAW>(d, a.p, Ax, Ay, Az, db, lam, m);
+  macro<L, T, MHD, ST, RAW>(d, a.p, Ax, Ay, Az, db, lam, m);
+  if constexpr (ST) store_stress<L, T>(a, n, m);
   if (MAC) {
     // density and velocity of the pre-step state, for the adjoint
     T* mo = (T*)a.mac;
@@ -647,7 +684,7 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles, uint32
 // RU: 0 generic addressing; 1 row-uniform pointers; 2 row-uniform pointers
 // for rows with boundary links and buffer resources for the other rows
 // (arrays below 4 GiB).
-template <class L, int P, int MHD, int PAR, bool DIAG, int RU, bool MAC = false>
+template <class L, int P, int MHD, int PAR, bool DIAG, int RU, bool MAC = false, bool ST = false>
 __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   using T = typename Stor<P>::T;
   const Geom& g = a.geo;
@@ -697,27 +734,27 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
         if constexpr (XS_OK) {
           if ((bgrp >> 27) & 1u) {
             // tile of whole rows without boundary links (uniform per tile)
-            node_update<L, P, MHD, PAR, DIAG, MAC, false, AddrB, true>(a, n, Af, Ag, rec, bal, wacc, bgrp, x);
+            node_update<L, P, MHD, PAR, DIAG, MAC, false, AddrB, true, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp, x);
           } else {
-            node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+            node_update<L, P, MHD, PAR, DIAG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp);
           }
         } else {
-          node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          node_update<L, P, MHD, PAR, DIAG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp);
         }
       } else if (RU) {
         const AddrR Af = addr_r(g, x, y, z, L::Q);
         const AddrR Ag = addr_r(g, x, y, z, MHD ? Ind<L>::K * Ind<L>::NB : L::Q);
         if (rr < 0)
-          node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          node_update<L, P, MHD, PAR, DIAG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp);
         else
-          node_update<L, P, MHD, PAR, DIAG, MAC, true>(a, n, Af, Ag, rec, bal, wacc, bgrp, 0u, suw);
+          node_update<L, P, MHD, PAR, DIAG, MAC, true, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp, 0u, suw);
       } else {
         const AddrG Af = addr_g(g, x, y, z, r, L::Q);
         const AddrG Ag = addr_g(g, x, y, z, r, MHD ? Ind<L>::K * Ind<L>::NB : L::Q);
         if (rr < 0)
-          node_update<L, P, MHD, PAR, DIAG, MAC, false>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          node_update<L, P, MHD, PAR, DIAG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp);
         else
-          node_update<L, P, MHD, PAR, DIAG, MAC, true>(a, n, Af, Ag, rec, bal, wacc, bgrp, 0u, suw);
+          node_update<L, P, MHD, PAR, DIAG, MAC, true, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp, 0u, suw);
       }
     }
   }
@@ -1302,19 +1339,29 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // launchers (called by the host library)
 // ---------------------------------------------------------------------------
-template <class L, int P, int MHD, int RU>
-static void launch_step_ru(const StepArgs& a, int parity, bool diag, uint32_t nb, hipStream_t st) {
+template <class L, int P, int MHD, int RU, bool ST>
+static void launch_step_ru_st(const StepArgs& a, int parity, bool diag, uint32_t nb, hipStream_t st) {
   if (parity == 0) {
     if (diag)
-      k_step<L, P, MHD, 0, true, RU><<<nb, NTHREADS, 0, st>>>(a);
+      k_step<L, P, MHD, 0, true, RU, false, ST><<<nb, NTHREADS, 0, st>>>(a);
     else
-      k_step<L, P, MHD, 0, false, RU><<<nb, NTHREADS, 0, st>>>(a);
+      k_step<L, P, MHD, 0, false, RU, false, ST><<<nb, NTHREADS, 0, st>>>(a);
   } else {
     if (diag)
-      k_step<L, P, MHD, 1, true, RU><<<nb, NTHREADS, 0, st>>>(a);
+      k_step<L, P, MHD, 1, true, RU, false, ST><<<nb, NTHREADS, 0, st>>>(a);
     else
-      k_step<L, P, MHD, 1, false, RU><<<nb, NTHREADS, 0, st>>>(a);
+      k_step<L, P, MHD, 1, false, RU, false, ST><<<nb, NTHREADS, 0, st>>>(a);
   }
+}
+
+// Steps that store the stress and strain rate (a.sig or a.strain set) run
+// their own instantiation, so that the other steps keep their registers.
+template <class L, int P, int MHD, int RU>
+static void launch_step_ru(const StepArgs& a, int parity, bool diag, uint32_t nb, hipStream_t st) {
+  if (a.sig || a.strain)
+    launch_step_ru_st<L, P, MHD, RU, true>(a, parity, diag, nb, st);
+  else
+    launch_step_ru_st<L, P, MHD, RU, false>(a, parity, diag, nb, st);
 }
 
 template <class L, int P, int MHD>

@@ -55,6 +55,10 @@ struct StepArgs {
   const double* uw;        // [MAXG][3] wall velocity / c
   double* part;            // [ntiles][NPART] on diagnostic steps
   void* mac;               // [4][N] rho, U of the pre-step state (adjoint recompute), or null
+  float* sig;              // [NC][N] stress of the pre-step state (Eq. 8), FP32, or null
+  float* strain;           // [NC][N] strain rate (Eq. 9), FP32, or null
+  float st_c2, st_hdt;     // c^2 and 3 / (2 dt) of the stress and strain outputs
+  int st_artefact;         // include the artefact term E in them
   Geom geo;
   Phys p;
 };

@@ -111,6 +111,11 @@ struct lbm_ctx {
   int stokes = 0;
   double darcy = 0;
   int artefact = 0;
+  // stress and strain rate written by the steps themselves (borrowed device
+  // buffers [NC][N] FP32) every st_every steps, or none
+  float* st_sig = nullptr;
+  float* st_strain = nullptr;
+  int st_every = 0;
   bool mhd = false;
   bool lorentz = false;  // MHD coupling: Lorentz force through the force term
   double B0[3] = {0, 0, 0}, mu = 1, tau_m = 1;
@@ -710,6 +715,24 @@ int lbm_set_darcy(lbm_ctx* h, double sigma) {
   return LBM_OK;
 }
 
+int lbm_set_step_stress(lbm_ctx* h, void* sigma_dev, void* strain_dev, int every) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (!sigma_dev && !strain_dev) {
+    h->st_sig = h->st_strain = nullptr;
+    h->st_every = 0;
+    return LBM_OK;
+  }
+  if (every < 1) return fail(LBM_EINVAL, "every must be >= 1 (got %d)", every);
+  const size_t bytes = (size_t)h->NC * h->N * sizeof(float);
+  if (sigma_dev) HIPCHK(hipMemsetAsync(sigma_dev, 0, bytes, h->stream));
+  if (strain_dev) HIPCHK(hipMemsetAsync(strain_dev, 0, bytes, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->st_sig = (float*)sigma_dev;
+  h->st_strain = (float*)strain_dev;
+  h->st_every = every;
+  return LBM_OK;
+}
+
 int lbm_set_artefact(lbm_ctx* h, int on) {
   if (!h) return fail(LBM_EINVAL, "null context");
   h->artefact = on ? 1 : 0;
@@ -891,7 +914,13 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
   }
   const int par0 = h->parity;
   if (timing) HIPCHK(hipEventRecord(h->ev[0], h->stream));
+  a.st_c2 = (float)(h->c * h->c);
+  a.st_hdt = (float)(1.5 / h->dt);
+  a.st_artefact = h->artefact;
   for (int i = 0; i < n; ++i) {
+    const bool st = h->st_every > 0 && (h->steps + i) % h->st_every == 0;
+    a.sig = st ? h->st_sig : nullptr;
+    a.strain = st ? h->st_strain : nullptr;
     if (ckpt_every > 0 && i % ckpt_every == 0)
       HIPCHK(hipMemcpyAsync((char*)h->ckpt.p + (size_t)(i / ckpt_every) * sbytes, h->f.p, sbytes,
                             hipMemcpyDeviceToDevice, h->stream));

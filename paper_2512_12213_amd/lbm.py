@@ -41,6 +41,7 @@ _SIGS = [
     ("lbm_set_equilibrium", C.c_int, [_P, C.c_int]),
     ("lbm_set_darcy", C.c_int, [_P, C.c_double]),
     ("lbm_set_artefact", C.c_int, [_P, C.c_int]),
+    ("lbm_set_step_stress", C.c_int, [_P, C.c_void_p, C.c_void_p, C.c_int]),
     ("lbm_set_mhd", C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]),
     ("lbm_set_mhd_coupling", C.c_int, [_P, C.c_int]),
     ("lbm_set_stream", C.c_int, [_P, C.c_void_p]),
@@ -195,6 +196,12 @@ class Lattice:
 
     def set_artefact(self, on):
         _chk(self.L.lbm_set_artefact(self.h, int(on)))
+
+    def set_step_stress(self, sigma_ptr, strain_ptr, every=1):
+        """Device float buffers [ncomp, nz, ny, nx] (int addresses, or None)
+        that every `every`-th step fills with the stress and strain rate of
+        the state it starts from."""
+        _chk(self.L.lbm_set_step_stress(self.h, sigma_ptr, strain_ptr, every))
 
     def set_mhd(self, B0, mu, tau_m):
         _chk(self.L.lbm_set_mhd(self.h, B0[0], B0[1], B0[2], mu, tau_m))
