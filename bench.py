@@ -70,7 +70,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and workloads")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--only", choices=["adjoint", "hartmann", "halfstep", "sphere", "formats", "stress"], default=None,
+    ap.add_argument("--only", choices=["adjoint", "hartmann", "halfstep", "sphere", "formats", "stress", "history"],
+                    default=None,
                     help="run only this measurement (for profiling its kernels) and print its record")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run one 1 GiB device-to-device copy (a plain copy kernel of known size, "
@@ -104,12 +105,15 @@ def copy_ceiling(torch, nbytes, repeats=20):
     return 2 * n * 4 / t / 1e9
 
 
-def timed_run(lbm, torch, w, steps, warmup, storage=None, stress_every_step=False):
+def timed_run(lbm, torch, w, steps, warmup, storage=None, stress_every_step=False, wall_history=False):
     """Warm up, then time one lbm_step(steps) call; returns a result dict.
     stress_every_step: every step also stores the stress and strain rate of
     the state it starts from (lbm_set_step_stress, FP32, 2 x 4 x ncomp bytes
-    per node more)."""
+    per node more).  wall_history: every step also records its wall force
+    (lbm_set_wall_force_history)."""
     lat = lbm.from_workload(w, storage=storage)
+    if wall_history:
+        lat.set_wall_force_history(True)
     stream = torch.cuda.current_stream()
     lat.set_stream(stream.cuda_stream)
     nc = 3 if w.D == 2 else 6
@@ -129,6 +133,8 @@ def timed_run(lbm, torch, w, steps, warmup, storage=None, stress_every_step=Fals
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) * 1e-3
     tim = lat.step_timings()
+    if wall_history:
+        assert lat.wall_force_history().shape[0] == steps
     bal = lat.force_balance()
     fw = lat.wall_force()
     lat.close()
@@ -382,6 +388,12 @@ def main():
               "duct_les_f32": timed_run(lbm, torch, W.duct_les(), args.steps, args.warmup)}
         print(json.dumps(rs), flush=True)
         return
+    if args.only == "history":
+        rs = {"duct_les_f32_wall_force_every_step": timed_run(lbm, torch, W.duct_les(), args.steps, args.warmup,
+                                                               wall_history=True),
+              "duct_les_f32": timed_run(lbm, torch, W.duct_les(), args.steps, args.warmup)}
+        print(json.dumps(rs), flush=True)
+        return
     if args.only == "sphere":
         # the duct with a sphere, halfway and interpolated walls
         rs = {}
@@ -442,6 +454,9 @@ def main():
         print("bench: variant duct storing the stress and strain rate every step", file=sys.stderr, flush=True)
         variants["duct_les_f32_stress_every_step"] = timed_run(lbm, torch, w, half, min(args.warmup, 10),
                                                                stress_every_step=True)
+        print("bench: variant duct recording the wall force of every step", file=sys.stderr, flush=True)
+        variants["duct_les_f32_wall_force_every_step"] = timed_run(lbm, torch, w, half, min(args.warmup, 10),
+                                                                   wall_history=True)
         print("bench: variant duct without LES", file=sys.stderr, flush=True)
         wn = W.duct_les()
         wn.les_cs = 0.0

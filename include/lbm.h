@@ -265,6 +265,21 @@ int lbm_halfstep(lbm_ctx* ctx, double* fbar, double* rho_bar, double* u_bar, dou
  * LBM_ESTATE before the first step. */
 int lbm_wall_force(lbm_ctx* ctx, double* out);
 
+/* Per-step wall-force record (Eq. 25 for every step, not only the last):
+ * with on != 0, the steps of later lbm_step calls also sum the momentum
+ * exchange of their wall links (only the 256-node tiles that a wall group
+ * meets do any extra work), and lbm_wall_force_history returns, for each step
+ * of the most recent such call in order, the four variants of lbm_wall_force:
+ * out[n][G][4][3], G = lbm_num_groups, n = min(steps of that call,
+ * max_steps), written to *nsteps.  The last entry equals lbm_wall_force.
+ * Halfway walls only (LBM_EINVAL with lbm_set_link_fractions); not recorded by
+ * lbm_step_noalloc (LBM_EINVAL while on) or lbm_adjoint_forward.  Device
+ * buffers of about 64 bytes per such tile and recorded step are allocated on
+ * the first call.  LBM_ESTATE when no call has recorded it since the state
+ * was set. */
+int lbm_set_wall_force_history(lbm_ctx* ctx, int on);
+int lbm_wall_force_history(lbm_ctx* ctx, double* out, int max_steps, int* nsteps);
+
 /* Global balance of the last step (Eq. 32), out[24] doubles:
  *  0-2  F_wall raw (all groups)          3-5  sum rho a dx^D at t
  *  6-8  (P(t+dt) - P(t)) / dt, P = sum rho u dx^D

@@ -515,12 +515,18 @@ __device__ __forceinline__ void store_stress(const StepArgs& a, uint32_t n, cons
 // holds whole rows and x wraps inside a row, so every slot it loads or stores
 // still belongs to one of its own nodes.  Every thread of the tile takes this
 // path (the choice is per tile), so the two barriers are reached uniformly.
-// ST: the step also stores the stress and strain rate of the pre-step state.
-template <class L, int P, int MHD, int PAR, bool DIAG, bool MAC, bool BND, class AD, bool XS = false, bool ST = false>
+// DG: diagnostics of the step, 0 none, 1 the momentum exchange of the wall
+// links only, 2 that and the balance sums.  ST: the step also stores the
+// stress and strain rate of the pre-step state.
+// lds: the tile's shared buffer, for the x staging (XS) or, in tiles that a
+// wall group meets, the wall-link sums of each thread (DG): swall[j][tid],
+// j = slot NWALL + quantity, each thread adding only to its own column (no
+// barrier; quantity-major, so that a wavefront's accesses are conflict-free).
+template <class L, int P, int MHD, int PAR, int DG, bool MAC, bool BND, class AD, bool XS = false, bool ST = false>
 __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const AD& Af, const AD& Ag, const uint4& rec,
-                                            typename Stor<P>::T (&bal)[NBAL],
-                                            typename Stor<P>::T (&wacc)[MAXBG][NWALL], uint32_t bgrp,
-                                            uint32_t x = 0, const typename Stor<P>::T* uwl = nullptr) {
+                                            typename Stor<P>::T (&bal)[NBAL], typename Stor<P>::T* lds,
+                                            uint32_t bgrp, uint32_t x = 0,
+                                            const typename Stor<P>::T* uwl = nullptr) {
   using S = Stor<P>;
   using T = typename S::T;
   // 16-bit formats at interior nodes work in the stored units
@@ -533,9 +539,8 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
   [[maybe_unused]] uint32_t rb = 0;
   if constexpr (XS) {
     static_assert(PAR == 1 && !BND && MHD == 0, "x staging is for odd steps of interior tiles");
-    __shared__ T xs_in[NS][NTHREADS];
-    __shared__ T xs_outb[NS][NTHREADS];
-    xs_out = xs_outb;
+    T (*xs_in)[NTHREADS] = (T(*)[NTHREADS])lds;
+    xs_out = xs_in + NS;
     const uint32_t tid = threadIdx.x;
     rb = tid - x;  // first thread of this node's row in the tile
 #pragma unroll
@@ -588,7 +593,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
     mo[2 * (uint64_t)g.N + n] = m.U[1];
     mo[3 * (uint64_t)g.N + n] = m.U[2];
   }
-  if (DIAG) {
+  if (DG == 2) {
     bal[0] += m.drho;
     bal[1] += m.rho * m.U[0];
     bal[2] += m.rho * m.U[1];
@@ -609,15 +614,16 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
       const T ladd = T(-6) * (T)L::w(q) * m.rho * edot<L>(q, ux, uy, uz);
       const T out = v;
       v = out + ladd;
-      if (DIAG) {
+      if (DG) {
         const T cq = out + v;
+        T* sw = lds + threadIdx.x;
 #pragma unroll
         for (int s = 0; s < MAXBG; ++s) {
           if (((bgrp >> (4 * s)) & 15u) == gr) {
-            wacc[s][0] += (T)L::ex(q) * cq;
-            wacc[s][1] += (T)L::ey(q) * cq;
-            wacc[s][2] += (T)L::ez(q) * cq;
-            wacc[s][3] += ladd;
+            sw[(s * NWALL + 0) * NTHREADS] += (T)L::ex(q) * cq;
+            sw[(s * NWALL + 1) * NTHREADS] += (T)L::ey(q) * cq;
+            sw[(s * NWALL + 2) * NTHREADS] += (T)L::ez(q) * cq;
+            sw[(s * NWALL + 3) * NTHREADS] += ladd;
           }
         }
       }
@@ -684,7 +690,7 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles, uint32
 // RU: 0 generic addressing; 1 row-uniform pointers; 2 row-uniform pointers
 // for rows with boundary links and buffer resources for the other rows
 // (arrays below 4 GiB).
-template <class L, int P, int MHD, int PAR, bool DIAG, int RU, bool MAC = false, bool ST = false>
+template <class L, int P, int MHD, int PAR, int DG, int RU, bool MAC = false, bool ST = false>
 __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   using T = typename Stor<P>::T;
   const Geom& g = a.geo;
@@ -692,20 +698,26 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   const uint32_t n = tile * NTHREADS + threadIdx.x;
   const bool active = n < g.N;
   T bal[NBAL];
-  T wacc[MAXBG][NWALL];
-  if (DIAG) {
+  if (DG == 2) {
 #pragma unroll
     for (int k = 0; k < NBAL; ++k) bal[k] = T(0);
-#pragma unroll
-    for (int s = 0; s < MAXBG; ++s)
-#pragma unroll
-      for (int k = 0; k < NWALL; ++k) wacc[s][k] = T(0);
   }
   // LDS x-staging on odd steps: FP32 (odd step -5 %) and FP64 (odd step
   // -7 %, 40 KB of LDS per tile); the 2-byte formats and the diagnostic
   // variant (register pressure) measured slower with it
-  constexpr bool XS_OK = RU == 2 && MHD == 0 && PAR == 1 && !MAC && !DIAG && (P == S_F32 || P == S_F64);
+  constexpr bool XS_OK = RU == 2 && MHD == 0 && PAR == 1 && !MAC && DG != 2 && (P == S_F32 || P == S_F64);
   const uint32_t bgrp = a.blkgrp[tile];
+  // one shared buffer: the x staging of interior tiles, or the per-thread
+  // wall-link sums of tiles that a wall group meets (never both in a tile)
+  constexpr int NXS = xshift_count<L>();
+  constexpr uint32_t LDS_XS = XS_OK ? 2 * NXS * NTHREADS : 0;
+  constexpr uint32_t LDS_W = DG ? MAXBG * NWALL * NTHREADS : 0;
+  constexpr uint32_t LDS_N = LDS_XS > LDS_W ? LDS_XS : (LDS_W > 0 ? LDS_W : 1);
+  __shared__ T lds[LDS_N];
+  if (DG && (bgrp >> 28)) {
+#pragma unroll
+    for (int j = 0; j < MAXBG * NWALL; ++j) lds[j * NTHREADS + threadIdx.x] = T(0);
+  }
   // Tiles that a wall group meets (uniform per tile) put the wall velocities
   // in LDS: each wall link reads its group's velocity behind its own branch,
   // and from memory those reads would wait one link after the other.
@@ -734,39 +746,45 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
         if constexpr (XS_OK) {
           if ((bgrp >> 27) & 1u) {
             // tile of whole rows without boundary links (uniform per tile)
-            node_update<L, P, MHD, PAR, DIAG, MAC, false, AddrB, true, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp, x);
+            node_update<L, P, MHD, PAR, DG, MAC, false, AddrB, true, ST>(a, n, Af, Ag, rec, bal, lds, bgrp, x);
           } else {
-            node_update<L, P, MHD, PAR, DIAG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+            node_update<L, P, MHD, PAR, DG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, lds, bgrp);
           }
         } else {
-          node_update<L, P, MHD, PAR, DIAG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          node_update<L, P, MHD, PAR, DG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, lds, bgrp);
         }
       } else if (RU) {
         const AddrR Af = addr_r(g, x, y, z, L::Q);
         const AddrR Ag = addr_r(g, x, y, z, MHD ? Ind<L>::K * Ind<L>::NB : L::Q);
         if (rr < 0)
-          node_update<L, P, MHD, PAR, DIAG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          node_update<L, P, MHD, PAR, DG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, lds, bgrp);
         else
-          node_update<L, P, MHD, PAR, DIAG, MAC, true, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp, 0u, suw);
+          node_update<L, P, MHD, PAR, DG, MAC, true, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, lds, bgrp, 0u, suw);
       } else {
         const AddrG Af = addr_g(g, x, y, z, r, L::Q);
         const AddrG Ag = addr_g(g, x, y, z, r, MHD ? Ind<L>::K * Ind<L>::NB : L::Q);
         if (rr < 0)
-          node_update<L, P, MHD, PAR, DIAG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp);
+          node_update<L, P, MHD, PAR, DG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, lds, bgrp);
         else
-          node_update<L, P, MHD, PAR, DIAG, MAC, true, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, wacc, bgrp, 0u, suw);
+          node_update<L, P, MHD, PAR, DG, MAC, true, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, lds, bgrp, 0u, suw);
       }
     }
   }
-  if (DIAG) {
+  if (DG == 1 && (bgrp >> 28)) {
+    // wall-link sums of this tile into the step's slot of the per-step ring
+    // (compact tile index, quantity-major)
+    double v[MAXBG * NWALL];
+#pragma unroll
+    for (int j = 0; j < MAXBG * NWALL; ++j) v[j] = (double)lds[j * NTHREADS + threadIdx.x];
+    tile_sum_store<MAXBG * NWALL>(v, a.hist + a.wtile[tile], a.nwt);
+  }
+  if (DG == 2) {
     if (bgrp >> 28) {
       double v[NPART];
 #pragma unroll
       for (int k = 0; k < NBAL; ++k) v[k] = (double)bal[k];
 #pragma unroll
-      for (int s = 0; s < MAXBG; ++s)
-#pragma unroll
-        for (int k = 0; k < NWALL; ++k) v[NBAL + s * NWALL + k] = (double)wacc[s][k];
+      for (int j = 0; j < MAXBG * NWALL; ++j) v[NBAL + j] = (double)lds[j * NTHREADS + threadIdx.x];
       tile_sum_store<NPART>(v, a.part + tile, gridDim.x);
     } else {
       // no wall group meets this tile (uniform per tile): its wall slots are
@@ -1336,36 +1354,63 @@ __global__ __launch_bounds__(NTHREADS) void k_reduce(const double* __restrict__ 
   tile_sum_store<1>(v, out + o);
 }
 
+// Per-step wall-force record: ring [steps][MAXBG NWALL][nwt] of compact-tile
+// partial sums (nwt tiles that a wall group meets) -> out[step][MAXG NWALL]
+// (group-major, the layout of the step record's wall part).  Block (step s,
+// quantity o = g NWALL + k) sums the tiles of group g from the compact list
+// wlc (entries wlc[wlc[g]] ... wlc[wlc[g + 1] - 1]: compact tile index in
+// bits 0-27, the group's slot in that tile in bits 28-31), in list order:
+// deterministic.  Groups not in use give 0.
+__global__ __launch_bounds__(NTHREADS) void k_hist_reduce(const double* __restrict__ ring,
+                                                          const uint32_t* __restrict__ wlc, uint32_t nwt, int G,
+                                                          double* __restrict__ out) {
+  const uint32_t s = blockIdx.x, o = blockIdx.y;
+  const uint32_t grp = o / NWALL, k = o % NWALL;
+  double acc = 0.0;
+  if ((int)grp < G) {
+    const double* r = ring + (uint64_t)s * MAXBG * NWALL * nwt;
+    for (uint32_t i = wlc[grp] + threadIdx.x; i < wlc[grp + 1]; i += NTHREADS) {
+      const uint32_t en = wlc[i];
+      acc += r[(uint64_t)((en >> 28) * NWALL + k) * nwt + (en & 0x0FFFFFFFu)];
+    }
+  }
+  double v[1] = {acc};
+  tile_sum_store<1>(v, out + (uint64_t)s * MAXG * NWALL + o);
+}
+
 // ---------------------------------------------------------------------------
 // launchers (called by the host library)
 // ---------------------------------------------------------------------------
+template <class L, int P, int MHD, int PAR, int RU, bool ST>
+static void launch_step_dg(const StepArgs& a, int dg, uint32_t nb, hipStream_t st) {
+  if (dg == 2)
+    k_step<L, P, MHD, PAR, 2, RU, false, ST><<<nb, NTHREADS, 0, st>>>(a);
+  else if (dg == 1)
+    k_step<L, P, MHD, PAR, 1, RU, false, ST><<<nb, NTHREADS, 0, st>>>(a);
+  else
+    k_step<L, P, MHD, PAR, 0, RU, false, ST><<<nb, NTHREADS, 0, st>>>(a);
+}
+
 template <class L, int P, int MHD, int RU, bool ST>
-static void launch_step_ru_st(const StepArgs& a, int parity, bool diag, uint32_t nb, hipStream_t st) {
-  if (parity == 0) {
-    if (diag)
-      k_step<L, P, MHD, 0, true, RU, false, ST><<<nb, NTHREADS, 0, st>>>(a);
-    else
-      k_step<L, P, MHD, 0, false, RU, false, ST><<<nb, NTHREADS, 0, st>>>(a);
-  } else {
-    if (diag)
-      k_step<L, P, MHD, 1, true, RU, false, ST><<<nb, NTHREADS, 0, st>>>(a);
-    else
-      k_step<L, P, MHD, 1, false, RU, false, ST><<<nb, NTHREADS, 0, st>>>(a);
-  }
+static void launch_step_ru_st(const StepArgs& a, int parity, int dg, uint32_t nb, hipStream_t st) {
+  if (parity == 0)
+    launch_step_dg<L, P, MHD, 0, RU, ST>(a, dg, nb, st);
+  else
+    launch_step_dg<L, P, MHD, 1, RU, ST>(a, dg, nb, st);
 }
 
 // Steps that store the stress and strain rate (a.sig or a.strain set) run
 // their own instantiation, so that the other steps keep their registers.
 template <class L, int P, int MHD, int RU>
-static void launch_step_ru(const StepArgs& a, int parity, bool diag, uint32_t nb, hipStream_t st) {
+static void launch_step_ru(const StepArgs& a, int parity, int dg, uint32_t nb, hipStream_t st) {
   if (a.sig || a.strain)
-    launch_step_ru_st<L, P, MHD, RU, true>(a, parity, diag, nb, st);
+    launch_step_ru_st<L, P, MHD, RU, true>(a, parity, dg, nb, st);
   else
-    launch_step_ru_st<L, P, MHD, RU, false>(a, parity, diag, nb, st);
+    launch_step_ru_st<L, P, MHD, RU, false>(a, parity, dg, nb, st);
 }
 
 template <class L, int P, int MHD>
-static hipError_t launch_step_t(const StepArgs& a, int parity, bool diag, hipStream_t st) {
+static hipError_t launch_step_t(const StepArgs& a, int parity, int dg, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
   using E = typename Stor<P>::E;
   const uint64_t fb = (uint64_t)a.geo.N * L::Q * sizeof(E);
@@ -1373,11 +1418,11 @@ static hipError_t launch_step_t(const StepArgs& a, int parity, bool diag, hipStr
   // buffer form (measured: FP32 -1 %, FP16 and BF16 -6 to -8 %; FP64 +2 %
   // alone, but it carries the LDS staging of odd steps, and with it -4 %)
   if (a.geo.nx % 64 == 0 && fb < (1ull << 32) && gb < (1ull << 32))
-    launch_step_ru<L, P, MHD, 2>(a, parity, diag, nb, st);
+    launch_step_ru<L, P, MHD, 2>(a, parity, dg, nb, st);
   else if (a.geo.nx % 64 == 0)
-    launch_step_ru<L, P, MHD, 1>(a, parity, diag, nb, st);
+    launch_step_ru<L, P, MHD, 1>(a, parity, dg, nb, st);
   else
-    launch_step_ru<L, P, MHD, 0>(a, parity, diag, nb, st);
+    launch_step_ru<L, P, MHD, 0>(a, parity, dg, nb, st);
   return hipGetLastError();
 }
 
@@ -1390,15 +1435,15 @@ static hipError_t launch_step_mac_t(const StepArgs& a, int parity, bool diag, hi
 #define LBM_MAC(PAR, DG, RU) k_step<L, P, 0, PAR, DG, RU, true><<<nb, NTHREADS, 0, st>>>(a)
   if (ru) {
     if (parity == 0) {
-      if (diag) LBM_MAC(0, true, true); else LBM_MAC(0, false, true);
+      if (diag) LBM_MAC(0, 2, 1); else LBM_MAC(0, 0, 1);
     } else {
-      if (diag) LBM_MAC(1, true, true); else LBM_MAC(1, false, true);
+      if (diag) LBM_MAC(1, 2, 1); else LBM_MAC(1, 0, 1);
     }
   } else {
     if (parity == 0) {
-      if (diag) LBM_MAC(0, true, false); else LBM_MAC(0, false, false);
+      if (diag) LBM_MAC(0, 2, 0); else LBM_MAC(0, 0, 0);
     } else {
-      if (diag) LBM_MAC(1, true, false); else LBM_MAC(1, false, false);
+      if (diag) LBM_MAC(1, 2, 0); else LBM_MAC(1, 0, 0);
     }
   }
 #undef LBM_MAC
@@ -1472,8 +1517,10 @@ static hipError_t launch_init_t(const InitArgs& a, hipStream_t st) {
     }                                                                                        \
   } while (0)
 
-hipError_t launch_step(int lattice, int prec, int mhd, const StepArgs& a, int parity, bool diag, hipStream_t st) {
-  LBM_DISPATCH(launch_step_t, lattice, prec, mhd, a, parity, diag, st);
+// dg: 0 no diagnostics, 1 the wall links' momentum exchange into the
+// per-step ring (a.hist), 2 all diagnostics of the last step of a call.
+hipError_t launch_step(int lattice, int prec, int mhd, const StepArgs& a, int parity, int dg, hipStream_t st) {
+  LBM_DISPATCH(launch_step_t, lattice, prec, mhd, a, parity, dg, st);
 }
 
 hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, bool diag, hipStream_t st) {
@@ -1512,6 +1559,13 @@ hipError_t launch_ibb_reduce(int lattice, const double* delta, const uint8_t* gr
 
 hipError_t launch_init(int lattice, int prec, int mhd, const InitArgs& a, hipStream_t st) {
   LBM_DISPATCH(launch_init_t, lattice, prec, mhd, a, st);
+}
+
+hipError_t launch_hist_reduce(const double* ring, const uint32_t* wlc, uint32_t nwt, int G, uint32_t nsteps,
+                              double* out, hipStream_t st) {
+  if (nsteps == 0) return hipSuccess;
+  k_hist_reduce<<<dim3(nsteps, MAXG * NWALL), NTHREADS, 0, st>>>(ring, wlc, nwt, G, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double* part, const uint32_t* wlist, uint32_t ntiles, int mode, int G, int nout, double* out,

@@ -59,6 +59,9 @@ struct StepArgs {
   float* strain;           // [NC][N] strain rate (Eq. 9), FP32, or null
   float st_c2, st_hdt;     // c^2 and 3 / (2 dt) of the stress and strain outputs
   int st_artefact;         // include the artefact term E in them
+  double* hist;            // per-step ring slot [MAXBG NWALL][nwt] of the wall-link sums (diagnostics mode 1)
+  const int* wtile;        // per tile: compact index among the tiles a wall group meets, or -1
+  uint32_t nwt;            // number of such tiles
   Geom geo;
   Phys p;
 };

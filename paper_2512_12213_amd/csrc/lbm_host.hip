@@ -16,7 +16,9 @@
 #include "lattice.hpp"
 
 namespace lbm {
-hipError_t launch_step(int lattice, int prec, int mhd, const StepArgs& a, int parity, bool diag, hipStream_t st);
+hipError_t launch_step(int lattice, int prec, int mhd, const StepArgs& a, int parity, int dg, hipStream_t st);
+hipError_t launch_hist_reduce(const double* ring, const uint32_t* wlc, uint32_t nwt, int G, uint32_t nsteps,
+                              double* out, hipStream_t st);
 hipError_t launch_diag(int lattice, int prec, int mhd, const DiagArgs& a, hipStream_t st);
 hipError_t launch_init(int lattice, int prec, int mhd, const InitArgs& a, hipStream_t st);
 hipError_t launch_reduce(const double* part, const uint32_t* wlist, uint32_t ntiles, int mode, int G, int nout, double* out,
@@ -130,6 +132,15 @@ struct lbm_ctx {
   std::vector<long> nlink;  // [MAXG][Q]
 
   DevBuf f, g, rec, rowrec, blkgrp, wlist, uwdev, part, red, dpart, dred, tmp;
+  // per-step wall-force record: the tiles a wall group meets get a compact
+  // index (wtile, -1 elsewhere; nwt of them) and per group a compact tile
+  // list (wlc, the layout of wlist); steps other than a call's last sum their
+  // wall links into a ring of hist_ring_steps slots, reduced into hist_out
+  bool hist_on = false;
+  uint32_t nwt = 0;
+  DevBuf wtile, wlc, hist_ring, hist_out;
+  std::vector<double> hist;  // [steps of the last call][MAXG NWALL]
+  long hist_steps = 0;
   // walls that are not halfway: link fractions (host, [Q][N]) and the list of
   // nodes whose links are interpolated after each step
   std::vector<double> qlink;
@@ -370,6 +381,21 @@ int build_geometry(lbm_ctx* h) {
     }
   }
   wlist[MAXG] = (uint32_t)wlist.size();
+  // compact indices of the tiles a wall group meets, and the same per-group
+  // lists with those indices
+  std::vector<int> wtile(h->ntiles, -1);
+  uint32_t nwt = 0;
+  for (uint32_t t = 0; t < h->ntiles; ++t)
+    if (tilegrp[t] >> 28) wtile[t] = (int)nwt++;
+  std::vector<uint32_t> wlc(wlist.size());
+  for (int gr = 0; gr <= MAXG; ++gr) wlc[gr] = wlist[gr];
+  for (size_t i = MAXG + 1; i < wlist.size(); ++i)
+    wlc[i] = (uint32_t)wtile[wlist[i] & 0x0FFFFFFFu] | (wlist[i] & 0xF0000000u);
+  h->nwt = nwt;
+  HIPCHK(h->wtile.ensure(wtile.size() * sizeof(int)));
+  HIPCHK(hipMemcpy(h->wtile.p, wtile.data(), wtile.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(h->wlc.ensure(wlc.size() * sizeof(uint32_t)));
+  HIPCHK(hipMemcpy(h->wlc.p, wlc.data(), wlc.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
   HIPCHK(h->wlist.ensure(wlist.size() * sizeof(uint32_t)));
   HIPCHK(hipMemcpy(h->wlist.p, wlist.data(), wlist.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
   HIPCHK(h->rowrec.ensure(rows * sizeof(int)));
@@ -797,6 +823,7 @@ int lbm_init_equilibrium(lbm_ctx* h, const double* u0) {
   h->steps = 0;
   h->parity = 0;
   h->have_step = false;
+  h->hist_steps = 0;
   return LBM_OK;
 }
 
@@ -825,6 +852,7 @@ int lbm_set_state(lbm_ctx* h, const double* d) {
   h->steps = 0;
   h->parity = 0;
   h->have_step = false;
+  h->hist_steps = 0;
   return LBM_OK;
 }
 
@@ -882,14 +910,27 @@ static int upload_uw(lbm_ctx* h) {
 // i % ckpt_every == 0; with a tape, every step also records rho and U of its
 // pre-step state at tape + i * 4 N values.  sc: the scratch buffers of the
 // step (the context's own when null); timing events are recorded only with
-// the context's own buffers (creating events may allocate).
-static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, const Scratch* scp = nullptr) {
+// the context's own buffers (creating events may allocate).  With hist, the
+// steps before the last also record the momentum exchange of the wall links
+// (reduced in chunks of the ring's size into hist_out).
+constexpr int HIST_RING = 256;  // steps per ring (one reduction per chunk)
+static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, const Scratch* scp = nullptr,
+                     bool hist = false) {
   int rc = upload_uw(h);
   if (rc) return rc;
   const Scratch sc = scp ? *scp : own_scratch(h);
   const bool timing = h->timing && !scp;
   StepArgs a = step_args(h);
   a.part = sc.part;
+  a.wtile = (const int*)h->wtile.p;
+  a.nwt = h->nwt;
+  const size_t slot = (size_t)MAXBG * NWALL * std::max<uint32_t>(h->nwt, 1);  // doubles per ring slot
+  const int ring = std::min(HIST_RING, std::max(n - 1, 1));
+  if (hist) {
+    HIPCHK(h->hist_ring.ensure((size_t)ring * slot * sizeof(double)));
+    HIPCHK(h->hist_out.ensure((size_t)std::max(n - 1, 1) * MAXG * NWALL * sizeof(double)));
+  }
+  int chunk0 = 0;  // first step of the ring's current chunk
   const size_t mbytes = (size_t)4 * h->N * elem_bytes(h->prec);
   IbbArgs ib = {};
   if (h->nibb) {
@@ -929,7 +970,15 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
       a.mac = (char*)tape + (size_t)i * mbytes;
       HIPCHK(launch_step_mac(h->lattice, h->prec, a, h->parity, diag, h->stream));
     } else {
-      HIPCHK(launch_step(h->lattice, h->prec, mhd_mode(h), a, h->parity, diag, h->stream));
+      const int dg = diag ? 2 : (hist ? 1 : 0);
+      a.hist = dg == 1 ? (double*)h->hist_ring.p + (size_t)(i - chunk0) * slot : nullptr;
+      HIPCHK(launch_step(h->lattice, h->prec, mhd_mode(h), a, h->parity, dg, h->stream));
+      if (hist && !diag && (i - chunk0 + 1 == ring || i == n - 2)) {
+        HIPCHK(launch_hist_reduce((const double*)h->hist_ring.p, (const uint32_t*)h->wlc.p, h->nwt, h->G,
+                                  (uint32_t)(i - chunk0 + 1),
+                                  (double*)h->hist_out.p + (size_t)chunk0 * MAXG * NWALL, h->stream));
+        chunk0 = i + 1;
+      }
     }
     if (h->nibb) {
       ib.parity = h->parity ^ 1;
@@ -979,6 +1028,18 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
   // interpolated links: the returning values changed after the step's own sums
   for (int gr = 0; h->nibb && gr < h->G; ++gr)
     for (int k = 0; k < NWALL; ++k) h->last[NBAL + gr * NWALL + k] += ibb_host[gr * 4 + k];
+  if (hist) {
+    // the steps before the last from the ring's reductions, the last from the
+    // call's own record
+    h->hist.assign((size_t)n * MAXG * NWALL, 0.0);
+    if (n > 1)
+      HIPCHK(hipMemcpy(h->hist.data(), h->hist_out.p, (size_t)(n - 1) * MAXG * NWALL * sizeof(double),
+                       hipMemcpyDeviceToHost));
+    std::memcpy(h->hist.data() + (size_t)(n - 1) * MAXG * NWALL, h->last + NBAL, MAXG * NWALL * sizeof(double));
+    h->hist_steps = n;
+  } else {
+    h->hist_steps = 0;
+  }
   std::memcpy(h->last_uw, h->uw, sizeof(h->last_uw));
   h->steps += n;
   h->have_step = true;
@@ -992,7 +1053,7 @@ int lbm_step(lbm_ctx* h, int n) {
   if (n < 0) return fail(LBM_EINVAL, "negative step count");
   if (n == 0) return LBM_OK;
   h->tape = false;
-  return step_loop(h, n, 0);
+  return step_loop(h, n, 0, nullptr, nullptr, h->hist_on);
 }
 
 int lbm_step_noalloc(lbm_ctx* h, int n) {
@@ -1000,6 +1061,7 @@ int lbm_step_noalloc(lbm_ctx* h, int n) {
   if (rc) return rc;
   if (n < 0) return fail(LBM_EINVAL, "negative step count");
   if (!h->scratch) return fail(LBM_EHIP, "the fixed scratch array of this device could not be located");
+  if (h->hist_on) return fail(LBM_EINVAL, "lbm_step_noalloc does not record the per-step wall-force history");
   size_t need = 0;
   const Scratch sc = fixed_scratch(h, &need);
   if (need > (size_t)LBM_SCRATCH_BYTES)
@@ -1098,9 +1160,9 @@ int lbm_halfstep(lbm_ctx* h, double* fbar, double* rho_bar, double* u_bar, doubl
 
 // Wall-force variants per group from the last step's FP64 sums plus the
 // constant per-link parts (rest-state pressure, Maxwell stress at B0).
-static void wall_variants(const lbm_ctx* h, int gr, double out[4][3]) {
+static void wall_variants(const lbm_ctx* h, int gr, double out[4][3], const double* sums = nullptr) {
   const double fscale = vol(h) * h->c / h->dt;  // (dx^D / dt) c
-  const double* s = h->last + NBAL + gr * NWALL;
+  const double* s = (sums ? sums : h->last + NBAL) + gr * NWALL;
   double raw[3], mf[3], mx[3] = {0, 0, 0};
   double stat[3] = {0, 0, 0};
   const double b = h->mhd ? 1.0 / (h->c * std::sqrt(h->mu)) : 0.0;
@@ -1150,6 +1212,35 @@ int lbm_wall_force(lbm_ctx* h, double* out) {
     for (int var = 0; var < 4; ++var)
       for (int k = 0; k < 3; ++k) out[(gr * 4 + var) * 3 + k] = v[var][k];
   }
+  return LBM_OK;
+}
+
+int lbm_set_wall_force_history(lbm_ctx* h, int on) {
+  if (!h) return fail(LBM_EINVAL, "null context");
+  if (on && !h->geom_ok) {
+    int rc = build_geometry(h);
+    if (rc) return rc;
+  }
+  if (on && h->nibb) return fail(LBM_EINVAL, "the per-step wall-force history covers halfway walls only");
+  h->hist_on = on != 0;
+  return LBM_OK;
+}
+
+int lbm_wall_force_history(lbm_ctx* h, double* out, int max_steps, int* nsteps) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!out || !nsteps) return fail(LBM_EINVAL, "null buffer");
+  if (max_steps < 0) return fail(LBM_EINVAL, "negative max_steps");
+  if (!h->have_step || !h->hist_steps) return fail(LBM_ESTATE, "no call with the history on since the state was set");
+  const int n = (int)std::min<long>(h->hist_steps, max_steps);
+  for (int st = 0; st < n; ++st)
+    for (int gr = 0; gr < h->G; ++gr) {
+      double v[4][3];
+      wall_variants(h, gr, v, h->hist.data() + (size_t)st * MAXG * NWALL);
+      for (int var = 0; var < 4; ++var)
+        for (int k = 0; k < 3; ++k) out[(((size_t)st * h->G + gr) * 4 + var) * 3 + k] = v[var][k];
+    }
+  *nsteps = n;
   return LBM_OK;
 }
 

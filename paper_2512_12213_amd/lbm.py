@@ -57,6 +57,8 @@ _SIGS = [
     ("lbm_halfstep", C.c_int, [_P, _D, _D, _D, _D]),
     ("lbm_wall_force", C.c_int, [_P, _D]),
     ("lbm_force_balance", C.c_int, [_P, _D]),
+    ("lbm_set_wall_force_history", C.c_int, [_P, C.c_int]),
+    ("lbm_wall_force_history", C.c_int, [_P, _D, C.c_int, C.POINTER(C.c_int)]),
     ("lbm_num_groups", C.c_int, [_P]),
     ("lbm_link_count", C.c_long, [_P, C.c_int]),
     ("lbm_steps_taken", C.c_long, [_P]),
@@ -280,6 +282,18 @@ class Lattice:
         out = np.empty((G, 4, 3))
         _chk(self.L.lbm_wall_force(self.h, _dp(out)))
         return out
+
+    def set_wall_force_history(self, on=True):
+        _chk(self.L.lbm_set_wall_force_history(self.h, int(on)))
+
+    def wall_force_history(self, max_steps=1 << 20):
+        """[n, G, 4, 3]: the wall-force variants of every step of the last call."""
+        G = self.num_groups()
+        nmax = min(max_steps, int(self.steps_taken()))
+        out = np.empty((max(nmax, 1), G, 4, 3))
+        n = C.c_int(0)
+        _chk(self.L.lbm_wall_force_history(self.h, _dp(out), nmax, C.byref(n)))
+        return out[:n.value]
 
     def force_balance(self):
         out = np.empty(LBM_NREC)

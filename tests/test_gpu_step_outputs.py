@@ -158,3 +158,103 @@ def test_step_stress_argument_checks(env):
     g.set_step_stress(None, None, 0)  # off
     g.step(2)
     g.close()
+
+
+# ---------------------------------------------------------------------------
+# Per-step wall-force record (Eq. 25 for every step of a call)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+@pytest.mark.parametrize("lattice", [W.D2Q9, W.D3Q19])
+def test_wall_force_history_matches_oracle(env, lattice, storage):
+    """A 7-step call with the history on, from a seeded state with a wall
+    moving along its normal and tangentially (all four variants nonzero or
+    exactly zero as in the oracle), a static wall group, a solid body and
+    non-unity dx, dt: every step's record against the oracle's record of
+    that step; FP64 1e-12, FP32 1e-4 (2-norm per group and variant)."""
+    L, torch = env
+    if lattice == W.D2Q9:
+        nx, ny, nz = 40, 17, 1
+        mask = W.cylinder_mask(nx, ny, 14.2, 8.3, 3.1)
+        walls = ((1, 0, 1),)
+    else:
+        nx, ny, nz = 24, 13, 11
+        mask = W.sphere_mask(nx, ny, nz, 9.4, 6.2, 5.1, 2.6)
+        walls = ((1, 0, 1), (2, 2, 3))
+    c = 0.5 / 0.2
+    w = W.Workload("history", lattice, nx, ny, nz, 0.66, dx=0.5, dt=0.2, model=W.GUO, storage=storage,
+                   body_force=(0.05, -0.02, 0.03), walls=walls,
+                   wall_velocity=((1, 0.03 * c, 0.02 * c, 0.01 * c),), groups=5)
+    Q = w.Q
+    say("case wall-force history", lattice, storage)
+    d0 = W.random_state(Q, nx, ny, nz, 2e-3, seed=51) * (1 - mask[None])
+    g = L.from_workload(w, init=False)
+    g.add_solid_mask(mask, 4)
+    g.set_wall_force_history(True)
+    g.set_state(d0)
+    o = make_oracle(w, init=False)
+    o.set_solid(mask, 4)
+    o.groups = 5
+    o.set_state(quantize_state(d0, storage))
+    g.step(7)
+    hist = g.wall_force_history()
+    assert hist.shape == (7, 5, 4, 3)
+    assert np.array_equal(hist[-1], g.wall_force())
+    tol = 1e-12 if storage == W.F64 else 1e-4
+    worst = 0.0
+    for s in range(7):
+        o.step(1)
+        fo = o.wall_force(5)
+        for k in range(5):
+            for var in range(4):
+                ref = np.linalg.norm(fo[k, var])
+                if ref > 0:
+                    worst = max(worst, np.linalg.norm(hist[s, k, var] - fo[k, var]) / ref)
+                else:
+                    assert np.abs(hist[s, k, var]).max() == 0.0
+    say("  worst relative error over 7 steps: %.2e" % worst)
+    assert worst <= tol
+    # the normal motion gives a momentum-flux correction
+    assert np.abs(hist[:, 1, 1] - hist[:, 1, 0]).max() > 0
+
+
+def test_wall_force_history_of_a_long_call_equals_one_step_calls(env):
+    """A 300-step call (two chunks of the 256-step ring) against 300
+    one-step calls of the same deterministic steps: the same states, records
+    summed in another order (FP64 sums, 1e-12 relative)."""
+    L, torch = env
+    w = W.couette_cylinder(nx=128, ny=32, r=5.0, cx=40.0, cy=16.0, steps=0)
+    say("case history 300 steps")
+    a = L.from_workload(w)
+    a.set_wall_force_history(True)
+    a.step(300)
+    hist = a.wall_force_history()
+    assert hist.shape[0] == 300
+    b = L.from_workload(w)
+    worst = 0.0
+    for s in range(300):
+        b.step(1)
+        fb = b.wall_force()
+        worst = max(worst, float(np.abs(hist[s] - fb).max() / np.abs(fb).max()))
+    say("  worst %.2e" % worst)
+    assert worst <= 1e-12
+    assert np.array_equal(a.get_state(), b.get_state())
+    # the history also caps at max_steps and refuses lbm_step_noalloc
+    assert a.wall_force_history(max_steps=5).shape[0] == 5
+    with pytest.raises(L.LBMError) as ei:
+        a.step_noalloc(1)
+    assert ei.value.code == L.LBM_EINVAL
+    a.set_wall_force_history(False)
+    a.step_noalloc(1)
+
+
+def test_wall_force_history_refuses_walls_that_are_not_halfway(env):
+    L, torch = env
+    w = W.duct_sphere(nx=32, ny=16, nz=16, r=3.0, steps=0)
+    w.curved = True
+    g = L.from_workload(w)
+    with pytest.raises(L.LBMError) as ei:
+        g.set_wall_force_history(True)
+    assert ei.value.code == L.LBM_EINVAL
+    with pytest.raises(L.LBMError) as ei:
+        g.wall_force_history()
+    assert ei.value.code == L.LBM_ESTATE
