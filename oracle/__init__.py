@@ -15,6 +15,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+# the sanitizer builds of oracle/build.py are loaded from another folder
+LIBDIR = os.environ.get("ORACLE_LIB_DIR", HERE)
 
 D2Q9, D3Q19 = 0, 1
 HE, LUO, SHANCHEN, EDM, GUO, SHANCHEN_ORIG, EDM_ORIG = range(7)
@@ -25,7 +27,7 @@ _libs = {}
 def _lib(complex_step: bool):
     name = "liboracle_cs.so" if complex_step else "liboracle.so"
     if name not in _libs:
-        path = os.path.join(HERE, name)
+        path = os.path.join(LIBDIR, name)
         if not os.path.exists(path):
             from . import build as _b
             _b.build()

@@ -1,4 +1,12 @@
-"""Build the HIP library ``liblbm.so`` in-tree for gfx950 with hipcc."""
+"""Build the HIP library ``liblbm.so`` in-tree for gfx950 with hipcc.
+
+``build()`` keeps its object files in ``_build/``.  ``build_host_sanitized``
+links another copy of the library whose host code in ``lbm_host.hip`` (the
+C ABI and its argument checks) carries AddressSanitizer and
+UndefinedBehaviorSanitizer; the kernel objects are those of ``build()``.
+That copy loads only in a process with clang's ASan runtime preloaded
+(``asan_runtime()``), through ``LBM_LIBRARY``.
+"""
 import os
 import subprocess
 import sys
@@ -6,6 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
+OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["kernels.hip", "adjoint.hip", "lbm_host.hip"]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 
@@ -29,8 +38,9 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
     procs = []
+    os.makedirs(OBJDIR, exist_ok=True)
     for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
+        obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -49,9 +59,46 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
-    for o in objs:
-        os.remove(o)
     return LIB
+
+
+# host code only: -Xarch_host keeps the sanitizers out of the device code
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
+                 "-Xarch_host", "-g"]
+
+
+def _objects_current() -> bool:
+    inputs = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + [os.path.abspath(__file__)]
+    newest = max(os.path.getmtime(f) for f in inputs)
+    objs = [os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    return all(os.path.exists(o) and os.path.getmtime(o) >= newest for o in objs)
+
+
+def build_host_sanitized(outdir: str, verbose: bool = False) -> str:
+    """Write ``outdir/liblbm.so`` with the sanitized host code (builds the
+    kernel objects first when they are missing or older than a source)."""
+    if not _objects_current():
+        build(verbose)
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    obj = os.path.join(outdir, "lbm_host_san.o")
+    cmd = [hipcc, *HIPCC_FLAGS, *SANITIZE_HOST, "-c", os.path.join(CSRC, "lbm_host.hip"), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True, stderr=subprocess.DEVNULL if not verbose else None)
+    out = os.path.join(outdir, "liblbm.so")
+    objs = [os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o") for s in SOURCES if s != "lbm_host.hip"]
+    subprocess.run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", out, *objs, obj], check=True)
+    return out
+
+
+def asan_runtime() -> str:
+    """Path of the ASan runtime of hipcc's compiler."""
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise FileNotFoundError("no libclang_rt.asan-x86_64.so under /opt/rocm/llvm")
+    return hits[-1]
 
 
 if __name__ == "__main__":

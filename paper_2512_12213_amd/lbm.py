@@ -11,7 +11,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm.so")
+# LBM_LIBRARY names another build of the same library (the host-sanitizer
+# build of build.py); by default the in-tree one
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(HERE, "liblbm.so")
 
 LBM_D2Q9, LBM_D3Q19 = 0, 1
 LBM_FORCE_HE, LBM_FORCE_LUO, LBM_FORCE_SHANCHEN, LBM_FORCE_EDM, LBM_FORCE_GUO = range(5)
