@@ -99,8 +99,11 @@ int lbm_add_solid_mask(lbm_ctx* ctx, const unsigned char* mask_host, int group);
  * Firdaouss and Lallemand 2001) in a pass after each step, with the
  * moving-wall term: q < 1/2: 2q f_rel_a(x) + (1 - 2q) f_rel_a(x - e_a) (halfway
  * when x - e_a is not fluid); q >= 1/2: [f_rel_a(x) + (2q - 1) f_rel_opp(a)(x)]
- * / (2q).  The wall force uses the values that leave and return at the node.
- * Not with MHD, lbm_halfstep or the adjoint (LBM_EINVAL).  Set-up only. */
+ * / (2q).  The wall force uses the values that leave and return at the node;
+ * lbm_halfstep averages f_rel(x, t) with the interpolated f(x, t + dt).  At
+ * most 1,048,574 fluid nodes with such links (LBM_EINVAL beyond).  Not with
+ * MHD, the per-step wall-force record or the adjoint (LBM_EINVAL).  Set-up
+ * only. */
 int lbm_set_link_fractions(lbm_ctx* ctx, const double* q_host);
 
 /* Wall velocity of a group (moving-wall bounce-back adds
@@ -253,7 +256,9 @@ int lbm_stress(lbm_ctx* ctx, double* sigma, double* strain);
  * sigma_bar [ncomp][nz][ny][nx] (physical, component order of lbm_stress); any
  * may be NULL; solid nodes read 0.  LBM_ESTATE unless a step has been taken
  * since the state was last set.  The wall velocities of the last step are
- * used, even if they have been changed since. */
+ * used, even if they have been changed since.  At links to walls that are
+ * not halfway (lbm_set_link_fractions), f(x, t + dt) is the interpolated
+ * returning value. */
 int lbm_halfstep(lbm_ctx* ctx, double* fbar, double* rho_bar, double* u_bar, double* sigma_bar);
 
 /* Momentum-exchange force on the walls of each group during the last step

@@ -1077,6 +1077,10 @@ __global__ __launch_bounds__(IBB_THREADS) void k_ibb(const IbbArgs a) {
     }
     if (a.delta) a.delta[(uint64_t)i * L::Q + q] = dnew[q] - V[q];
   }
+  if (a.half) {
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) a.half[(uint64_t)i * L::Q + q] = V[q];
+  }
 }
 
 // Wall-force corrections of the interpolated links: per block of 256 list
@@ -1119,6 +1123,10 @@ __global__ __launch_bounds__(NTHREADS) void k_colsum(const double* __restrict__ 
 // rho = rho0 + sum_a f_rel_a = rho0 + sum_a V_a + rho K, with V the values as
 // read and K = sum over wall links of 6 w (e.u_w).  Induction distributions
 // likewise (anti-bounce-back: the stored value is the negated relaxed one).
+// At a node with links to walls that are not halfway, the interpolation
+// replaced the halfway values of the last step in the node's own slots; the
+// pass after that step kept them (ibb_half), and they stand in for the slots'
+// contents here, so that f_rel(x, t) and rho(x, t) come back the same way.
 template <class L, int P, int MHD, int PAR>
 __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
   using S = Stor<P>;
@@ -1146,13 +1154,19 @@ __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
     read_f<L, P, PAR, true>((const E*)a.f, Af, mask, a.p, d1);
     double V[L::Q];
     double sV = 0.0, K = 0.0;
+    const uint32_t ix = a.ibb_half ? rec.w >> 12 : 0u;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
       const bool wall = q > 0 && ((mask >> q) & 1u);
       const E* ptr = (PAR == 1 || wall) ? Af.template ptr<L>((const E*)a.f, opp(q), -1)
                                         : Af.template ptr<L>((const E*)a.f, q, q);
-      double v = (double)S::ld(ptr);
-      if (P == S_F16 || P == S_BF16) v *= (double)a.p.inv_scale[q];
+      double v;
+      if (wall && ix) {
+        v = a.ibb_half[(uint64_t)(ix - 1) * L::Q + q];
+      } else {
+        v = (double)S::ld(ptr);
+        if (P == S_F16 || P == S_BF16) v *= (double)a.p.inv_scale[q];
+      }
       V[q] = v;
       sV += v;
       if (wall) {

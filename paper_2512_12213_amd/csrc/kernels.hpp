@@ -49,7 +49,8 @@ struct StepArgs {
   void* f;                 // distributions, row-blocked [ny nz][Q][nx]
   void* g;                 // induction deviations, row-blocked [ny nz][K NB][nx] (MHD) or null
   const float* afield;     // [3][N] or null
-  const uint4* rec;        // boundary records: x = solid-link mask (bit 31: node solid), y..w = group nibbles
+  const uint4* rec;        // boundary records: x = solid-link mask (bit 31: node solid), y..w = group nibbles;
+                           // w >> 12: 1 + index in the list of nodes with interpolated links (0: none)
   const int* rowrec;       // per row: index of the row's first record, or -1
   const uint32_t* blkgrp;  // per tile: up to MAXBG group labels, 4 bits each, + count in bits 28..31
   const double* uw;        // [MAXG][3] wall velocity / c
@@ -116,6 +117,7 @@ struct IbbArgs {
   const double* qf;        // [M][Q] wall distance / link length (1/2: halfway, left as is)
   const uint8_t* grp;      // [M][Q] wall group of each link
   double* delta;           // [M][Q] change of the returning value (diagnostic steps), or null
+  double* half;            // [M][Q] the halfway values the step returned (last step of a call), or null
   const uint4* nrec;       // [M] boundary record of each listed node (wall mask, group nibbles)
   double uw[MAXG][3];      // wall velocities / c of the step
   uint32_t M;
@@ -134,6 +136,7 @@ struct HalfArgs {
   double* rho;          // [N] or null
   double* vel;          // [D][N] u_bar (physical), or null
   double* sigma;        // [NC][N] -sum e e f_bar + Mbar^eq (physical), or null
+  const double* ibb_half;  // [M][Q] halfway values of the last step at nodes with interpolated links, or null
   double uw[MAXG][3];   // wall velocities / c of the last step
   Geom geo;
   Phys p;

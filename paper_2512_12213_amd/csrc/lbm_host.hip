@@ -145,6 +145,7 @@ struct lbm_ctx {
   // nodes whose links are interpolated after each step
   std::vector<double> qlink;
   DevBuf ibb_node, ibb_rec, ibb_q, ibb_grp, ibb_delta, ibb_part, ibb_red;
+  DevBuf ibb_half;  // [nibb][Q] halfway values of the last step (half-step distribution)
   uint32_t nibb = 0;
   double* hred = nullptr;  // pinned [NBAL + MAXG * NWALL]
   void* scratch = nullptr;  // this device's fixed scratch array (lbm_step_noalloc), or null
@@ -334,8 +335,12 @@ int build_geometry(lbm_ctx* h) {
         for (int q = 1; q < Q; ++q)
           if (((r.x >> q) & 1u) && h->qlink[(size_t)q * h->N + n] != 0.5) any = true;
         if (!any) continue;
+        // the record carries 1 + the node's index in this list
+        if (inode.size() + 1 >= (1u << 20))
+          return fail(LBM_EINVAL, "more than %u nodes with links to walls that are not halfway", (1u << 20) - 2);
+        recs[(size_t)rowrec[row] + x].w |= (uint32_t)(inode.size() + 1) << 12;
         inode.push_back((uint32_t)n);
-        irec.push_back(r);
+        irec.push_back(recs[(size_t)rowrec[row] + x]);
         for (int q = 0; q < Q; ++q) {
           const bool wall = q > 0 && ((r.x >> q) & 1u);
           const uint32_t wv = q < 8 ? r.y : (q < 16 ? r.z : r.w);
@@ -415,6 +420,7 @@ int build_geometry(lbm_ctx* h) {
     HIPCHK(h->ibb_q.ensure(iq.size() * sizeof(double)));
     HIPCHK(h->ibb_grp.ensure(igrp.size()));
     HIPCHK(h->ibb_delta.ensure(iq.size() * sizeof(double)));
+    HIPCHK(h->ibb_half.ensure(iq.size() * sizeof(double)));
     HIPCHK(h->ibb_red.ensure(MAXG * 4 * sizeof(double)));
     HIPCHK(h->ibb_part.ensure(((iq.size() + NTHREADS - 1) / NTHREADS) * MAXG * 4 * sizeof(double)));
     HIPCHK(hipMemcpy(h->ibb_node.p, inode.data(), inode.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -983,6 +989,7 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
     if (h->nibb) {
       ib.parity = h->parity ^ 1;
       ib.delta = diag ? sc.ibb_delta : nullptr;
+      ib.half = diag ? (double*)h->ibb_half.p : nullptr;
       HIPCHK(launch_ibb(h->lattice, h->prec, ib, h->stream));
     }
     if (timing) HIPCHK(hipEventRecord(h->ev[i + 1], h->stream));
@@ -1126,7 +1133,6 @@ int lbm_stress(lbm_ctx* h, double* sigma, double* strain) {
 int lbm_halfstep(lbm_ctx* h, double* fbar, double* rho_bar, double* u_bar, double* sigma_bar) {
   int rc = check_ready(h);
   if (rc) return rc;
-  if (h->nibb) return fail(LBM_EINVAL, "the half-step distribution is not available with interpolated walls");
   if (!h->have_step) return fail(LBM_ESTATE, "no step taken since the state was set");
   const size_t N = h->N, Q = h->Q, D = h->D, nc = h->NC;
   const size_t total = (fbar ? Q : 0) + (rho_bar ? 1 : 0) + (u_bar ? D : 0) + (sigma_bar ? nc : 0);
@@ -1137,6 +1143,7 @@ int lbm_halfstep(lbm_ctx* h, double* fbar, double* rho_bar, double* u_bar, doubl
   a.g = h->mhd ? h->g.p : nullptr;
   a.rec = (const uint4*)h->rec.p;
   a.rowrec = (const int*)h->rowrec.p;
+  a.ibb_half = h->nibb ? (const double*)h->ibb_half.p : nullptr;
   double* base = (double*)h->tmp.p;
   size_t off = 0;
   if (fbar) { a.fbar = base + off; off += Q * N; }

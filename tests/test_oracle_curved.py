@@ -95,6 +95,21 @@ def test_offset_couette_is_exact():
         assert abs(fw[1, 0, 0] + nu * U / H) < 1e-10 * nu * U / H
 
 
+def test_halfstep_stress_is_exact_in_the_offset_couette():
+    """Steady lid-driven channel with walls at fractions (0.25, 0.8) and
+    (0.9, 0.3): the half-step stress of Eq. (28), formed from f_rel(x, t) and
+    the interpolated f(x, t + dt) at the nodes next to the walls, is the
+    exact shear stress rho nu U / H at every node."""
+    n, tau, U = 16, 0.8, 0.02
+    for qb, qt in ((0.25, 0.8), (0.9, 0.3)):
+        o = channel(n, qb, tau=tau, a=0.0, steps=40000, uw=U, q_top=qt)
+        _, rb, _, sb = o.halfstep()
+        H = n - 1 + qb + qt
+        nu = (tau - 0.5) / 3
+        exact = rb[0, :, 0] * nu * U / H
+        assert np.abs(sb[1, 0, :, 0] - exact).max() < 1e-10 * nu * U / H
+
+
 def test_cylinder_with_geometric_fractions_balance():
     """Cylinder with link fractions from the exact circle: Eq. (32) holds per
     step (momentum exchange with the interpolated returning values)."""
