@@ -666,8 +666,31 @@ int orc_get_induction(const orc* o, double* g) {
 /* ---------------------------------------------------------------------------
  * One time step
  * ------------------------------------------------------------------------- */
-/* per-row partial sums: [G][3][3] wall force, then M, P[3], rho_a[3] */
-static int part_size(const orc* o) { return o->G * 9 + 7; }
+/* per-row partial sums: [G][3][3] wall force, then M, P[3], rho_a[3], then
+ * [G][Q] the number of wall links of each group and direction */
+static int part_size(const orc* o) { return o->G * 9 + 7 + o->G * o->Q; }
+static int count_slot(const orc* o, int grp, int q) { return o->G * 9 + 7 + grp * o->Q + q; }
+
+/* Eq. (25) with f = d + c_a, c_a = w_a rho0 + phi_a(B0) the rest-state
+ * populations: each link contributes e_a (f_out + f_in) = e_a (d_out + d_in)
+ * + 2 e_a c_a (c_a is the same for a and its opposite).  The deviation parts
+ * are summed link by link; the rest-state parts, large next to the force on
+ * a body and cancelling between its sides, are summed exactly as integer
+ * link counts per direction and its opposite, then weighted (an FP64 sum of
+ * the absolute populations loses about 1e-12 of the force on a small
+ * sphere).  The momentum-flux term has no rest-state part (f_out - f_in =
+ * d_out - d_in). */
+static void add_rest_state_part(const orc* o, const real* tot, real* wf_raw, int grp) {
+  const double vol = o->lat == 0 ? o->dx * o->dx : o->dx * o->dx * o->dx;
+  for (int q = 1; q < o->Q; ++q) {
+    const int qb = o->opp[q];
+    if (qb < q) continue;
+    const real n = tot[count_slot(o, grp, q)] - tot[count_slot(o, grp, qb)];
+    if (n == 0) continue;
+    const real ca = o->w[q] * o->rho0 + phi0(o, q);
+    for (int k = 0; k < 3; ++k) wf_raw[k] += vol / o->dt * 2.0 * (o->c * o->e[q][k]) * ca * n;
+  }
+}
 
 /* Everything of one node's update before propagation: node_setup, then the
  * relaxation of Eq. (2), drel = d + (d^eq - d)/tau + F, with the equilibrium
@@ -730,15 +753,17 @@ static void update_node(orc* o, int x, int y, int z, real* part) {
     const int qb = o->opp[q];
     real ladd = moving_wall_term(o, q, s.rho, o->uw[grp]);
     o->dn[(long)qb * N + idx] = drel[q] + ladd;
-    /* Eq. (25): outgoing f_bar = f_rel(x_f, t), incoming f_bar = f(x_f, t + dt) */
-    real fout = drel[q] + o->w[q] * o->rho0 + phi0(o, q);
-    real fin = fout + ladd;
+    /* Eq. (25): outgoing f_bar = f_rel(x_f, t), incoming f_bar = f(x_f, t + dt),
+     * as deviations (rest-state part: add_rest_state_part) */
+    real dout = drel[q];
+    real din = dout + ladd;
     real* pw = part + grp * 9;
     for (int k = 0; k < 3; ++k) {
       double ek = c * o->e[q][k], ebk = c * o->e[qb][k];
-      pw[k] += vol / dt * (ek * fout - ebk * fin);          /* raw momentum exchange */
-      pw[3 + k] += -vol / dt * o->uw[grp][k] * (fout - fin); /* minus momentum flux */
+      pw[k] += vol / dt * (ek * dout - ebk * din);          /* raw momentum exchange */
+      pw[3 + k] += -vol / dt * o->uw[grp][k] * (dout - din); /* minus momentum flux */
     }
+    part[count_slot(o, grp, q)] += 1;
     if (mhd_eq(o)) {
       /* minus Maxwell stress: the magnetic part of the equilibrium at the wall
        * field carried by both populations of the link */
@@ -819,14 +844,14 @@ static void interpolated_bounce_back(orc* o, real* tot) {
             din = rq / (2.0 * qv) + (2.0 * qv - 1.0) / (2.0 * qv) * o->rel[(long)qb * N + idx] + ladd / (2.0 * qv);
           }
           o->dn[(long)qb * N + idx] = din;
-          const real fout = rq + o->w[q] * o->rho0 + phi0(o, q);
-          const real fin = din + o->w[q] * o->rho0 + phi0(o, qb);
+          /* deviations (rest-state part: add_rest_state_part) */
           real* pw = tot + grp * 9;
           for (int k = 0; k < 3; ++k) {
             double ek = c * o->e[q][k], ebk = c * o->e[qb][k];
-            pw[k] += vol / dt * (ek * fout - ebk * fin);
-            pw[3 + k] += -vol / dt * o->uw[grp][k] * (fout - fin);
+            pw[k] += vol / dt * (ek * rq - ebk * din);
+            pw[3 + k] += -vol / dt * o->uw[grp][k] * (rq - din);
           }
+          tot[count_slot(o, grp, q)] += 1;
         }
       }
 }
@@ -849,11 +874,12 @@ int orc_step(orc* o, int n) {
       }
     }
     /* row partials summed in row order */
-    real tot[MAXG * 9 + 7];
+    real tot[MAXG * 9 + 7 + MAXG * 19];
     memset(tot, 0, sizeof(tot));
     for (long r = 0; r < rows; ++r)
       for (int k = 0; k < P; ++k) tot[k] += part[r * P + k];
     if (o->qlink) interpolated_bounce_back(o, tot);
+    for (int gr = 0; gr < o->G; ++gr) add_rest_state_part(o, tot, tot + gr * 9, gr);
     for (int gr = 0; gr < o->G; ++gr)
       for (int v = 0; v < 3; ++v)
         for (int k = 0; k < 3; ++k) o->wf[gr][v][k] = tot[gr * 9 + v * 3 + k];
