@@ -96,8 +96,8 @@ int lbm_add_solid_mask(lbm_ctx* ctx, const unsigned char* mask_host, int group);
  * (0, 1]; 1/2 keeps halfway bounce-back; entries of other links are ignored
  * but must also lie in (0, 1]; NULL returns to halfway walls everywhere.
  * Links with q != 1/2 are bounced back by linear interpolation (Bouzidi,
- * Firdaouss and Lallemand 2001) in a pass after each step, with the
- * moving-wall term: q < 1/2: 2q f_rel_a(x) + (1 - 2q) f_rel_a(x - e_a) (halfway
+ * Firdaouss and Lallemand 2001), inside the step (in a pass after the last
+ * step of each call), with the moving-wall term: q < 1/2: 2q f_rel_a(x) + (1 - 2q) f_rel_a(x - e_a) (halfway
  * when x - e_a is not fluid); q >= 1/2: [f_rel_a(x) + (2q - 1) f_rel_opp(a)(x)]
  * / (2q).  The wall force uses the values that leave and return at the node;
  * lbm_halfstep averages f_rel(x, t) with the interpolated f(x, t + dt).  At

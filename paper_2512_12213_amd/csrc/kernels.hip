@@ -522,7 +522,8 @@ __device__ __forceinline__ void store_stress(const StepArgs& a, uint32_t n, cons
 // wall group meets, the wall-link sums of each thread (DG): swall[j][tid],
 // j = slot NWALL + quantity, each thread adding only to its own column (no
 // barrier; quantity-major, so that a wavefront's accesses are conflict-free).
-template <class L, int P, int MHD, int PAR, int DG, bool MAC, bool BND, class AD, bool XS = false, bool ST = false>
+template <class L, int P, int MHD, int PAR, int DG, bool MAC, bool BND, class AD, bool XS = false, bool ST = false,
+          bool IB = false>
 __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const AD& Af, const AD& Ag, const uint4& rec,
                                             typename Stor<P>::T (&bal)[NBAL], typename Stor<P>::T* lds,
                                             uint32_t bgrp, uint32_t x = 0,
@@ -565,6 +566,24 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
   } else {
     read_f<L, P, PAR, BND, AD, !RAW>((const typename S::E*)a.f, Af, mask, a.p, d);
   }
+  if constexpr (BND && IB) {
+    // Links to walls that are not halfway with q < 1/2 (interpolated
+    // bounce-back, see k_ibb): the previous step of this call left
+    // 2q f_rel_a(x) + ladd in the returning slot; the value streamed in along
+    // a, f_rel_a(x - e_a), completes it (x - e_a fluid).
+    const uint32_t ix = a.ibb_in ? rec.w >> 12 : 0u;
+    if (ix) {
+      const double* qp = a.ibq + (uint64_t)(ix - 1) * L::Q;
+#pragma unroll
+      for (int q = 1; q < L::Q; ++q) {
+        const int qb = opp(q);
+        if (((mask >> q) & 1u) && !((mask >> qb) & 1u)) {
+          const double qv = qp[q];
+          if (qv < 0.5) d[qb] += (T)(1.0 - 2.0 * qv) * d[q];
+        }
+      }
+    }
+  }
   T Ax, Ay, Az;
   if (a.afield) {
     const T s = par<T>(a.p.afield_scale, a.p.f.afield_scale);
@@ -603,7 +622,10 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
     bal[6] += m.rho * m.A[2];
   }
   typename S::E* fo = (typename S::E*)a.f;
-  auto sink = [&](int q, T v) __attribute__((always_inline)) {
+  // emit(q, v, vo): store the relaxed value v of direction q (vo: that of
+  // its opposite, which the interpolated bounce-back needs)
+  [[maybe_unused]] const uint32_t ixo = (BND && IB && a.ibb_out) ? rec.w >> 12 : 0u;
+  auto emit = [&](int q, T v, [[maybe_unused]] T vo) __attribute__((always_inline)) {
     if (BND && q > 0 && ((mask >> q) & 1u)) {
       // halfway bounce-back link: the returning population is d_rel plus the
       // moving-wall term 6 w rho (e_opp . u_w) / c^2; the Eq. (25) momentum
@@ -614,6 +636,17 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
       const T ladd = T(-6) * (T)L::w(q) * m.rho * edot<L>(q, ux, uy, uz);
       const T out = v;
       v = out + ladd;
+      if (IB && ixo) {
+        // wall at fraction qv of the link (steps before the last of a call;
+        // the last one returns the halfway value and k_ibb interpolates,
+        // with the wall-force sums, which are formed on that step only)
+        const double qv = a.ibq[(uint64_t)(ixo - 1) * L::Q + q];
+        if (qv < 0.5) {
+          if (!((mask >> opp(q)) & 1u)) v = (T)(2.0 * qv) * out + ladd;
+        } else if (qv > 0.5) {
+          v = (out + (T)(2.0 * qv - 1.0) * vo + ladd) * (T)(0.5 / qv);
+        }
+      }
       if (DG) {
         const T cq = out + v;
         T* sw = lds + threadIdx.x;
@@ -641,6 +674,24 @@ __device__ __forceinline__ void node_update(const StepArgs& a, uint32_t n, const
     } else {
       write_f1<L, P, PAR, BND, AD, !RAW>(fo, Af, mask, a.p, q, v);
     }
+  };
+  // The relaxation hands over a direction q (odd) and its opposite q + 1
+  // one after the other; at boundary nodes the first is held until the
+  // second arrives, so that each wall link sees its opposite's value.
+  [[maybe_unused]] T held = T(0);
+  auto sink = [&](int q, T v) __attribute__((always_inline)) {
+    if constexpr (BND && IB) {
+      if (q & 1) {
+        held = v;
+        return;
+      }
+      if (q > 0) {
+        emit(q - 1, held, v);
+        emit(q, v, held);
+        return;
+      }
+    }
+    emit(q, v, v);
   };
   if constexpr (RAW)
     collide_raw<L, P>(d, m, a.p, sink);
@@ -690,7 +741,10 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles, uint32
 // RU: 0 generic addressing; 1 row-uniform pointers; 2 row-uniform pointers
 // for rows with boundary links and buffer resources for the other rows
 // (arrays below 4 GiB).
-template <class L, int P, int MHD, int PAR, int DG, int RU, bool MAC = false, bool ST = false>
+// IB: links to walls that are not halfway are interpolated inside the step
+// (a.ibb_in, a.ibb_out); only the row-uniform buffer form without MHD, stress
+// or the density record has this variant, so the others keep their registers.
+template <class L, int P, int MHD, int PAR, int DG, int RU, bool MAC = false, bool ST = false, bool IB = false>
 __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   using T = typename Stor<P>::T;
   const Geom& g = a.geo;
@@ -759,7 +813,8 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
         if (rr < 0)
           node_update<L, P, MHD, PAR, DG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, lds, bgrp);
         else
-          node_update<L, P, MHD, PAR, DG, MAC, true, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, lds, bgrp, 0u, suw);
+          node_update<L, P, MHD, PAR, DG, MAC, true, decltype(Af), false, ST, IB>(a, n, Af, Ag, rec, bal, lds, bgrp, 0u,
+                                                                                 suw);
       } else {
         const AddrG Af = addr_g(g, x, y, z, r, L::Q);
         const AddrG Ag = addr_g(g, x, y, z, r, MHD ? Ind<L>::K * Ind<L>::NB : L::Q);
@@ -978,14 +1033,19 @@ __global__ __launch_bounds__(NTHREADS) void k_diag(const DiagArgs a) {
 // ---------------------------------------------------------------------------
 // interpolated bounce-back (walls that are not halfway between nodes)
 // ---------------------------------------------------------------------------
-// Run after a step on the nodes with such links.  The step itself returned
-// the halfway value f_rel_a(x) + ladd into the node's own slot for direction
-// opp(a); this replaces it with the linear interpolation of Bouzidi,
-// Firdaouss and Lallemand (2001) for a wall at fraction q of the link:
+// The linear interpolation of Bouzidi, Firdaouss and Lallemand (2001) for a
+// wall at fraction q of the link a returns into x, as direction opp(a):
 //   q <  1/2: 2q f_rel_a(x) + (1 - 2q) f_rel_a(x - e_a) + ladd
 //             (f_rel_a(x - e_a) is the value that streamed into x along a;
 //             halfway when x - e_a is not a fluid node),
 //   q >= 1/2: [f_rel_a(x) + (2q - 1) f_rel_opp(a)(x) + ladd] / (2q).
+// The steps before the last of a call do this themselves: the q >= 1/2 form
+// at once (both values are the node's own), the q < 1/2 form in two parts,
+// 2q f_rel_a(x) + ladd in the step and the streamed part when the next step
+// reads the node.  The last step of a call returns the halfway value
+// f_rel_a(x) + ladd into the node's own slot for direction opp(a), and this
+// pass, run after it on the nodes with such links, replaces it with the
+// interpolated value and forms the changes the wall force needs.
 // f_rel(x, t) is read back as for the half-step distribution; the moving-wall
 // term ladd = -6 w rho(x, t) e_a.u_w needs rho(x, t), recovered by mass
 // conservation of the relaxation.  One thread per node: every slot it reads
@@ -1407,6 +1467,19 @@ static void launch_step_dg(const StepArgs& a, int dg, uint32_t nb, hipStream_t s
 
 template <class L, int P, int MHD, int RU, bool ST>
 static void launch_step_ru_st(const StepArgs& a, int parity, int dg, uint32_t nb, hipStream_t st) {
+  if constexpr (RU == 2 && MHD == 0 && !ST) {
+    if (a.ibb_in || a.ibb_out) {
+      // interpolated links inside the step (never with diagnostics mode 1)
+      if (parity == 0) {
+        if (dg == 2) k_step<L, P, 0, 0, 2, 2, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
+        else k_step<L, P, 0, 0, 0, 2, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
+      } else {
+        if (dg == 2) k_step<L, P, 0, 1, 2, 2, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
+        else k_step<L, P, 0, 1, 0, 2, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
+      }
+      return;
+    }
+  }
   if (parity == 0)
     launch_step_dg<L, P, MHD, 0, RU, ST>(a, dg, nb, st);
   else
@@ -1424,14 +1497,21 @@ static void launch_step_ru(const StepArgs& a, int parity, int dg, uint32_t nb, h
 }
 
 template <class L, int P, int MHD>
+static bool buffer_form(const Geom& g) {
+  using E = typename Stor<P>::E;
+  const uint64_t fb = (uint64_t)g.N * L::Q * sizeof(E);
+  const uint64_t gb = MHD ? (uint64_t)g.N * Ind<L>::K * Ind<L>::NB * sizeof(E) : 0;
+  return g.nx % 64 == 0 && fb < (1ull << 32) && gb < (1ull << 32);
+}
+
+template <class L, int P, int MHD>
 static hipError_t launch_step_t(const StepArgs& a, int parity, int dg, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
-  using E = typename Stor<P>::E;
-  const uint64_t fb = (uint64_t)a.geo.N * L::Q * sizeof(E);
-  const uint64_t gb = MHD ? (uint64_t)a.geo.N * Ind<L>::K * Ind<L>::NB * sizeof(E) : 0;
+  if ((a.ibb_in || a.ibb_out) && (MHD != 0 || !buffer_form<L, P, MHD>(a.geo) || a.sig || a.strain || dg == 1))
+    return hipErrorInvalidValue;
   // buffer form (measured: FP32 -1 %, FP16 and BF16 -6 to -8 %; FP64 +2 %
   // alone, but it carries the LDS staging of odd steps, and with it -4 %)
-  if (a.geo.nx % 64 == 0 && fb < (1ull << 32) && gb < (1ull << 32))
+  if (buffer_form<L, P, MHD>(a.geo))
     launch_step_ru<L, P, MHD, 2>(a, parity, dg, nb, st);
   else if (a.geo.nx % 64 == 0)
     launch_step_ru<L, P, MHD, 1>(a, parity, dg, nb, st);
@@ -1535,6 +1615,29 @@ static hipError_t launch_init_t(const InitArgs& a, hipStream_t st) {
 // per-step ring (a.hist), 2 all diagnostics of the last step of a call.
 hipError_t launch_step(int lattice, int prec, int mhd, const StepArgs& a, int parity, int dg, hipStream_t st) {
   LBM_DISPATCH(launch_step_t, lattice, prec, mhd, a, parity, dg, st);
+}
+
+template <class L, int P, int MHD>
+static bool in_step_ibb_t(const Geom& g) {
+  return MHD == 0 && buffer_form<L, P, MHD>(g);
+}
+
+bool step_interpolates_in_step(int lattice, int prec, int mhd, const Geom& g) {
+  if (mhd) return false;
+  if (lattice == 0) {
+    switch (prec) {
+      case S_F64: return in_step_ibb_t<D2Q9, S_F64, 0>(g);
+      case S_F32: return in_step_ibb_t<D2Q9, S_F32, 0>(g);
+      case S_F16: return in_step_ibb_t<D2Q9, S_F16, 0>(g);
+      default: return in_step_ibb_t<D2Q9, S_BF16, 0>(g);
+    }
+  }
+  switch (prec) {
+    case S_F64: return in_step_ibb_t<D3Q19, S_F64, 0>(g);
+    case S_F32: return in_step_ibb_t<D3Q19, S_F32, 0>(g);
+    case S_F16: return in_step_ibb_t<D3Q19, S_F16, 0>(g);
+    default: return in_step_ibb_t<D3Q19, S_BF16, 0>(g);
+  }
 }
 
 hipError_t launch_step_mac(int lattice, int prec, const StepArgs& a, int parity, bool diag, hipStream_t st) {

@@ -63,6 +63,10 @@ struct StepArgs {
   double* hist;            // per-step ring slot [MAXBG NWALL][nwt] of the wall-link sums (diagnostics mode 1)
   const int* wtile;        // per tile: compact index among the tiles a wall group meets, or -1
   uint32_t nwt;            // number of such tiles
+  // links to walls that are not halfway (nodes with rec.w >> 12 != 0)
+  const double* ibq;       // [M][Q] wall distance / link length of each listed node
+  int ibb_in;              // the state holds 2q f_rel + ladd at their q < 1/2 links: complete it at the read
+  int ibb_out;             // interpolate at their links in the step (q < 1/2: the part known at x)
   Geom geo;
   Phys p;
 };

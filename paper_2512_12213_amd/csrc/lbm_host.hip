@@ -17,6 +17,7 @@
 
 namespace lbm {
 hipError_t launch_step(int lattice, int prec, int mhd, const StepArgs& a, int parity, int dg, hipStream_t st);
+bool step_interpolates_in_step(int lattice, int prec, int mhd, const Geom& g);
 hipError_t launch_hist_reduce(const double* ring, const uint32_t* wlc, uint32_t nwt, int G, uint32_t nsteps,
                               double* out, hipStream_t st);
 hipError_t launch_diag(int lattice, int prec, int mhd, const DiagArgs& a, hipStream_t st);
@@ -961,6 +962,9 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
   }
   const int par0 = h->parity;
   if (timing) HIPCHK(hipEventRecord(h->ev[0], h->stream));
+  a.ibq = h->nibb ? (const double*)h->ibb_q.p : nullptr;
+  const bool in_step = h->nibb && !tape && h->st_every == 0 && !hist &&
+                       step_interpolates_in_step(h->lattice, h->prec, mhd_mode(h), a.geo);
   a.st_c2 = (float)(h->c * h->c);
   a.st_hdt = (float)(1.5 / h->dt);
   a.st_artefact = h->artefact;
@@ -972,6 +976,11 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
       HIPCHK(hipMemcpyAsync((char*)h->ckpt.p + (size_t)(i / ckpt_every) * sbytes, h->f.p, sbytes,
                             hipMemcpyDeviceToDevice, h->stream));
     const bool diag = i == n - 1;
+    // interpolated links: in the step except on the last one of the call,
+    // whose halfway values the pass after it replaces (row-uniform buffer
+    // form without stress storage; otherwise the pass runs after every step)
+    a.ibb_in = in_step && i > 0;
+    a.ibb_out = in_step && !diag;
     if (tape) {
       a.mac = (char*)tape + (size_t)i * mbytes;
       HIPCHK(launch_step_mac(h->lattice, h->prec, a, h->parity, diag, h->stream));
@@ -986,7 +995,7 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
         chunk0 = i + 1;
       }
     }
-    if (h->nibb) {
+    if (h->nibb && (diag || !in_step)) {
       ib.parity = h->parity ^ 1;
       ib.delta = diag ? sc.ibb_delta : nullptr;
       ib.half = diag ? (double*)h->ibb_half.p : nullptr;

@@ -1,6 +1,8 @@
 """Walls that are not halfway between nodes on the GPU: linearly interpolated
-bounce-back (Bouzidi, Firdaouss and Lallemand 2001) run as a pass after each
-step, against the oracle element by element, and the Section 5 statement that
+bounce-back (Bouzidi, Firdaouss and Lallemand 2001), inside the steps before
+the last of a call (row-uniform lattices, widths that are multiples of 64)
+or in a pass after each step (other widths), against the oracle element by
+element, and the Section 5 statement that
 the momentum exchange of Eq. (25) then gives the stress at the half-grid point
 x_f + e dt / 2, checked on the GPU alone in steady flows.
 
@@ -52,25 +54,27 @@ def pair(lbm, w, q, storage=None):
     return g, o
 
 
+@pytest.mark.parametrize("nx", [8, 64])
 @pytest.mark.parametrize("storage", [W.F64, W.F32])
 @pytest.mark.parametrize("steps", [300, 301])
-def test_offset_channel_matches_oracle(lbm, storage, steps):
+def test_offset_channel_matches_oracle(lbm, storage, steps, nx):
     """Force-driven channel with walls at q = 0.25 below and 0.8 above the
     end nodes; both A-A parities end the call."""
-    w, q = offset_channel(8, 16, 0.25, 0.8, a=2e-5)
-    say("case offset channel", storage, steps)
+    w, q = offset_channel(nx, 16, 0.25, 0.8, a=2e-5)
+    say("case offset channel", storage, steps, nx)
     g, o = pair(lbm, w, q, storage)
     g.step(steps)
     o.step(steps)
     compare_all(g, o, storage, 2, "offset channel")
 
 
+@pytest.mark.parametrize("nx", [8, 64])
 @pytest.mark.parametrize("storage", [W.F64, W.F32])
-def test_offset_couette_matches_oracle(lbm, storage):
+def test_offset_couette_matches_oracle(lbm, storage, nx):
     """Moving top wall with fractions 0.9 (bottom) and 0.3 (top): the
     moving-wall term enters both interpolation branches."""
-    w, q = offset_channel(8, 12, 0.9, 0.3, a=0.0, uw=0.03)
-    say("case offset couette", storage)
+    w, q = offset_channel(nx, 12, 0.9, 0.3, a=0.0, uw=0.03)
+    say("case offset couette", storage, nx)
     g, o = pair(lbm, w, q, storage)
     for _ in range(3):
         g.step(67)
@@ -100,8 +104,9 @@ def test_curved_cylinder_matches_oracle(lbm, storage):
 @pytest.mark.parametrize("storage", [W.F64, W.F32])
 def test_curved_sphere_matches_oracle(lbm, storage):
     """D3Q19 duct with an off-lattice sphere (fractions of the exact sphere)
-    and a moving top wall."""
-    w = W.duct_sphere(nx=24, ny=16, nz=14, r=3.7, storage=storage)
+    and a moving top wall; 64 wide, so that the steps before the last of a
+    call interpolate inside the step."""
+    w = W.duct_sphere(nx=64, ny=16, nz=14, r=3.7, storage=storage)
     w.curved = True
     say("case curved sphere", storage)
     g, o = pair(lbm, w, None, storage)
@@ -109,6 +114,30 @@ def test_curved_sphere_matches_oracle(lbm, storage):
         g.step(n)
         o.step(n)
         compare_all(g, o, storage, 5, "curved sphere")
+
+
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+def test_interpolation_in_the_step_equals_the_pass(lbm, storage):
+    """Steps before the last of a call interpolate inside the step (q < 1/2
+    links completed when the next step reads the node); a call's last step
+    leaves it to the pass after it.  A 40-step call against 40 one-step
+    calls (every step then ends a call): the same states and wall forces up
+    to the rounding order (FP64 1e-13, FP32 1e-5 relative).  64 wide (the
+    row-uniform form, which has the in-step variant)."""
+    w = W.duct_sphere(nx=64, ny=16, nz=14, r=3.7, storage=storage)
+    w.curved = True
+    say("case in-step interpolation", storage)
+    a = lbm.from_workload(w)
+    b = lbm.from_workload(w)
+    a.step(40)
+    for _ in range(40):
+        b.step(1)
+    tol = 1e-13 if storage == W.F64 else 1e-5
+    es = rel_inf(a.get_state(), b.get_state())
+    ef = rel_inf(a.wall_force(), b.wall_force())
+    say("  state %.2e wall force %.2e" % (es, ef))
+    assert es <= tol and ef <= 10 * tol
+    assert es > 0  # the two forms round differently: the in-step one ran
 
 
 @pytest.mark.parametrize("qv", [0.25, 0.7, 1.0])
@@ -136,14 +165,16 @@ def test_gpu_momentum_exchange_is_the_half_grid_stress(lbm, qv):
     assert abs((s_w - P) - a * (qv - 0.5)) < 1e-9 * P
 
 
-def test_gpu_offset_couette_is_exact(lbm):
+@pytest.mark.parametrize("nx", [4, 64])
+def test_gpu_offset_couette_is_exact(lbm, nx):
     """Linear interpolation makes the linear profile between the true walls
     exact: u(y) = U (y + q_b) / H with H = n - 1 + q_b + q_t, and both walls
-    carry rho nu U / H."""
+    carry rho nu U / H.  4 wide: the pass after each step; 64 wide: inside
+    the steps."""
     n, tau, U = 16, 0.8, 0.02
     for qb, qt in ((0.25, 0.8), (0.9, 0.3)):
-        w, q = offset_channel(4, n, qb, qt, tau=tau, a=0.0, uw=U)
-        say("case exact couette", qb, qt)
+        w, q = offset_channel(nx, n, qb, qt, tau=tau, a=0.0, uw=U)
+        say("case exact couette", nx, qb, qt)
         g = lbm.from_workload(w, init=False)
         g.set_link_fractions(q)
         g.init_equilibrium()
@@ -171,9 +202,9 @@ def test_halfstep_with_interpolated_walls_matches_oracle(lbm, lattice, storage):
     fractions (both interpolation branches), a moving wall and a body force:
     FP64 1e-12, FP32 1e-5 on f_bar, rho_bar, u_bar and 1e-5 on sigma_bar."""
     if lattice == W.D2Q9:
-        w = W.couette_cylinder(nx=48, ny=24, r=4.3, cx=16.4, cy=11.7, uw=0.03, tau=0.7, a=2e-5, storage=storage)
+        w = W.couette_cylinder(nx=64, ny=24, r=4.3, cx=16.4, cy=11.7, uw=0.03, tau=0.7, a=2e-5, storage=storage)
     else:
-        w = W.duct_sphere(nx=24, ny=16, nz=14, r=3.7, storage=storage)
+        w = W.duct_sphere(nx=64, ny=16, nz=14, r=3.7, storage=storage)
     w.curved = True
     q = W.link_fractions(w)
     assert (q < 0.5).any() and (q > 0.5).any()
