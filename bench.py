@@ -70,7 +70,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and workloads")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--only", choices=["adjoint", "hartmann", "halfstep", "sphere", "formats", "stress", "history"],
+    ap.add_argument("--only", choices=["adjoint", "hartmann", "halfstep", "sphere", "formats", "stress", "history",
+                                       "large"],
                     default=None,
                     help="run only this measurement (for profiling its kernels) and print its record")
     ap.add_argument("--calibrate", action="store_true",
@@ -391,6 +392,13 @@ def main():
     if args.only == "history":
         rs = {"duct_les_f32_wall_force_every_step": timed_run(lbm, torch, W.duct_les(), args.steps, args.warmup,
                                                                wall_history=True),
+              "duct_les_f32": timed_run(lbm, torch, W.duct_les(), args.steps, args.warmup)}
+        print(json.dumps(rs), flush=True)
+        return
+    if args.only == "large":
+        # the duct beyond the last-level cache, next to the headline size
+        rs = {"duct_les_f32_512x256x256": timed_run(lbm, torch, W.duct_les(nx=512, ny=256, nz=256), args.steps,
+                                                    args.warmup),
               "duct_les_f32": timed_run(lbm, torch, W.duct_les(), args.steps, args.warmup)}
         print(json.dumps(rs), flush=True)
         return
