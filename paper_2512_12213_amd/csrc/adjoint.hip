@@ -38,9 +38,11 @@
 
 namespace lbm {
 
+// pu: this thread's column of the wall-velocity cotangents in LDS,
+// [MAXBG][3] with stride NTHREADS.
 template <class L, int PS, int PL, int PAR, bool SEED, bool BND, class AD>
 __device__ __forceinline__ void adj_node(const AdjArgs& a, uint32_t n, const AD& Al, const uint4& rec,
-                                         typename Stor<PL>::T (&pu)[MAXBG][3], uint32_t bgrp) {
+                                         double* pu, uint32_t bgrp) {
   using S = Stor<PL>;
   using T = typename S::T;
   using E = typename S::E;
@@ -64,15 +66,13 @@ __device__ __forceinline__ void adj_node(const AdjArgs& a, uint32_t n, const AD&
       mu[q] = s;
     } else {
       const int qb = opp(q);
-      const E* ptr;
-      if (PAR == 0) {
-        ptr = Al.template ptr<L>(lam, qb, -1);
-      } else if (BND) {
-        ptr = pick((mask >> q) & 1u, Al.template ptr<L>(lam, qb, -1), Al.template ptr<L>(lam, q, q));
+      if constexpr (BND && PAR == 1) {
+        mu[q] = S::ld(pick((mask >> q) & 1u, Al.template ptr<L>(lam, qb, -1), Al.template ptr<L>(lam, q, q)));
+      } else if constexpr (PAR == 0) {
+        mu[q] = Al.template ld<L, PL>(lam, qb, -1);
       } else {
-        ptr = Al.template ptr<L>(lam, q, q);
+        mu[q] = Al.template ld<L, PL>(lam, q, q);
       }
-      mu[q] = S::ld(ptr);
     }
   }
 
@@ -171,9 +171,9 @@ __device__ __forceinline__ void adj_node(const AdjArgs& a, uint32_t n, const AD&
 #pragma unroll
         for (int s = 0; s < MAXBG; ++s) {
           if (((bgrp >> (4 * s)) & 15u) == gr) {
-            pu[s][0] += cr6 * (T)L::ex(q);
-            pu[s][1] += cr6 * (T)L::ey(q);
-            pu[s][2] += cr6 * (T)L::ez(q);
+            pu[(3 * s + 0) * NTHREADS] += (double)(cr6 * (T)L::ex(q));
+            pu[(3 * s + 1) * NTHREADS] += (double)(cr6 * (T)L::ey(q));
+            pu[(3 * s + 2) * NTHREADS] += (double)(cr6 * (T)L::ez(q));
           }
         }
       }
@@ -188,15 +188,13 @@ __device__ __forceinline__ void adj_node(const AdjArgs& a, uint32_t n, const AD&
   for (int q = 0; q < L::Q; ++q) {
     const int qb = opp(q);
     const T lq = keep * mu[q] + Mrho + edot<L>(q, MU[0], MU[1], MU[2]) * irho - MUU;
-    E* ptr;
-    if (PAR == 0) {
-      ptr = Al.template ptr<L>(lam, q, -1);
-    } else if (BND) {
-      ptr = pick((mask >> qb) & 1u, Al.template ptr<L>(lam, q, -1), Al.template ptr<L>(lam, qb, qb));
+    if constexpr (BND && PAR == 1) {
+      S::st(pick((mask >> qb) & 1u, Al.template ptr<L>(lam, q, -1), Al.template ptr<L>(lam, qb, qb)), lq);
+    } else if constexpr (PAR == 0) {
+      Al.template st<L, PL>(lam, q, -1, lq);
     } else {
-      ptr = Al.template ptr<L>(lam, qb, qb);
+      Al.template st<L, PL>(lam, qb, qb, lq);
     }
-    S::st(ptr, lq);
   }
 
   // body-force gradient, accumulated over the steps
@@ -214,15 +212,25 @@ __device__ __forceinline__ void adj_node(const AdjArgs& a, uint32_t n, const AD&
   }
 }
 
+// Register budget of three wavefronts per SIMD (at most 168 VGPRs; the FP64
+// adjoint state otherwise takes 205-211 and runs two): measured 3.5 % faster
+// per backward pass with two spilled registers; a budget of four spills 40-56
+// and is 18 % slower.
 template <class L, int PS, int PL, int PAR, bool SEED, bool RU>
-__global__ __launch_bounds__(NTHREADS) void k_adj(const AdjArgs a) {
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_adj(const AdjArgs a) {
   using T = typename Stor<PL>::T;
   const Geom& g = a.geo;
   const uint32_t n = blockIdx.x * NTHREADS + threadIdx.x;
   const uint32_t bgrp = a.blkgrp[blockIdx.x];
-  T pu[MAXBG][3];
+  // wall-velocity cotangents of this thread's links, in its own column of
+  // LDS (FP64; no barrier: a thread touches only its column) rather than in
+  // twelve registers held through the whole node update
+  __shared__ double spu[MAXBG * 3 * NTHREADS];
+  double* pu = spu + threadIdx.x;
+  if (bgrp >> 28) {
 #pragma unroll
-  for (int s = 0; s < MAXBG; ++s) pu[s][0] = pu[s][1] = pu[s][2] = T(0);
+    for (int j = 0; j < MAXBG * 3; ++j) pu[j * NTHREADS] = 0.0;
+  }
   if (n < g.N) {
     uint32_t x, y, z, r;
     coords(g, n, x, y, z, r);
@@ -235,11 +243,19 @@ __global__ __launch_bounds__(NTHREADS) void k_adj(const AdjArgs a) {
     const uint4 rec = rr < 0 ? make_uint4(0u, 0u, 0u, 0u) : a.rec[rr + x];
     if (!(rec.x >> 31)) {
       if (RU) {
-        const AddrR Al = addr_r(g, x, y, z, L::Q);
-        if (rr < 0)
-          adj_node<L, PS, PL, PAR, SEED, false>(a, n, Al, rec, pu, bgrp);
-        else
-          adj_node<L, PS, PL, PAR, SEED, true>(a, n, Al, rec, pu, bgrp);
+        using E = typename Stor<PL>::E;
+        if (rr < 0 && (uint64_t)g.N * L::Q * sizeof(E) < (1ull << 32)) {
+          // rows without boundary links, state below 4 GiB: buffer
+          // addressing (no 64-bit per-lane addresses)
+          const AddrB Ab = addr_b<E>(g, x, y, z, L::Q, a.lam, (uint32_t)((uint64_t)g.N * L::Q * sizeof(E)));
+          adj_node<L, PS, PL, PAR, SEED, false>(a, n, Ab, rec, pu, bgrp);
+        } else {
+          const AddrR Al = addr_r(g, x, y, z, L::Q);
+          if (rr < 0)
+            adj_node<L, PS, PL, PAR, SEED, false>(a, n, Al, rec, pu, bgrp);
+          else
+            adj_node<L, PS, PL, PAR, SEED, true>(a, n, Al, rec, pu, bgrp);
+        }
       } else {
         const AddrG Al = addr_g(g, x, y, z, r, L::Q);
         if (rr < 0)
@@ -255,9 +271,9 @@ __global__ __launch_bounds__(NTHREADS) void k_adj(const AdjArgs a) {
     double v[MAXBG * NWALL];
 #pragma unroll
     for (int s = 0; s < MAXBG; ++s) {
-      v[s * NWALL + 0] = (double)pu[s][0];
-      v[s * NWALL + 1] = (double)pu[s][1];
-      v[s * NWALL + 2] = (double)pu[s][2];
+      v[s * NWALL + 0] = pu[(3 * s + 0) * NTHREADS];
+      v[s * NWALL + 1] = pu[(3 * s + 1) * NTHREADS];
+      v[s * NWALL + 2] = pu[(3 * s + 2) * NTHREADS];
       v[s * NWALL + 3] = 0.0;
     }
     tile_sum_store<MAXBG * NWALL, true>(v, a.part + (uint64_t)NBAL * gridDim.x + blockIdx.x, gridDim.x);

@@ -13,7 +13,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import make_oracle, rel_inf
+from helpers import make_oracle, quantize_state, quantized_steps, rel_inf
 from paper_2512_12213_amd import workloads as W
 from test_gpu_parity import compare_all
 
@@ -114,6 +114,25 @@ def test_curved_sphere_matches_oracle(lbm, storage):
         g.step(n)
         o.step(n)
         compare_all(g, o, storage, 5, "curved sphere")
+
+
+@pytest.mark.parametrize("storage", [W.F16, W.BF16])
+def test_curved_sphere_16bit_matches_quantized_oracle(lbm, storage):
+    """The sphere duct in 16-bit storage (interpolated links in the steps,
+    their q < 1/2 parts stored in the format between steps) against the
+    oracle whose state is rounded to the format after every step: the
+    tolerances of the 16-bit parity tests (2e-3; BF16's recorded bounds)."""
+    w = W.duct_sphere(nx=64, ny=16, nz=14, r=3.7, storage=storage)
+    w.curved = True
+    say("case curved sphere 16-bit", storage)
+    g, o = pair(lbm, w, None, storage)
+    d0 = o.get_state()
+    g.set_state(d0)
+    o.set_state(quantize_state(d0, storage))
+    for n in (20, 21):
+        g.step(n)
+        quantized_steps(o, storage, n)
+        compare_all(g, o, storage, 5, "curved sphere %d" % storage)
 
 
 @pytest.mark.parametrize("storage", [W.F64, W.F32])
