@@ -852,6 +852,14 @@ static void interpolated_bounce_back(orc* o, real* tot) {
             pw[3 + k] += -vol / dt * o->uw[grp][k] * (rq - din);
           }
           tot[count_slot(o, grp, q)] += 1;
+          if (mhd_eq(o)) {
+            /* minus Maxwell stress, per link as at a halfway wall: both
+             * populations of the link carry the magnetic part of the
+             * equilibrium at the wall field B0 */
+            real Bw[3] = {o->B0[0], o->B0[1], o->B0[2]};
+            real ph = phi_mhd(o, q, Bw);
+            for (int k = 0; k < 3; ++k) pw[6 + k] += -vol / dt * 2.0 * (c * o->e[q][k]) * ph;
+          }
         }
       }
 }

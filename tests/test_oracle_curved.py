@@ -133,3 +133,65 @@ def test_link_fractions_are_checked_and_adjoint_refuses_them():
     o.init_equilibrium()
     with pytest.raises(ValueError):
         o.adjoint(2, 0, 0)
+
+
+def test_maxwell_correction_at_interpolated_walls_equals_L_n():
+    """Walls at fractions 0.3 (bottom) and 0.8 (top) under the MHD
+    equilibrium: the Maxwell correction of each wall is L n A, as for
+    halfway walls (the per-link term does not depend on where the wall cuts
+    the link)."""
+    B = np.array([0.03, 0.05, -0.02])
+    mu, dx, dt = 1.3, 0.5, 0.25
+    nx, ny, nz = 4, 6, 3
+    o = oracle.Oracle(oracle.D3Q19, nx, ny, nz, 0.9, dx, dt, oracle.GUO)
+    o.set_walls(1, 0, 1)
+    q = np.full((19, nz, ny, nx), 0.5)
+    q[:, :, 0, :] = 0.3
+    q[:, :, ny - 1, :] = 0.8
+    o.set_link_fraction(q)
+    o.set_mhd(B, mu, 0.8)
+    o.init_equilibrium()
+    o.step(1)
+    fw = o.wall_force(2)
+    corr = fw[:, 2, :] - fw[:, 0, :]
+    L = (0.5 * (B @ B) * np.eye(3) - np.outer(B, B)) / mu
+    area = nx * nz * dx * dx
+    np.testing.assert_allclose(corr[0], L @ np.array([0, 1.0, 0]) * area, rtol=1e-12, atol=1e-16)
+    np.testing.assert_allclose(corr[1], L @ np.array([0, -1.0, 0]) * area, rtol=1e-12, atol=1e-16)
+
+
+@pytest.mark.parametrize("lorentz", [False, True])
+def test_offset_couette_in_an_aligned_field_is_exact(lorentz):
+    """Lid-driven channel with walls at fractions (0.25, 0.8) in a uniform
+    field along the flow: u x B = 0, so B stays uniform and carries no
+    current, and the flow is the exact linear profile between the true
+    walls, with both walls carrying rho nu U / H; the Maxwell-corrected
+    force equals the hydrodynamic one (D3Q19 slab, both MHD couplings)."""
+    n, tau, U, qb, qt = 16, 0.8, 0.02, 0.25, 0.8
+    forces = []
+    for mhd in (False, True):
+        o = oracle.Oracle(oracle.D3Q19, 1, n, 1, tau, 1.0, 1.0, oracle.GUO)
+        o.set_walls(1, 0, 1)
+        o.set_wall_velocity(1, [U, 0, 0])
+        q = np.full((19, 1, n, 1), 0.5)
+        q[:, 0, 0, 0] = qb
+        q[:, 0, n - 1, 0] = qt
+        o.set_link_fraction(q)
+        if mhd:
+            o.set_mhd([0.05, 0.0, 0.0], 1.0, 0.9)
+            if lorentz:
+                o.set_lorentz_force(True)
+        o.init_equilibrium()
+        o.step(40000)
+        rho, v, *rest = o.get_macro(with_B=True) if mhd else o.get_macro()
+        H = n - 1 + qb + qt
+        y = np.arange(n, dtype=float)
+        assert np.abs(v[0, 0, :, 0] - U * (y + qb) / H).max() < 1e-12 * U
+        if mhd:
+            Bf = rest[0]
+            assert np.abs(Bf[0] - 0.05).max() < 1e-14 and np.abs(Bf[1:]).max() < 1e-14
+        forces.append(o.wall_force(2))
+    hydro, magn = forces
+    nu = (tau - 0.5) / 3
+    assert abs(magn[0, 0, 0] - nu * U / (n - 1 + qb + qt)) < 1e-10 * nu * U
+    np.testing.assert_allclose(magn[:, 2, :], hydro[:, 0, :], rtol=1e-12, atol=1e-15)
