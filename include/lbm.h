@@ -101,9 +101,11 @@ int lbm_add_solid_mask(lbm_ctx* ctx, const unsigned char* mask_host, int group);
  * when x - e_a is not fluid); q >= 1/2: [f_rel_a(x) + (2q - 1) f_rel_opp(a)(x)]
  * / (2q).  The wall force uses the values that leave and return at the node;
  * lbm_halfstep averages f_rel(x, t) with the interpolated f(x, t + dt).  At
- * most 1,048,574 fluid nodes with such links (LBM_EINVAL beyond).  Not with
- * MHD, the per-step wall-force record or the adjoint (LBM_EINVAL).  Set-up
- * only. */
+ * most 1,048,574 fluid nodes with such links (LBM_EINVAL beyond).  Under
+ * MHD the induction distributions keep halfway anti-bounce-back (B = B0
+ * half a link from the fluid node), each wall link keeps its Maxwell-stress
+ * correction, and the pass runs after every step.  Not with the per-step
+ * wall-force record or the adjoint (LBM_EINVAL).  Set-up only. */
 int lbm_set_link_fractions(lbm_ctx* ctx, const double* q_host);
 
 /* Wall velocity of a group (moving-wall bounce-back adds

@@ -352,7 +352,6 @@ int build_geometry(lbm_ctx* h) {
     }
   }
   h->nibb = (uint32_t)inode.size();
-  if (h->nibb && h->mhd) return fail(LBM_EINVAL, "walls that are not halfway are not supported with MHD");
   for (uint32_t t = 0; t < h->ntiles; ++t) {
     uint32_t cnt = 0, packed = 0;
     for (int gr = 0; gr < MAXG; ++gr)
