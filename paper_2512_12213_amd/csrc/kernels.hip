@@ -1218,22 +1218,29 @@ __global__ __launch_bounds__(NTHREADS) void k_half(const HalfArgs a) {
     TS d1[L::Q];
     read_f<L, P, PAR, true>((const E*)a.f, Af, mask, a.p, d1);
     double V[L::Q];
-    double sV = 0.0, K = 0.0;
-    const uint32_t ix = a.ibb_half ? rec.w >> 12 : 0u;
 #pragma unroll
     for (int q = 0; q < L::Q; ++q) {
       const bool wall = q > 0 && ((mask >> q) & 1u);
       const E* ptr = (PAR == 1 || wall) ? Af.template ptr<L>((const E*)a.f, opp(q), -1)
                                         : Af.template ptr<L>((const E*)a.f, q, q);
-      double v;
-      if (wall && ix) {
-        v = a.ibb_half[(uint64_t)(ix - 1) * L::Q + q];
-      } else {
-        v = (double)S::ld(ptr);
-        if (P == S_F16 || P == S_BF16) v *= (double)a.p.inv_scale[q];
-      }
+      double v = (double)S::ld(ptr);
+      if (P == S_F16 || P == S_BF16) v *= (double)a.p.inv_scale[q];
       V[q] = v;
-      sV += v;
+    }
+    // nodes with interpolated links: their wall slots' halfway values, as
+    // the last step returned them (after the loads above, so that those are
+    // not held behind a per-direction branch)
+    const uint32_t ix = a.ibb_half ? rec.w >> 12 : 0u;
+    if (ix) {
+#pragma unroll
+      for (int q = 1; q < L::Q; ++q)
+        if ((mask >> q) & 1u) V[q] = a.ibb_half[(uint64_t)(ix - 1) * L::Q + q];
+    }
+    double sV = 0.0, K = 0.0;
+#pragma unroll
+    for (int q = 0; q < L::Q; ++q) {
+      const bool wall = q > 0 && ((mask >> q) & 1u);
+      sV += V[q];
       if (wall) {
         const uint32_t gr = nibble(rec, q);
         K += 6.0 * L::w(q) * edot<L>(q, suw[gr][0], suw[gr][1], suw[gr][2]);
