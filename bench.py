@@ -169,6 +169,8 @@ def halfstep_run(lbm, torch, W, calls=5):
     requested (the kernel's own time is in the rocprofv3 trace)."""
     w = W.duct_les()
     lat = lbm.from_workload(w)
+    stream = torch.cuda.current_stream()
+    lat.set_stream(stream.cuda_stream)
     lat.step(20)
     lat.halfstep()
     torch.cuda.synchronize()
@@ -176,9 +178,29 @@ def halfstep_run(lbm, torch, W, calls=5):
     for _ in range(calls):
         lat.halfstep()
     t = (time.perf_counter() - t0) / calls
+    # the same outputs into device buffers (lbm_halfstep_device), timed
+    # with events around the calls on the library's stream
+    nc = 3 if w.D == 2 else 6
+    dev = dict(dtype=torch.float64, device="cuda")
+    bufs = [torch.empty((w.Q, w.nz, w.ny, w.nx), **dev), torch.empty((w.nz, w.ny, w.nx), **dev),
+            torch.empty((w.D, w.nz, w.ny, w.nx), **dev), torch.empty((nc, w.nz, w.ny, w.nx), **dev)]
+    ptrs = [b.data_ptr() for b in bufs]
+    lat.halfstep_device(*ptrs)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(calls):
+        lat.halfstep_device(*ptrs)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    td = e0.elapsed_time(e1) * 1e-3 / calls
     lat.close()
+    nbytes = w.N * (2 * w.Q * 4 + 8 * (w.Q + 1 + w.D + nc))
     return {"call_ms": t * 1e3, "nodes": w.N,
-            "outputs": "f_bar, rho_bar, u_bar, sigma_bar to host (FP64)"}
+            "outputs": "f_bar, rho_bar, u_bar, sigma_bar to host (FP64)",
+            "device_call_ms": round(td * 1e3, 4), "device_bytes": nbytes,
+            "device_frac": round(nbytes / td / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def adjoint_run(lbm, torch, W, adj_prec, K=40, repeats=3):

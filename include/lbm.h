@@ -263,6 +263,14 @@ int lbm_stress(lbm_ctx* ctx, double* sigma, double* strain);
  * returning value. */
 int lbm_halfstep(lbm_ctx* ctx, double* fbar, double* rho_bar, double* u_bar, double* sigma_bar);
 
+/* The same half-step distribution and moments (Section 5, Eqs. 27-28) into
+ * caller-owned DEVICE buffers of the same layouts (FP64), with no copy to
+ * the host: one kernel enqueued on the context's stream (lbm_set_stream);
+ * the outputs are complete when that stream reaches this point.  Any may be
+ * NULL; the buffers must stay valid until then and must not overlap.
+ * LBM_ESTATE unless a step has been taken since the state was last set. */
+int lbm_halfstep_device(lbm_ctx* ctx, double* fbar, double* rho_bar, double* u_bar, double* sigma_bar);
+
 /* Momentum-exchange force on the walls of each group during the last step
  * (Eq. 25, the populations leaving at t and returning at t + dt, per link
  * (dx^D / dt)(e_out f_out - e_in f_in)).  out [G][4][3], G = lbm_num_groups:

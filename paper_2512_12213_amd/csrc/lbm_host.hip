@@ -1138,6 +1138,37 @@ int lbm_stress(lbm_ctx* h, double* sigma, double* strain) {
   return LBM_OK;
 }
 
+// The half-step kernel's arguments for the last step, outputs left null.
+static HalfArgs half_args(lbm_ctx* h) {
+  HalfArgs a = {};
+  a.f = h->f.p;
+  a.g = h->mhd ? h->g.p : nullptr;
+  a.rec = (const uint4*)h->rec.p;
+  a.rowrec = (const int*)h->rowrec.p;
+  a.ibb_half = h->nibb ? (const double*)h->ibb_half.p : nullptr;
+  for (int gr = 0; gr < MAXG; ++gr)
+    for (int k = 0; k < 3; ++k) a.uw[gr][k] = h->last_uw[gr][k] / h->c;
+  a.geo = make_geom(h);
+  a.p = make_phys(h);
+  a.parity = h->parity;
+  a.c = h->c;
+  return a;
+}
+
+int lbm_halfstep_device(lbm_ctx* h, double* fbar, double* rho_bar, double* u_bar, double* sigma_bar) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!h->have_step) return fail(LBM_ESTATE, "no step taken since the state was set");
+  if (!fbar && !rho_bar && !u_bar && !sigma_bar) return LBM_OK;
+  HalfArgs a = half_args(h);
+  a.fbar = fbar;
+  a.rho = rho_bar;
+  a.vel = u_bar;
+  a.sigma = sigma_bar;
+  HIPCHK(launch_half(h->lattice, h->prec, mhd_mode(h), a, h->stream));
+  return LBM_OK;
+}
+
 int lbm_halfstep(lbm_ctx* h, double* fbar, double* rho_bar, double* u_bar, double* sigma_bar) {
   int rc = check_ready(h);
   if (rc) return rc;
@@ -1146,24 +1177,13 @@ int lbm_halfstep(lbm_ctx* h, double* fbar, double* rho_bar, double* u_bar, doubl
   const size_t total = (fbar ? Q : 0) + (rho_bar ? 1 : 0) + (u_bar ? D : 0) + (sigma_bar ? nc : 0);
   if (!total) return LBM_OK;
   HIPCHK(h->tmp.ensure(total * N * sizeof(double)));
-  HalfArgs a = {};
-  a.f = h->f.p;
-  a.g = h->mhd ? h->g.p : nullptr;
-  a.rec = (const uint4*)h->rec.p;
-  a.rowrec = (const int*)h->rowrec.p;
-  a.ibb_half = h->nibb ? (const double*)h->ibb_half.p : nullptr;
+  HalfArgs a = half_args(h);
   double* base = (double*)h->tmp.p;
   size_t off = 0;
   if (fbar) { a.fbar = base + off; off += Q * N; }
   if (rho_bar) { a.rho = base + off; off += N; }
   if (u_bar) { a.vel = base + off; off += D * N; }
   if (sigma_bar) { a.sigma = base + off; off += nc * N; }
-  for (int gr = 0; gr < MAXG; ++gr)
-    for (int k = 0; k < 3; ++k) a.uw[gr][k] = h->last_uw[gr][k] / h->c;
-  a.geo = make_geom(h);
-  a.p = make_phys(h);
-  a.parity = h->parity;
-  a.c = h->c;
   HIPCHK(launch_half(h->lattice, h->prec, mhd_mode(h), a, h->stream));
   if (fbar) HIPCHK(hipMemcpyAsync(fbar, a.fbar, Q * N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   if (rho_bar) HIPCHK(hipMemcpyAsync(rho_bar, a.rho, N * sizeof(double), hipMemcpyDeviceToHost, h->stream));

@@ -57,6 +57,7 @@ _SIGS = [
     ("lbm_get_field_B", C.c_int, [_P, _D]),
     ("lbm_stress", C.c_int, [_P, _D, _D]),
     ("lbm_halfstep", C.c_int, [_P, _D, _D, _D, _D]),
+    ("lbm_halfstep_device", C.c_int, [_P, _P, _P, _P, _P]),
     ("lbm_wall_force", C.c_int, [_P, _D]),
     ("lbm_force_balance", C.c_int, [_P, _D]),
     ("lbm_set_wall_force_history", C.c_int, [_P, C.c_int]),
@@ -275,6 +276,12 @@ class Lattice:
         sb = np.empty((self.NC,) + sh)
         _chk(self.L.lbm_halfstep(self.h, _dp(fb), _dp(rb), _dp(ub), _dp(sb)))
         return fb, rb, ub, sb
+
+    def halfstep_device(self, fbar_ptr, rho_ptr, u_ptr, sigma_ptr):
+        """lbm_halfstep_device: the same outputs into caller device buffers
+        (pointers, e.g. torch tensors' data_ptr(); None for any not wanted),
+        enqueued on the library's stream."""
+        _chk(self.L.lbm_halfstep_device(self.h, fbar_ptr, rho_ptr, u_ptr, sigma_ptr))
 
     def num_groups(self):
         return _chk(self.L.lbm_num_groups(self.h))

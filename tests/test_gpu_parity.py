@@ -387,11 +387,46 @@ def test_halfstep_mhd(lbm):
             assert e["u"] <= TOL_FIELD[storage] and e["sigma"] <= TOL_STRESS[storage]
 
 
+@pytest.mark.parametrize("curved", [False, True])
+def test_halfstep_into_device_buffers_equals_host_outputs(lbm, curved):
+    """lbm_halfstep_device writes the same values (bit for bit) into caller
+    device buffers as lbm_halfstep does into host buffers: a duct with a
+    sphere, halfway or with interpolated walls, after a 7-step call; with
+    some outputs left NULL."""
+    import torch
+    w = W.duct_sphere(nx=64, ny=16, nz=14, r=3.7)
+    w.curved = curved
+    say("case halfstep device", curved)
+    g = gpu_from(w, lbm)
+    g.step(7)
+    fh, rh, uh, sh = g.halfstep()
+    dev = dict(dtype=torch.float64, device="cuda")
+    fb = torch.full(fh.shape, 7.0, **dev)
+    rb = torch.full(rh.shape, 7.0, **dev)
+    ub = torch.full(uh.shape, 7.0, **dev)
+    sb = torch.full(sh.shape, 7.0, **dev)
+    torch.cuda.synchronize()
+    g.halfstep_device(fb.data_ptr(), rb.data_ptr(), ub.data_ptr(), sb.data_ptr())
+    torch.cuda.synchronize()
+    for a, b in ((fb, fh), (rb, rh), (ub, uh), (sb, sh)):
+        assert np.array_equal(a.cpu().numpy(), b)
+    sb.fill_(7.0)
+    rb.fill_(7.0)
+    torch.cuda.synchronize()
+    g.halfstep_device(None, None, None, sb.data_ptr())
+    torch.cuda.synchronize()
+    assert np.array_equal(sb.cpu().numpy(), sh)
+    assert float(rb.cpu().max()) == 7.0  # left alone
+
+
 def test_halfstep_needs_a_step(lbm):
     w = W.poiseuille(nx=8, ny=8)
     g = gpu_from(w, lbm)
     with pytest.raises(lbm.LBMError) as ei:
         g.halfstep()
+    assert ei.value.code == lbm.LBM_ESTATE
+    with pytest.raises(lbm.LBMError) as ei:
+        g.halfstep_device(None, None, None, None)
     assert ei.value.code == lbm.LBM_ESTATE
 
 
