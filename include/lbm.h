@@ -245,6 +245,13 @@ int lbm_get_field_B(lbm_ctx* ctx, double* B);
  * buffers [ncomp][nz][ny][nx]; either may be NULL.  Solid nodes read 0. */
 int lbm_stress(lbm_ctx* ctx, double* sigma, double* strain);
 
+/* The same stress and strain rate (Eqs. 8-9) into caller-owned DEVICE
+ * buffers of the same layout (FP64), with no copy to the host: one kernel
+ * enqueued on the context's stream (lbm_set_stream); the outputs are
+ * complete when that stream reaches this point.  Either may be NULL; the
+ * buffers must stay valid until then and must not overlap. */
+int lbm_stress_device(lbm_ctx* ctx, double* sigma, double* strain);
+
 /* Half-step distribution of the last step (Section 5, Eq. 27):
  * f_bar = (f_rel(x, t) + f(x, t + dt)) / 2, the relaxed value before
  * propagation averaged with the propagated one, and its moments: density

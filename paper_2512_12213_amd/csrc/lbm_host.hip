@@ -1138,6 +1138,16 @@ int lbm_stress(lbm_ctx* h, double* sigma, double* strain) {
   return LBM_OK;
 }
 
+int lbm_stress_device(lbm_ctx* h, double* sigma, double* strain) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (!sigma && !strain) return LBM_OK;
+  DiagArgs a = diag_args(h);
+  a.sigma = sigma;
+  a.strain = strain;
+  return run_diag(h, a);
+}
+
 // The half-step kernel's arguments for the last step, outputs left null.
 static HalfArgs half_args(lbm_ctx* h) {
   HalfArgs a = {};

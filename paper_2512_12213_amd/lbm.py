@@ -58,6 +58,7 @@ _SIGS = [
     ("lbm_stress", C.c_int, [_P, _D, _D]),
     ("lbm_halfstep", C.c_int, [_P, _D, _D, _D, _D]),
     ("lbm_halfstep_device", C.c_int, [_P, _P, _P, _P, _P]),
+    ("lbm_stress_device", C.c_int, [_P, _P, _P]),
     ("lbm_wall_force", C.c_int, [_P, _D]),
     ("lbm_force_balance", C.c_int, [_P, _D]),
     ("lbm_set_wall_force_history", C.c_int, [_P, C.c_int]),
@@ -276,6 +277,12 @@ class Lattice:
         sb = np.empty((self.NC,) + sh)
         _chk(self.L.lbm_halfstep(self.h, _dp(fb), _dp(rb), _dp(ub), _dp(sb)))
         return fb, rb, ub, sb
+
+    def stress_device(self, sigma_ptr, strain_ptr):
+        """lbm_stress_device: sigma and S of the current state into caller
+        device buffers (pointers; None for one not wanted), enqueued on the
+        library's stream."""
+        _chk(self.L.lbm_stress_device(self.h, sigma_ptr, strain_ptr))
 
     def halfstep_device(self, fbar_ptr, rho_ptr, u_ptr, sigma_ptr):
         """lbm_halfstep_device: the same outputs into caller device buffers

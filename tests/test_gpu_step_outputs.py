@@ -147,6 +147,34 @@ def test_step_stress_equals_lbm_stress_full_size(env):
     assert e3 <= 1e-5
 
 
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+def test_stress_into_device_buffers_equals_host_outputs(env, storage):
+    """lbm_stress_device writes the same values (bit for bit) into caller
+    device buffers as lbm_stress does into host buffers, for a seeded state
+    with walls, a solid body and LES; either output alone."""
+    L, torch = env
+    w, mask = case(W.D3Q19, 4, storage)
+    say("case stress device", storage)
+    g = L.from_workload(w, init=False)
+    g.add_solid_mask(mask, 4)
+    g.set_state(W.random_state(w.Q, w.nx, w.ny, w.nz, 2e-3, seed=29) * (1 - mask[None]))
+    g.step(3)
+    sh, Sh = g.stress()
+    dev = dict(dtype=torch.float64, device="cuda")
+    sd = torch.full(sh.shape, 7.0, **dev)
+    Sd = torch.full(Sh.shape, 7.0, **dev)
+    torch.cuda.synchronize()
+    g.stress_device(sd.data_ptr(), Sd.data_ptr())
+    torch.cuda.synchronize()
+    assert np.array_equal(sd.cpu().numpy(), sh) and np.array_equal(Sd.cpu().numpy(), Sh)
+    sd.fill_(7.0)
+    Sd.fill_(7.0)
+    torch.cuda.synchronize()
+    g.stress_device(None, Sd.data_ptr())
+    torch.cuda.synchronize()
+    assert np.array_equal(Sd.cpu().numpy(), Sh) and float(sd.cpu().max()) == 7.0
+
+
 def test_step_stress_argument_checks(env):
     L, torch = env
     w = W.poiseuille(nx=8, ny=8)
