@@ -747,8 +747,8 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles, uint32
 // for rows with boundary links and buffer resources for the other rows
 // (arrays below 4 GiB).
 // IB: links to walls that are not halfway are interpolated inside the step
-// (a.ibb_in, a.ibb_out); only the row-uniform buffer form without MHD, stress
-// or the density record has this variant, so the others keep their registers.
+// (a.ibb_in, a.ibb_out); only the row-uniform buffer form without MHD or the
+// density record has this variant, so the others keep their registers.
 template <class L, int P, int MHD, int PAR, int DG, int RU, bool MAC = false, bool ST = false, bool IB = false>
 __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   using T = typename Stor<P>::T;
@@ -1479,15 +1479,15 @@ static void launch_step_dg(const StepArgs& a, int dg, uint32_t nb, hipStream_t s
 
 template <class L, int P, int MHD, int RU, bool ST>
 static void launch_step_ru_st(const StepArgs& a, int parity, int dg, uint32_t nb, hipStream_t st) {
-  if constexpr (RU == 2 && MHD == 0 && !ST) {
+  if constexpr (RU == 2 && MHD == 0) {
     if (a.ibb_in || a.ibb_out) {
       // interpolated links inside the step (never with diagnostics mode 1)
       if (parity == 0) {
-        if (dg == 2) k_step<L, P, 0, 0, 2, 2, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
-        else k_step<L, P, 0, 0, 0, 2, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
+        if (dg == 2) k_step<L, P, 0, 0, 2, 2, false, ST, true><<<nb, NTHREADS, 0, st>>>(a);
+        else k_step<L, P, 0, 0, 0, 2, false, ST, true><<<nb, NTHREADS, 0, st>>>(a);
       } else {
-        if (dg == 2) k_step<L, P, 0, 1, 2, 2, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
-        else k_step<L, P, 0, 1, 0, 2, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
+        if (dg == 2) k_step<L, P, 0, 1, 2, 2, false, ST, true><<<nb, NTHREADS, 0, st>>>(a);
+        else k_step<L, P, 0, 1, 0, 2, false, ST, true><<<nb, NTHREADS, 0, st>>>(a);
       }
       return;
     }
@@ -1519,7 +1519,7 @@ static bool buffer_form(const Geom& g) {
 template <class L, int P, int MHD>
 static hipError_t launch_step_t(const StepArgs& a, int parity, int dg, hipStream_t st) {
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
-  if ((a.ibb_in || a.ibb_out) && (MHD != 0 || !buffer_form<L, P, MHD>(a.geo) || a.sig || a.strain || dg == 1))
+  if ((a.ibb_in || a.ibb_out) && (MHD != 0 || !buffer_form<L, P, MHD>(a.geo) || dg == 1))
     return hipErrorInvalidValue;
   // buffer form (measured: FP32 -1 %, FP16 and BF16 -6 to -8 %; FP64 +2 %
   // alone, but it carries the LDS staging of odd steps, and with it -4 %)

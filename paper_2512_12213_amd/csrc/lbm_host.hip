@@ -962,7 +962,7 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
   const int par0 = h->parity;
   if (timing) HIPCHK(hipEventRecord(h->ev[0], h->stream));
   a.ibq = h->nibb ? (const double*)h->ibb_q.p : nullptr;
-  const bool in_step = h->nibb && !tape && h->st_every == 0 && !hist &&
+  const bool in_step = h->nibb && !tape && !hist &&
                        step_interpolates_in_step(h->lattice, h->prec, mhd_mode(h), a.geo);
   a.st_c2 = (float)(h->c * h->c);
   a.st_hdt = (float)(1.5 / h->dt);
@@ -977,7 +977,7 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
     const bool diag = i == n - 1;
     // interpolated links: in the step except on the last one of the call,
     // whose halfway values the pass after it replaces (row-uniform buffer
-    // form without stress storage; otherwise the pass runs after every step)
+    // form without MHD; otherwise the pass runs after every step)
     a.ibb_in = in_step && i > 0;
     a.ibb_out = in_step && !diag;
     if (tape) {

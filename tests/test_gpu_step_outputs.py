@@ -175,6 +175,35 @@ def test_stress_into_device_buffers_equals_host_outputs(env, storage):
     assert np.array_equal(Sd.cpu().numpy(), Sh) and float(sd.cpu().max()) == 7.0
 
 
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+def test_step_stress_with_interpolated_walls(env, storage):
+    """The duct with an off-lattice sphere (64 wide: the steps interpolate
+    the sphere's links themselves) storing the stress every step: a 5-step
+    call leaves the stress of the state its last step started from, against
+    the oracle's stress of that state (after 4 steps): FP64 1e-6, FP32 1e-5;
+    and the state after the call against the oracle's."""
+    L, torch = env
+    w = W.duct_sphere(nx=64, ny=16, nz=14, r=3.7, storage=storage)
+    w.curved = True
+    say("case step stress curved", storage)
+    g = L.from_workload(w)
+    o = make_oracle(w)
+    sig = torch.empty((6, w.nz, w.ny, w.nx), dtype=torch.float32, device="cuda")
+    S = torch.empty_like(sig)
+    g.set_step_stress(sig.data_ptr(), S.data_ptr(), 1)
+    g.step(5)
+    o.step(4)
+    torch.cuda.synchronize()
+    so, So = o.stress()
+    e = dict(sigma=rel_inf(sig.cpu().numpy().astype(np.float64), so),
+             S=rel_inf(S.cpu().numpy().astype(np.float64), So))
+    o.step(1)
+    e["state"] = rel_inf(g.get_state(), o.get_state())
+    say("  %s" % {k: "%.2e" % v for k, v in e.items()})
+    assert e["sigma"] <= TOL[storage] and e["S"] <= TOL[storage]
+    assert e["state"] <= (1e-12 if storage == W.F64 else 1e-5)
+
+
 def test_step_stress_argument_checks(env):
     L, torch = env
     w = W.poiseuille(nx=8, ny=8)
