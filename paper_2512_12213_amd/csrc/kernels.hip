@@ -16,6 +16,8 @@
 //
 // All quantities inside the kernels are dimensionless: velocities in units of
 // c = dx/dt, body force as a dt / c, magnetic field as B / (c sqrt(mu)).
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace lbm {
@@ -749,7 +751,11 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles, uint32
 // IB: links to walls that are not halfway are interpolated inside the step
 // (a.ibb_in, a.ibb_out); only the row-uniform buffer form without MHD or the
 // density record has this variant, so the others keep their registers.
-template <class L, int P, int MHD, int PAR, int DG, int RU, bool MAC = false, bool ST = false, bool IB = false>
+// PLD: interior rows read with plain (cached) loads (AddrBP) instead of
+// non-temporal ones; instantiated for FP32 odd steps without diagnostics,
+// chosen by the host for states far beyond the last-level cache.
+template <class L, int P, int MHD, int PAR, int DG, int RU, bool MAC = false, bool ST = false, bool IB = false,
+          bool PLD = false>
 __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   using T = typename Stor<P>::T;
   const Geom& g = a.geo;
@@ -800,12 +806,16 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
       if (RU == 2 && rr < 0) {
         using E = typename Stor<P>::E;
         constexpr uint32_t GP = MHD ? Ind<L>::K * Ind<L>::NB : L::Q;
-        const AddrB Af = addr_b<E>(g, x, y, z, L::Q, a.f, (uint32_t)((uint64_t)g.N * L::Q * sizeof(E)));
-        const AddrB Ag = MHD ? addr_b<E>(g, x, y, z, GP, a.g, (uint32_t)((uint64_t)g.N * GP * sizeof(E))) : Af;
+        using AFT = std::conditional_t<PLD, AddrBP, AddrB>;
+        AFT Af;
+        static_cast<AddrB&>(Af) = addr_b<E>(g, x, y, z, L::Q, a.f, (uint32_t)((uint64_t)g.N * L::Q * sizeof(E)));
+        AFT Ag = Af;
+        if constexpr (MHD != 0)
+          static_cast<AddrB&>(Ag) = addr_b<E>(g, x, y, z, GP, a.g, (uint32_t)((uint64_t)g.N * GP * sizeof(E)));
         if constexpr (XS_OK) {
           if ((bgrp >> 27) & 1u) {
             // tile of whole rows without boundary links (uniform per tile)
-            node_update<L, P, MHD, PAR, DG, MAC, false, AddrB, true, ST>(a, n, Af, Ag, rec, bal, lds, bgrp, x);
+            node_update<L, P, MHD, PAR, DG, MAC, false, AFT, true, ST>(a, n, Af, Ag, rec, bal, lds, bgrp, x);
           } else {
             node_update<L, P, MHD, PAR, DG, MAC, false, decltype(Af), false, ST>(a, n, Af, Ag, rec, bal, lds, bgrp);
           }
@@ -1469,6 +1479,12 @@ __global__ __launch_bounds__(NTHREADS) void k_hist_reduce(const double* __restri
 // ---------------------------------------------------------------------------
 template <class L, int P, int MHD, int PAR, int RU, bool ST>
 static void launch_step_dg(const StepArgs& a, int dg, uint32_t nb, hipStream_t st) {
+  if constexpr (P == S_F32 && MHD == 0 && PAR == 1 && RU == 2 && !ST) {
+    if (dg == 0 && a.plain_loads) {
+      k_step<L, P, 0, 1, 0, 2, false, false, false, true><<<nb, NTHREADS, 0, st>>>(a);
+      return;
+    }
+  }
   if (dg == 2)
     k_step<L, P, MHD, PAR, 2, RU, false, ST><<<nb, NTHREADS, 0, st>>>(a);
   else if (dg == 1)

@@ -67,6 +67,7 @@ struct StepArgs {
   const double* ibq;       // [M][Q] wall distance / link length of each listed node
   int ibb_in;              // the state holds 2q f_rel + ladd at their q < 1/2 links: complete it at the read
   int ibb_out;             // interpolate at their links in the step (q < 1/2: the part known at x)
+  int plain_loads;         // FP32 odd steps read interior rows with plain (cached) loads
   Geom geo;
   Phys p;
 };

@@ -142,6 +142,25 @@ def test_random_state_two_steps(lbm, lattice, model, storage):
                   "with the artefact term")
 
 
+def test_state_beyond_1gib_odd_steps_with_plain_loads(lbm):
+    """FP32 duct with LES, 512x192x160 (15.7 M nodes, a 1.19 GB state): its
+    odd steps read interior rows with plain loads (states beyond 1 GiB).  A
+    3-step call (even, odd, then the diagnostic even step) against the
+    oracle: state, stress and wall force at the FP32 tolerances."""
+    import oracle
+    oracle.threads(16)
+    w = W.duct_les(nx=512, ny=192, nz=160)
+    say("case plain loads 512x192x160")
+    g = gpu_from(w, lbm)
+    o = make_oracle(w)
+    g.step(3)
+    o.step(3)
+    e_s = rel_inf(g.get_state(), o.get_state())
+    say("  state %.2e" % e_s)
+    assert e_s <= TOL_FIELD[W.F32]
+    compare_all(g, o, W.F32, 4, "plain loads")
+
+
 @pytest.mark.parametrize("storage", [W.F32, W.F64])
 @pytest.mark.parametrize("nx", [256, 512, 768])
 @pytest.mark.parametrize("case", ["walls", "periodic"])
