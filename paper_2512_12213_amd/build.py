@@ -85,7 +85,9 @@ def build_host_sanitized(outdir: str, verbose: bool = False) -> str:
     cmd = [hipcc, *HIPCC_FLAGS, *SANITIZE_HOST, "-c", os.path.join(CSRC, "lbm_host.hip"), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True, stderr=subprocess.DEVNULL if not verbose else None)
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError("hipcc failed on lbm_host.hip (host sanitizers):\n" + p.stderr)
     out = os.path.join(outdir, "liblbm.so")
     objs = [os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o") for s in SOURCES if s != "lbm_host.hip"]
     subprocess.run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", out, *objs, obj], check=True)
