@@ -203,12 +203,15 @@ def halfstep_run(lbm, torch, W, calls=5):
             "device_frac": round(nbytes / td / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def adjoint_run(lbm, torch, W, adj_prec, K=40, repeats=3):
+def adjoint_run(lbm, torch, W, adj_prec, K=40, repeats=3, curved=False):
     """Differentiable duct with a sphere (128x64x64, r = 8, tau 0.55, per-node
     Guo force field, 400 steps, checkpoints every 40, FP32): recorded forward
     and full checkpointed backward (segment recompute + adjoint steps),
-    timed with events around the calls; best of `repeats`."""
+    timed with events around the calls; best of `repeats`.  curved: the
+    sphere's links at their exact wall distance (interpolated bounce-back,
+    its pass and the pass's transpose in every step)."""
     w = W.duct_sphere()
+    w.curved = curved
     T = w.steps
     a0 = W.force_field(w.nx, w.ny, w.nz, base=w.body_force, amp=0.3, seed=16)
     af = torch.from_numpy(a0.astype(np.float32)).cuda()
@@ -241,7 +244,8 @@ def adjoint_run(lbm, torch, W, adj_prec, K=40, repeats=3):
     s_adj = 8 if adj_prec == W.F64 else 4
     rbytes = (2 * 19 * 4 + 16 + 12 if K else 0) + (2 * 19 * s_adj + 16 + 12 + 24)
     return {
-        "workload": "duct_sphere_d3q19_128x64x64_r8_T400_%s_f32" % ("ckpt%d" % K if K else "tape"),
+        "workload": "duct_sphere_d3q19_128x64x64_r8%s_T400_%s_f32" % ("_curved" if curved else "",
+                                                                       "ckpt%d" % K if K else "tape"),
         "adjoint_state": "f64" if adj_prec == W.F64 else "f32",
         "J": J,
         "dJ_duw_x": float(gu[1, 0]),
@@ -389,7 +393,9 @@ def main():
 
     if args.only == "adjoint":
         print(json.dumps({"adjoint": adjoint_run(lbm, torch, W, W.F64, repeats=1),
-                          "adjoint_tape": adjoint_run(lbm, torch, W, W.F64, K=0, repeats=1)}), flush=True)
+                          "adjoint_tape": adjoint_run(lbm, torch, W, W.F64, K=0, repeats=1),
+                          "adjoint_curved": adjoint_run(lbm, torch, W, W.F64, repeats=1, curved=True)}),
+              flush=True)
         return
     if args.only == "hartmann":
         rh = timed_run(lbm, torch, W.hartmann_duct(), args.steps, args.warmup)
@@ -527,6 +533,7 @@ def main():
         out["adjoint"] = adjoint_run(lbm, torch, W, W.F64)
         out["adjoint_f32_state"] = adjoint_run(lbm, torch, W, W.F32)
         out["adjoint_tape"] = adjoint_run(lbm, torch, W, W.F64, K=0)
+        out["adjoint_curved"] = adjoint_run(lbm, torch, W, W.F64, curved=True)
     if not args.no_cpu:
         print("bench: CPU reference baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_seconds)

@@ -104,8 +104,10 @@ int lbm_add_solid_mask(lbm_ctx* ctx, const unsigned char* mask_host, int group);
  * most 1,048,574 fluid nodes with such links (LBM_EINVAL beyond).  Under
  * MHD the induction distributions keep halfway anti-bounce-back (B = B0
  * half a link from the fluid node), each wall link keeps its Maxwell-stress
- * correction, and the pass runs after every step.  Not with the per-step
- * wall-force record or the adjoint (LBM_EINVAL).  Set-up only. */
+ * correction, and the pass runs after every step.  A run recorded by
+ * lbm_adjoint_forward also runs the pass after every step, and its adjoint
+ * reverses it.  Not with the per-step wall-force record (LBM_EINVAL).
+ * Set-up only. */
 int lbm_set_link_fractions(lbm_ctx* ctx, const double* q_host);
 
 /* Wall velocity of a group (moving-wall bounce-back adds
@@ -338,7 +340,11 @@ long lbm_steps_taken(lbm_ctx* ctx);
  * storage, no MHD and no Smagorinsky closure (LBM_EINVAL otherwise).  The run
  * stays recorded for lbm_adjoint_backward until the next lbm_step,
  * lbm_adjoint_forward, state upload or change of wall velocities, body force
- * or closure; the body-force field's device memory must not change meanwhile. */
+ * or closure; the body-force field's device memory must not change meanwhile.
+ * With walls that are not halfway (lbm_set_link_fractions) every recorded
+ * step runs the interpolation as a pass after it (the same values as inside
+ * the step, up to rounding order), and J includes the interpolated links'
+ * changes of the returning values. */
 int lbm_adjoint_forward(lbm_ctx* ctx, int T, int ckpt_every, int group, int axis, double* J);
 
 /* Gradient of gJ * J for the recorded run, by the adjoint of every step in
@@ -354,7 +360,10 @@ int lbm_adjoint_forward(lbm_ctx* ctx, int T, int ckpt_every, int group, int axis
  * are allocated on first use and kept.  The
  * context's state is not changed and the run stays recorded.  LBM_ESTATE
  * without a recorded run.  The recompute runs in the storage precision, the
- * adjoint steps in the adjoint precision (lbm_set_adjoint_precision). */
+ * adjoint steps in the adjoint precision (lbm_set_adjoint_precision).  With
+ * walls that are not halfway each adjoint step is preceded by the transpose
+ * of the interpolation pass (FP64 arithmetic), and dJ/du_w includes the
+ * moving-wall terms of the interpolated links. */
 int lbm_adjoint_backward(lbm_ctx* ctx, double gJ, void* grad_a_dev, int grad_f64, double* grad_uw);
 
 /* Precision of the adjoint state and its arithmetic: LBM_F64 (the default;

@@ -51,29 +51,30 @@ __device__ __forceinline__ void adj_node(const AdjArgs& a, uint32_t n, const AD&
   const uint32_t mask = rec.x;
   E* lam = (E*)a.lam;
 
+  // objective of the last forward step: sum over the links of one group of
+  // e_axis (2 d_rel + ladd), i.e. 2 e_axis on the cotangent of d_rel and
+  // e_axis on that of ladd (the link's seed e_axis below)
+  auto seed_of = [&](int q) __attribute__((always_inline)) -> T {
+    if (SEED && BND && q > 0 && ((mask >> q) & 1u) && (int)nibble(rec, q) == a.seed_group)
+      return T(a.seed_axis == 0 ? L::ex(q) : (a.seed_axis == 1 ? L::ey(q) : L::ez(q)));
+    return T(0);
+  };
+
   // cotangents of the relaxed values: read where the forward step wrote them
+  // (on the last forward step they hold what the transposed interpolation
+  // pass left there, zero without walls that are not halfway)
   T mu[L::Q];
 #pragma unroll
   for (int q = 0; q < L::Q; ++q) {
-    if (SEED) {
-      // objective: sum over the links of one group of e_axis (2 d_rel + ladd);
-      // mu holds the cotangent of d_rel here, that of ladd is mu / 2
-      T s = T(0);
-      if (BND && q > 0 && ((mask >> q) & 1u) && (int)nibble(rec, q) == a.seed_group) {
-        const int ek = a.seed_axis == 0 ? L::ex(q) : (a.seed_axis == 1 ? L::ey(q) : L::ez(q));
-        s = T(2 * ek);
-      }
-      mu[q] = s;
+    const int qb = opp(q);
+    if constexpr (BND && PAR == 1) {
+      mu[q] = S::ld(pick((mask >> q) & 1u, Al.template ptr<L>(lam, qb, -1), Al.template ptr<L>(lam, q, q)));
+    } else if constexpr (PAR == 0) {
+      mu[q] = Al.template ld<L, PL>(lam, qb, -1);
     } else {
-      const int qb = opp(q);
-      if constexpr (BND && PAR == 1) {
-        mu[q] = S::ld(pick((mask >> q) & 1u, Al.template ptr<L>(lam, qb, -1), Al.template ptr<L>(lam, q, q)));
-      } else if constexpr (PAR == 0) {
-        mu[q] = Al.template ld<L, PL>(lam, qb, -1);
-      } else {
-        mu[q] = Al.template ld<L, PL>(lam, q, q);
-      }
+      mu[q] = Al.template ld<L, PL>(lam, q, q);
     }
+    if (SEED) mu[q] += T(2) * seed_of(q);
   }
 
   // forward state of this node and its body force
@@ -164,7 +165,7 @@ __device__ __forceinline__ void adj_node(const AdjArgs& a, uint32_t n, const AD&
       if ((mask >> q) & 1u) {
         const uint32_t gr = nibble(rec, q);
         const T ux = (T)a.uw[3 * gr], uy = (T)a.uw[3 * gr + 1], uz = (T)a.uw[3 * gr + 2];
-        const T muL = SEED ? T(0.5) * mu[q] : mu[q];
+        const T muL = SEED ? mu[q] - seed_of(q) : mu[q];
         const T c6 = T(-6) * (T)L::w(q) * muL;
         Mrho += c6 * edot<L>(q, ux, uy, uz);
         const T cr6 = c6 * rho;
@@ -316,6 +317,198 @@ static hipError_t launch_adj_l(int prec, int adj_prec, const AdjArgs& a, int par
 hipError_t launch_adj(int lattice, int prec, int adj_prec, const AdjArgs& a, int parity, bool seed, hipStream_t st) {
   if (lattice == 0) return launch_adj_l<D2Q9>(prec, adj_prec, a, parity, seed, st);
   return launch_adj_l<D3Q19>(prec, adj_prec, a, parity, seed, st);
+}
+
+// ---------------------------------------------------------------------------
+// Transposed interpolation pass (walls that are not halfway)
+// ---------------------------------------------------------------------------
+// With walls that are not halfway the recorded forward step is P o K: K the
+// step with every wall link halfway, P the interpolation pass after it
+// (Bouzidi, Firdaouss and Lallemand 2001), which at each listed node x
+// replaces the value returned along opp(a) by a wall link a at fraction q:
+//   q <  1/2: 2q V_a + (1 - 2q) D_a + (2q - 1) 6 w_a rho_t e_a.u_w
+//             (D_a the value that streamed into x along a; V_a unchanged
+//             when x - e_a is not a fluid node),
+//   q >= 1/2: [V_a + (2q - 1) (V_opp(a) + 6 w_opp(a) rho_t e_opp(a).u_w)] / (2q)
+//             (the last term only when opp(a) is a wall link too),
+// with V the values node x wrote, rho_t = (rho0 + sum V) / (1 - K) and
+// K = sum over the wall links of 6 w e.u_w.  Its transpose runs before each
+// k_adj, on the adjoint state in the same layout.  Pass 1 (one thread per
+// listed node) takes the cotangents of the replaced values and writes the
+// cotangents of the node's own values V in place: those slots belong to that
+// node alone.  The D_a slots are values written by the upstream node, which
+// that node's own pass-1 thread updates when it is listed too, so pass 1
+// leaves their contributions in dd1 and pass 2 adds them after it.  The
+// wall-velocity cotangents of each link (along e_q, in the link's group) are
+// accumulated per link over the steps and summed once at the end.
+// On the last forward step the objective includes the interpolated links'
+// change of the returned value, e_axis (new - V), for the links of its group.
+constexpr int IBA_THREADS = 64;
+static_assert(IBA_THREADS >= 3 * MAXG, "one thread per wall-velocity component");
+
+template <class L, int PS, int PL, int PAR>
+__global__ __launch_bounds__(IBA_THREADS) void k_ibb_adj1(const IbbAdjArgs a) {
+  using S = Stor<PL>;
+  using E = typename S::E;
+  using T = typename S::T;
+  using M = typename Stor<PS>::T;
+  __shared__ double suw[MAXG][3];
+  if (threadIdx.x < 3 * MAXG) (&suw[0][0])[threadIdx.x] = (&a.uw[0][0])[threadIdx.x];
+  __syncthreads();
+  const uint32_t i = blockIdx.x * IBA_THREADS + threadIdx.x;
+  if (i >= a.M) return;
+  const Geom& g = a.geo;
+  // every load before the first store (the stores could alias the loads as
+  // far as the compiler knows, which would serialise them)
+  double qv[L::Q], sacc[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    qv[q] = a.qf[(uint64_t)i * L::Q + q];
+    sacc[q] = a.sacc[(uint64_t)i * L::Q + q];
+  }
+  const uint32_t n = a.node[i];
+  const uint4 rec = a.nrec[i];
+  uint32_t x, y, z, r;
+  coords(g, n, x, y, z, r);
+  const AddrG Al = addr_g(g, x, y, z, r, L::Q);
+  const uint32_t mask = rec.x;
+  E* lam = (E*)a.lam;
+  const double rho = (double)((const M*)a.mac)[n];
+  double eu[L::Q];
+  double K = 0.0;
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    eu[q] = 0.0;
+    if (q > 0 && ((mask >> q) & 1u)) {
+      const uint32_t gr = nibble(rec, q);
+      eu[q] = edot<L>(q, suw[gr][0], suw[gr][1], suw[gr][2]);
+      K += 6.0 * L::w(q) * eu[q];
+    }
+  }
+  // mu: cotangents of the replaced values; out: of the values V the pass read
+  double mu[L::Q], out[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const bool wall = q > 0 && ((mask >> q) & 1u);
+    const bool wr = wall && qv[q] != 0.5;
+    const E* ptr = (PAR == 1 || wall) ? Al.template ptr<L>((const E*)lam, opp(q), -1)
+                                      : Al.template ptr<L>((const E*)lam, q, q);
+    const double v = (double)S::ld(ptr);
+    mu[q] = wr ? v : 0.0;
+    out[q] = wr ? 0.0 : v;
+    if (wr && (int)nibble(rec, q) == a.seed_group) {
+      const double ek = a.seed_axis == 0 ? L::ex(q) : (a.seed_axis == 1 ? L::ey(q) : L::ez(q));
+      mu[q] += ek;
+      out[q] -= ek;
+    }
+  }
+  double srho = 0.0;  // cotangent of rho_t
+  double s[L::Q], d1c[L::Q];
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) s[q] = d1c[q] = 0.0;
+#pragma unroll
+  for (int q = 1; q < L::Q; ++q) {
+    if (!((mask >> q) & 1u) || qv[q] == 0.5) continue;
+    const int qb = opp(q);
+    const double t2 = 2.0 * qv[q];
+    if (qv[q] < 0.5) {
+      if ((mask >> qb) & 1u) {
+        out[q] += mu[q];
+      } else {
+        out[q] += t2 * mu[q];
+        d1c[q] = (1.0 - t2) * mu[q];
+        const double c6 = (t2 - 1.0) * 6.0 * L::w(q) * mu[q];
+        srho += c6 * eu[q];
+        s[q] += c6 * rho;
+      }
+    } else {
+      const double a2 = mu[q] * (t2 - 1.0) / t2;
+      out[q] += mu[q] / t2;
+      out[qb] += a2;
+      if ((mask >> qb) & 1u) {
+        const double c6 = a2 * 6.0 * L::w(qb);
+        srho += c6 * eu[qb];
+        s[qb] += c6 * rho;
+      }
+    }
+  }
+  // rho_t: through every V, and through K to the wall velocities
+  const double sr = srho / (1.0 - K);
+#pragma unroll
+  for (int q = 0; q < L::Q; ++q) {
+    const bool wall = q > 0 && ((mask >> q) & 1u);
+    E* ptr = (PAR == 1 || wall) ? Al.template ptr<L>(lam, opp(q), -1) : Al.template ptr<L>(lam, q, q);
+    S::st(ptr, (T)(out[q] + sr));
+    if (wall) s[q] += sr * rho * 6.0 * L::w(q);
+    a.dd1[(uint64_t)i * L::Q + q] = d1c[q];
+    a.sacc[(uint64_t)i * L::Q + q] = sacc[q] + s[q];  // 0 for links that are not wall links
+  }
+}
+
+template <class L, int PL, int PAR>
+__global__ __launch_bounds__(IBA_THREADS) void k_ibb_adj2(const IbbAdjArgs a) {
+  using S = Stor<PL>;
+  using E = typename S::E;
+  using T = typename S::T;
+  const uint32_t i = blockIdx.x * IBA_THREADS + threadIdx.x;
+  if (i >= a.M) return;
+  const Geom& g = a.geo;
+  const uint32_t n = a.node[i];
+  const uint32_t mask = a.nrec[i].x;
+  uint32_t x, y, z, r;
+  coords(g, n, x, y, z, r);
+  const AddrG Al = addr_g(g, x, y, z, r, L::Q);
+  E* lam = (E*)a.lam;
+  // loads first, then the stores (as in pass 1)
+  double v[L::Q], d[L::Q];
+  uint32_t sel = 0;  // links with q < 1/2 and a fluid node behind
+#pragma unroll
+  for (int q = 1; q < L::Q; ++q) {
+    const int qb = opp(q);
+    d[q] = a.dd1[(uint64_t)i * L::Q + q];
+    v[q] = 0.0;
+    if (!((mask >> q) & 1u) || ((mask >> qb) & 1u) || !(a.qf[(uint64_t)i * L::Q + q] < 0.5)) continue;
+    sel |= 1u << q;
+    // where the next step reads the value streamed into x along q
+    v[q] = (double)S::ld(PAR == 0 ? Al.template ptr<L>(lam, q, -1) : Al.template ptr<L>(lam, qb, qb));
+  }
+#pragma unroll
+  for (int q = 1; q < L::Q; ++q) {
+    const int qb = opp(q);
+    if ((sel >> q) & 1u)
+      S::st(PAR == 0 ? Al.template ptr<L>(lam, q, -1) : Al.template ptr<L>(lam, qb, qb), (T)(v[q] + d[q]));
+  }
+}
+
+template <class L, int PS, int PL>
+static void launch_ibb_adj_t(const IbbAdjArgs& a, hipStream_t st) {
+  const uint32_t nb = (a.M + IBA_THREADS - 1) / IBA_THREADS;
+  if (a.parity == 0) {
+    k_ibb_adj1<L, PS, PL, 0><<<nb, IBA_THREADS, 0, st>>>(a);
+    k_ibb_adj2<L, PL, 0><<<nb, IBA_THREADS, 0, st>>>(a);
+  } else {
+    k_ibb_adj1<L, PS, PL, 1><<<nb, IBA_THREADS, 0, st>>>(a);
+    k_ibb_adj2<L, PL, 1><<<nb, IBA_THREADS, 0, st>>>(a);
+  }
+}
+
+template <class L>
+static hipError_t launch_ibb_adj_l(int prec, int adj_prec, const IbbAdjArgs& a, hipStream_t st) {
+  if (prec == S_F64 && adj_prec == S_F64)
+    launch_ibb_adj_t<L, S_F64, S_F64>(a, st);
+  else if (prec == S_F32 && adj_prec == S_F64)
+    launch_ibb_adj_t<L, S_F32, S_F64>(a, st);
+  else if (prec == S_F32 && adj_prec == S_F32)
+    launch_ibb_adj_t<L, S_F32, S_F32>(a, st);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_ibb_adj(int lattice, int prec, int adj_prec, const IbbAdjArgs& a, hipStream_t st) {
+  if (a.M == 0) return hipSuccess;
+  if (lattice == 0) return launch_ibb_adj_l<D2Q9>(prec, adj_prec, a, st);
+  return launch_ibb_adj_l<D3Q19>(prec, adj_prec, a, st);
 }
 
 }  // namespace lbm

@@ -131,6 +131,22 @@ struct IbbArgs {
   int parity;              // parity of the next step
 };
 
+// Transposed interpolation pass of the adjoint (walls that are not halfway).
+struct IbbAdjArgs {
+  void* lam;               // adjoint state, type and layout of AdjArgs::lam
+  const void* mac;         // [4][N] rho, U of the forward step being reversed (rho read)
+  const uint32_t* node;    // [M] node index
+  const double* qf;        // [M][Q] wall distance / link length
+  const uint4* nrec;       // [M] boundary record of each listed node
+  double* dd1;             // [M][Q] cotangents of the streamed values the q < 1/2 links read
+  double* sacc;            // [M][Q] wall-velocity cotangent of each link along e_q, accumulated
+  double uw[MAXG][3];      // wall velocities / c
+  uint32_t M;
+  Geom geo;
+  int parity;              // parity of the step after the reversed one (that of the forward pass)
+  int seed_group, seed_axis;  // objective on the last forward step; seed_group < 0 on the others
+};
+
 // Half-step distribution of the last step (Section 5, Eq. 27).
 struct HalfArgs {
   const void* f;        // state at t + dt, in the layout the next step reads

@@ -30,6 +30,7 @@ hipError_t launch_ibb(int lattice, int prec, const IbbArgs& a, hipStream_t st);
 hipError_t launch_ibb_reduce(int lattice, const double* delta, const uint8_t* grp, uint32_t M, int G, double* part,
                              double* out, hipStream_t st);
 hipError_t launch_adj(int lattice, int prec, int adj_prec, const AdjArgs& a, int parity, bool seed, hipStream_t st);
+hipError_t launch_ibb_adj(int lattice, int prec, int adj_prec, const IbbAdjArgs& a, hipStream_t st);
 }  // namespace lbm
 
 using namespace lbm;
@@ -160,6 +161,7 @@ struct lbm_ctx {
   // adjoint: the recorded forward run (checkpoints every tape_K steps) and
   // the buffers of the backward pass
   DevBuf ckpt, replay, lam, mac, adjpart, adjred;
+  DevBuf ibb_dd1, ibb_sacc;  // [nibb][Q] transposed interpolation pass (walls that are not halfway)
   bool tape = false;
   int adj_prec = S_F64;  // precision of the adjoint state and arithmetic
   int tape_T = 0, tape_K = 0, tape_group = 0, tape_axis = 0, tape_par0 = 0;
@@ -966,7 +968,9 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
   const int par0 = h->parity;
   if (timing) HIPCHK(hipEventRecord(h->ev[0], h->stream));
   a.ibq = h->nibb ? (const double*)h->ibb_q.p : nullptr;
-  const bool in_step = h->nibb && !tape && !hist &&
+  // (a recorded run keeps the pass after every step: its checkpoints then
+  // hold whole states, and the adjoint reverses the pass step by step)
+  const bool in_step = h->nibb && !tape && !hist && ckpt_every == 0 &&
                        step_interpolates_in_step(h->lattice, h->prec, mhd_mode(h), a.geo);
   a.st_c2 = (float)(h->c * h->c);
   a.st_hdt = (float)(1.5 / h->dt);
@@ -1362,7 +1366,6 @@ long lbm_link_count(lbm_ctx* h, int group) {
 }
 
 static int adjoint_supported(lbm_ctx* h) {
-  if (h->nibb) return fail(LBM_EINVAL, "the adjoint covers halfway walls only");
   if (h->prec != S_F32 && h->prec != S_F64) return fail(LBM_EINVAL, "the adjoint needs F32 or F64 storage");
   if (h->mhd) return fail(LBM_EINVAL, "the adjoint does not cover the MHD equilibrium");
   if (h->cs > 0) return fail(LBM_EINVAL, "the adjoint does not cover the Smagorinsky closure");
@@ -1426,6 +1429,28 @@ int lbm_adjoint_backward(lbm_ctx* h, double gJ, void* grad_a_dev, int grad_f64, 
   const size_t gbytes = (size_t)3 * h->N * (grad_f64 ? sizeof(double) : sizeof(float));
   if (grad_a_dev) HIPCHK(hipMemsetAsync(grad_a_dev, 0, gbytes, h->stream));
   HIPCHK(hipMemsetAsync(h->adjpart.p, 0, (size_t)h->ntiles * NPART * sizeof(double), h->stream));
+  // the objective's step adds its seed to what the adjoint state holds
+  HIPCHK(hipMemsetAsync(h->lam.p, 0, (size_t)h->Q * h->N * elem_bytes(ap), h->stream));
+  const size_t ibytes = (size_t)h->nibb * h->Q * sizeof(double);
+  IbbArgs ib = {};
+  IbbAdjArgs ia = {};
+  if (h->nibb) {
+    HIPCHK(h->ibb_dd1.ensure(ibytes));
+    HIPCHK(h->ibb_sacc.ensure(ibytes));
+    HIPCHK(hipMemsetAsync(h->ibb_sacc.p, 0, ibytes, h->stream));
+    ib.f = h->replay.p;
+    ib.node = ia.node = (const uint32_t*)h->ibb_node.p;
+    ib.qf = ia.qf = (const double*)h->ibb_q.p;
+    ib.grp = (const uint8_t*)h->ibb_grp.p;
+    ib.nrec = ia.nrec = (const uint4*)h->ibb_rec.p;
+    for (int gr = 0; gr < MAXG; ++gr)
+      for (int k = 0; k < 3; ++k) ib.uw[gr][k] = ia.uw[gr][k] = h->uw[gr][k] / h->c;
+    ib.M = ia.M = h->nibb;
+    ia.lam = h->lam.p;
+    ia.dd1 = (double*)h->ibb_dd1.p;
+    ia.sacc = (double*)h->ibb_sacc.p;
+    ia.seed_axis = h->tape_axis;
+  }
   const double fscale = vol(h) * h->c / h->dt;  // force units of the unit-seed objective
   StepArgs sa = step_args(h);
   sa.f = h->replay.p;
@@ -1444,6 +1469,8 @@ int lbm_adjoint_backward(lbm_ctx* h, double gJ, void* grad_a_dev, int grad_f64, 
   aa.seed_axis = h->tape_axis;
   aa.geo = sa.geo;
   aa.p = sa.p;
+  ib.geo = ia.geo = sa.geo;
+  ib.p = sa.p;
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int t0 = K > 0 ? seg * K : 0, t1 = K > 0 ? std::min(T, t0 + K) : T;
     if (K > 0) {
@@ -1453,11 +1480,21 @@ int lbm_adjoint_backward(lbm_ctx* h, double gJ, void* grad_a_dev, int grad_f64, 
       for (int t = t0; t < t1; ++t) {
         sa.mac = (char*)h->mac.p + (size_t)(t - t0) * mbytes;
         HIPCHK(launch_step_mac(h->lattice, h->prec, sa, (h->tape_par0 + t) & 1, false, h->stream));
+        if (h->nibb) {
+          ib.parity = ((h->tape_par0 + t) & 1) ^ 1;
+          HIPCHK(launch_ibb(h->lattice, h->prec, ib, h->stream));
+        }
       }
     }
-    // then reverse its steps
+    // then reverse its steps (the interpolation pass first, then the step)
     for (int t = t1 - 1; t >= t0; --t) {
       aa.mac = (const char*)h->mac.p + (size_t)(t - t0) * mbytes;
+      if (h->nibb) {
+        ia.mac = aa.mac;
+        ia.parity = ((h->tape_par0 + t) & 1) ^ 1;
+        ia.seed_group = t == T - 1 ? h->tape_group : -1;
+        HIPCHK(launch_ibb_adj(h->lattice, h->prec, ap, ia, h->stream));
+      }
       HIPCHK(launch_adj(h->lattice, h->prec, ap, aa, (h->tape_par0 + t) & 1, t == T - 1, h->stream));
     }
   }
@@ -1465,11 +1502,20 @@ int lbm_adjoint_backward(lbm_ctx* h, double gJ, void* grad_a_dev, int grad_f64, 
   HIPCHK(launch_reduce((const double*)h->adjpart.p, (const uint32_t*)h->wlist.p, h->ntiles, 0, h->G, NBAL + MAXG * NWALL,
                        (double*)h->adjred.p, h->stream));
   HIPCHK(hipMemcpyAsync(hr, h->adjred.p, (NBAL + MAXG * NWALL) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  // the interpolation pass's wall-velocity cotangents, per link along e_q
+  double* ir = hr + NBAL + MAXG * NWALL;
+  if (h->nibb) {
+    HIPCHK(launch_ibb_reduce(h->lattice, (const double*)h->ibb_sacc.p, (const uint8_t*)h->ibb_grp.p, h->nibb, h->G,
+                             (double*)h->ibb_part.p, (double*)h->ibb_red.p, h->stream));
+    HIPCHK(hipMemcpyAsync(ir, h->ibb_red.p, (size_t)h->G * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  }
   HIPCHK(hipStreamSynchronize(h->stream));
   if (grad_uw) {
     const double su = gJ * fscale / h->c;
     for (int gr = 0; gr < h->G; ++gr)
-      for (int k = 0; k < 3; ++k) grad_uw[3 * gr + k] = k < h->D ? su * hr[NBAL + gr * NWALL + k] : 0.0;
+      for (int k = 0; k < 3; ++k)
+        grad_uw[3 * gr + k] =
+            k < h->D ? su * (hr[NBAL + gr * NWALL + k] + (h->nibb ? ir[gr * 4 + k] : 0.0)) : 0.0;
   }
   return LBM_OK;
 }

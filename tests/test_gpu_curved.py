@@ -304,7 +304,7 @@ def test_link_fraction_errors(lbm):
     g.init_equilibrium()
     g.step(2)
     with pytest.raises(lbm.LBMError):
-        g.adjoint_forward(4, 2, 0, 0)
+        g.set_wall_force_history(True)
     with pytest.raises(lbm.LBMError):
         g.set_link_fractions(q)  # set-up only
 

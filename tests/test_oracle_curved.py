@@ -195,3 +195,41 @@ def test_offset_couette_in_an_aligned_field_is_exact(lorentz):
     nu = (tau - 0.5) / 3
     assert abs(magn[0, 0, 0] - nu * U / (n - 1 + qb + qt)) < 1e-10 * nu * U
     np.testing.assert_allclose(magn[:, 2, :], hydro[:, 0, :], rtol=1e-12, atol=1e-15)
+
+
+def test_complex_step_derivative_through_interpolated_walls_equals_central_differences():
+    """The complex-step build differentiates the interpolated forward steps
+    (the reference for the GPU adjoint with such walls): its derivatives of
+    the wall force of a moving curved body, along a body-force direction and
+    along each component of that body's velocity, against central
+    differences of the double build."""
+    w = W.duct_sphere(nx=14, ny=12, nz=12, r=3.3, uw=0.01, a=1e-4)
+    w.curved = True
+    w.wall_velocity = ((1, 0.01, 0.0, 0.0), (4, 0.004, -0.003, 0.002))
+    a0 = W.force_field(w.nx, w.ny, w.nz, base=w.body_force, amp=0.3, seed=5)
+    r = W.direction(a0.shape, 6)
+    T, H = 7, 1e-30
+
+    def J(field, uw4=(0.004, -0.003, 0.002), cs=False, da=None, du=None):
+        o = make_oracle(w, complex_step=cs, init=False)
+        o.init_equilibrium()
+        o.set_body_force_field(field, None if da is None else H * da)
+        o.set_wall_velocity(4, list(uw4), None if du is None else H * np.asarray(du, dtype=float))
+        o.step(T)
+        if cs:
+            re, im = o.wall_force(imag=True)
+            return re[4, 0, 0], im[4, 0, 0] / H
+        return o.wall_force()[4, 0, 0]
+
+    J0, dJ = J(a0, cs=True, da=r)
+    assert abs(J0 - J(a0)) <= 1e-14 * abs(J0)
+    h = 1e-4 * np.abs(a0).max()
+    fd = (J(a0 + h * r) - J(a0 - h * r)) / (2 * h)
+    assert abs(dJ - fd) <= 1e-6 * abs(fd), (dJ, fd)
+    u = np.array([0.004, -0.003, 0.002])
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = 1.0
+        _, dJu = J(a0, cs=True, du=e)
+        fdu = (J(a0, u + 1e-5 * e) - J(a0, u - 1e-5 * e)) / 2e-5
+        assert abs(dJu - fdu) <= 1e-6 * abs(fdu), (k, dJu, fdu)
