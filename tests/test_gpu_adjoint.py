@@ -12,7 +12,7 @@ import sys
 import numpy as np
 import pytest
 
-from helpers import make_oracle, rel_inf
+from helpers import check_targets, make_oracle, rel_inf
 from paper_2512_12213_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -206,10 +206,13 @@ def test_full_size_fp32_adjoint_vs_fp64_finite_differences(env):
     per-node field, moving top wall, 400 steps, checkpoints every 40, FP32
     storage: the gradient along a seeded field direction and the top wall's
     velocity gradient (3 components) against central differences of the FP64
-    oracle.  Steps: 1e-3 of the field's max along the direction; 1e-4 on the
-    wall velocity (1e-3 leaves a truncation error of 8.5e-5 in the normal
-    component, where the transpiration response is strongly nonlinear; the
-    FP64 GPU adjoint agrees with h = 1e-4 differences to 2e-8)."""
+    oracle.  Steps: 1e-3 of the field's max along the direction; on the
+    wall velocity both 1e-3 and 1e-4, each component to 1e-4 (the normal
+    component, where the transpiration response is strongly nonlinear,
+    carries a truncation error of 8.5e-5 at 1e-3).  The FP32 adjoint state
+    meets 1e-4 on the field gradient; its wall-velocity gradient is a
+    recorded miss (small anisotropic parts of the adjoint state rounded
+    away), held to its recorded bounds."""
     import oracle
     w = W.duct_sphere()
     T, K = w.steps, 40
@@ -235,13 +238,15 @@ def test_full_size_fp32_adjoint_vs_fp64_finite_differences(env):
     J64 = Jo(a32)
     fd = (Jo(a32 + h * r) - Jo(a32 - h * r)) / (2 * h)
     fdu = np.zeros(3)
+    fdu3 = np.zeros(3)
     for k in range(3):
-        say("oracle wall-velocity difference", k)
-        up = np.array([0.01, 0.0, 0.0])
-        um = up.copy()
-        up[k] += 1e-4
-        um[k] -= 1e-4
-        fdu[k] = (Jo(a32, up) - Jo(a32, um)) / 2e-4
+        say("oracle wall-velocity differences", k)
+        for hu, out in ((1e-4, fdu), (1e-3, fdu3)):
+            up = np.array([0.01, 0.0, 0.0])
+            um = up.copy()
+            up[k] += hu
+            um[k] -= hu
+            out[k] = (Jo(a32, up) - Jo(a32, um)) / (2 * hu)
     dg, dg32 = float(np.sum(ga * r)), float(np.sum(ga32 * r))
     e_u = np.linalg.norm(gu[1] - fdu) / np.linalg.norm(fdu)
     e_u32 = np.linalg.norm(gu32[1] - fdu) / np.linalg.norm(fdu)
@@ -250,9 +255,18 @@ def test_full_size_fp32_adjoint_vs_fp64_finite_differences(env):
         % (dg, fd, abs(dg - fd) / abs(fd), e_u, np.abs(gu[1] - fdu) / np.abs(fdu)))
     say("FP32 adjoint state: field %.2e; top-wall velocity gradient %.2e, per component %s"
         % (abs(dg32 - fd) / abs(fd), e_u32, np.abs(gu32[1] - fdu) / np.abs(fdu)))
-    say("FD wall-velocity gradient", fdu)
+    say("FD wall-velocity gradient", fdu, "(h = 1e-3:", fdu3, ")")
+    pc = np.abs(gu[1] - fdu) / np.abs(fdu)
+    pc3 = np.abs(gu[1] - fdu3) / np.abs(fdu3)
+    pc32 = np.abs(gu32[1] - fdu) / np.abs(fdu)
+    say("per component against h = 1e-3 differences: %s" % pc3)
     assert abs(J - J64) <= 1e-4 * abs(J64)
     assert abs(dg - fd) <= 1e-4 * abs(fd)
     assert e_u <= 1e-4
-    # the FP32 adjoint state meets the target on the field gradient only
+    assert (pc <= 1e-4).all() and (pc3 <= 1e-4).all()
+    # the FP32 adjoint state meets the target on the field gradient ...
     assert abs(dg32 - fd) <= 1e-4 * abs(fd)
+    # ... not on the wall-velocity gradient (recorded, with its bounds)
+    errs = {"uw_norm": e_u32, "uw_x": pc32[0], "uw_y": pc32[1], "uw_z": pc32[2]}
+    check_targets(errs, 1e-4, misses={"uw_norm": 3e-4, "uw_x": 3e-2, "uw_y": 3e-4, "uw_z": 1.2e-3},
+                  what="FP32 adjoint state, top-wall velocity gradient")
