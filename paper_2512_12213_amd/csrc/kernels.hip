@@ -759,7 +759,10 @@ template <class L, int P, int MHD, int PAR, int DG, int RU, bool MAC = false, bo
 __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   using T = typename Stor<P>::T;
   const Geom& g = a.geo;
-  const uint32_t tile = PAR == 1 ? xcd_tile(blockIdx.x, gridDim.x, g.nx) : blockIdx.x;
+  // tiles with boundary rows (slower) first, so that they do not form the
+  // tail of the launch; the XCD-aware order of odd steps otherwise
+  const uint32_t tile =
+      a.tperm ? a.tperm[blockIdx.x] : (PAR == 1 ? xcd_tile(blockIdx.x, gridDim.x, g.nx) : blockIdx.x);
   const uint32_t n = tile * NTHREADS + threadIdx.x;
   const bool active = n < g.N;
   T bal[NBAL];

@@ -141,6 +141,8 @@ struct lbm_ctx {
   bool hist_on = false;
   uint32_t nwt = 0;
   DevBuf wtile, wlc, hist_ring, hist_out;
+  DevBuf tperm;  // launch order of the step's tiles (those with boundary rows first), when used
+  bool use_tperm = false;
   std::vector<double> hist;  // [steps of the last call][MAXG NWALL]
   long hist_steps = 0;
   // walls that are not halfway: link fractions (host, [Q][N]) and the list of
@@ -399,6 +401,26 @@ int build_geometry(lbm_ctx* h) {
   for (size_t i = MAXG + 1; i < wlist.size(); ++i)
     wlc[i] = (uint32_t)wtile[wlist[i] & 0x0FFFFFFFu] | (wlist[i] & 0xF0000000u);
   h->nwt = nwt;
+  // Launch order of the step: the tiles holding a row with boundary links
+  // first.  Used where the odd steps' XCD-aware order is the identity (rows
+  // of at most one tile), and when some but not all tiles have boundary rows.
+  {
+    std::vector<uint32_t> order, inner;
+    for (uint32_t t = 0; t < h->ntiles; ++t) {
+      const uint64_t n0 = (uint64_t)t * NTHREADS;
+      const uint64_t n1 = std::min<uint64_t>(n0 + NTHREADS, (uint64_t)h->N) - 1;
+      bool bnd = false;
+      for (uint64_t r = n0 / h->nx; r <= n1 / h->nx && !bnd; ++r) bnd = rowrec[r] >= 0;
+      (bnd ? order : inner).push_back(t);
+    }
+    const bool identity_odd = !(h->nx > NTHREADS && h->nx % NTHREADS == 0);
+    h->use_tperm = identity_odd && !order.empty() && !inner.empty();
+    if (h->use_tperm) {
+      order.insert(order.end(), inner.begin(), inner.end());
+      HIPCHK(h->tperm.ensure(order.size() * sizeof(uint32_t)));
+      HIPCHK(hipMemcpy(h->tperm.p, order.data(), order.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    }
+  }
   HIPCHK(h->wtile.ensure(wtile.size() * sizeof(int)));
   HIPCHK(hipMemcpy(h->wtile.p, wtile.data(), wtile.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(h->wlc.ensure(wlc.size() * sizeof(uint32_t)));
@@ -448,6 +470,7 @@ StepArgs step_args(lbm_ctx* h) {
   // odd steps read with plain loads (measured 3 % faster there; 4.5 %
   // slower on a 318 MB state, which partly stays in that cache)
   a.plain_loads = h->prec == S_F32 && (uint64_t)h->Q * h->N * 4 > (1ull << 30);
+  a.tperm = h->use_tperm ? (const uint32_t*)h->tperm.p : nullptr;
   a.f = h->f.p;
   a.g = h->mhd ? h->g.p : nullptr;
   a.afield = h->afield;
