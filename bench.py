@@ -483,40 +483,45 @@ def main():
     }
     if not args.no_variants:
         variants = {}
-        half = max(args.steps // 2, 10)
+        # at least 200 timed steps after 40 untimed ones: with fewer the GPU
+        # is still raising its clocks during the timed steps of the faster
+        # variants (16-bit duct: 59.2 us per launch after 10 untimed steps,
+        # 56.8 us after 40, on one box)
+        half = max(args.steps, 200)
+        vwarm = max(args.warmup, 40)
         for name, st in (("duct_f16", W.F16), ("duct_bf16", W.BF16), ("duct_f64", W.F64)):
             print("bench: variant %s" % name, file=sys.stderr, flush=True)
-            variants[name] = timed_run(lbm, torch, w, half, min(args.warmup, 10), storage=st)
+            variants[name] = timed_run(lbm, torch, w, half, vwarm, storage=st)
         print("bench: variant duct storing the stress and strain rate every step", file=sys.stderr, flush=True)
-        variants["duct_les_f32_stress_every_step"] = timed_run(lbm, torch, w, half, min(args.warmup, 10),
+        variants["duct_les_f32_stress_every_step"] = timed_run(lbm, torch, w, half, vwarm,
                                                                stress_every_step=True)
         print("bench: variant duct recording the wall force of every step", file=sys.stderr, flush=True)
-        variants["duct_les_f32_wall_force_every_step"] = timed_run(lbm, torch, w, half, min(args.warmup, 10),
+        variants["duct_les_f32_wall_force_every_step"] = timed_run(lbm, torch, w, half, vwarm,
                                                                    wall_history=True)
         print("bench: variant duct without LES", file=sys.stderr, flush=True)
         wn = W.duct_les()
         wn.les_cs = 0.0
-        variants["duct_no_les_f32"] = timed_run(lbm, torch, wn, half, min(args.warmup, 10))
+        variants["duct_no_les_f32"] = timed_run(lbm, torch, wn, half, vwarm)
         print("bench: variant large duct (beyond the last-level cache)", file=sys.stderr, flush=True)
         variants["duct_les_f32_512x256x256"] = timed_run(lbm, torch, W.duct_les(nx=512, ny=256, nz=256), 60, 5)
         print("bench: variant duct with the Stokes equilibrium and porous resistance", file=sys.stderr, flush=True)
         wsd = W.duct_les()
         wsd.stokes, wsd.darcy = True, 1e-4
-        variants["duct_stokes_darcy_f32"] = timed_run(lbm, torch, wsd, half, min(args.warmup, 10))
+        variants["duct_stokes_darcy_f32"] = timed_run(lbm, torch, wsd, half, vwarm)
         print("bench: variant hartmann duct", file=sys.stderr, flush=True)
-        variants["hartmann_duct_f32_192x96x96"] = timed_run(lbm, torch, W.hartmann_duct(), half, 10)
+        variants["hartmann_duct_f32_192x96x96"] = timed_run(lbm, torch, W.hartmann_duct(), half, vwarm)
         print("bench: variant hartmann duct, Lorentz-force coupling", file=sys.stderr, flush=True)
         hl = W.hartmann_duct()
         hl.lorentz = True
-        variants["hartmann_duct_lorentz_f32_192x96x96"] = timed_run(lbm, torch, hl, half, 10)
+        variants["hartmann_duct_lorentz_f32_192x96x96"] = timed_run(lbm, torch, hl, half, vwarm)
         print("bench: variant 2D hartmann channel", file=sys.stderr, flush=True)
         variants["hartmann_channel_d2q9_f32_4096x2048"] = timed_run(
-            lbm, torch, W.hartmann_channel(nx=4096, ny=2048, storage=W.F32), half, 10)
+            lbm, torch, W.hartmann_channel(nx=4096, ny=2048, storage=W.F32), half, vwarm)
         for curved in (False, True):
             print("bench: variant duct with sphere, curved %d" % curved, file=sys.stderr, flush=True)
             ws = W.duct_sphere()
             ws.curved = curved
-            variants["duct_sphere_%sf32_128x64x64" % ("curved_" if curved else "")] = timed_run(lbm, torch, ws, half, 10)
+            variants["duct_sphere_%sf32_128x64x64" % ("curved_" if curved else "")] = timed_run(lbm, torch, ws, half, vwarm)
         print("bench: variant couette cylinder", file=sys.stderr, flush=True)
         variants["couette_cylinder_f32_512x128"] = timed_run(lbm, torch, W.couette_cylinder(), 2000, 100)
         print("bench: variant poiseuille", file=sys.stderr, flush=True)
