@@ -760,9 +760,10 @@ __global__ __launch_bounds__(NTHREADS) void k_step(const StepArgs a) {
   using T = typename Stor<P>::T;
   const Geom& g = a.geo;
   // tiles with boundary rows (slower) first, so that they do not form the
-  // tail of the launch; the XCD-aware order of odd steps otherwise
-  const uint32_t tile =
-      a.tperm ? a.tperm[blockIdx.x] : (PAR == 1 ? xcd_tile(blockIdx.x, gridDim.x, g.nx) : blockIdx.x);
+  // tail of the launch (the host's order, one per parity, the odd one
+  // XCD-aware); else the XCD-aware order of odd steps
+  const uint32_t tile = a.tperm ? a.tperm[(PAR == 1 ? gridDim.x : 0u) + blockIdx.x]
+                                : (PAR == 1 ? xcd_tile(blockIdx.x, gridDim.x, g.nx) : blockIdx.x);
   const uint32_t n = tile * NTHREADS + threadIdx.x;
   const bool active = n < g.N;
   T bal[NBAL];

@@ -68,7 +68,7 @@ struct StepArgs {
   int ibb_in;              // the state holds 2q f_rel + ladd at their q < 1/2 links: complete it at the read
   int ibb_out;             // interpolate at their links in the step (q < 1/2: the part known at x)
   int plain_loads;         // FP32 odd steps read interior rows with plain (cached) loads
-  const uint32_t* tperm;   // [ntiles] tile of each workgroup (tiles with boundary rows first), or null
+  const uint32_t* tperm;   // [2][ntiles] tile of each workgroup, even / odd steps (boundary rows first), or null
   Geom geo;
   Phys p;
 };
