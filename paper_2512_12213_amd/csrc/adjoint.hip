@@ -221,8 +221,11 @@ template <class L, int PS, int PL, int PAR, bool SEED, bool RU>
 __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_adj(const AdjArgs a) {
   using T = typename Stor<PL>::T;
   const Geom& g = a.geo;
-  const uint32_t n = blockIdx.x * NTHREADS + threadIdx.x;
-  const uint32_t bgrp = a.blkgrp[blockIdx.x];
+  // tiles with boundary rows (slower) first, so that they do not form the
+  // tail of the launch
+  const uint32_t tile = a.tperm ? a.tperm[blockIdx.x] : blockIdx.x;
+  const uint32_t n = tile * NTHREADS + threadIdx.x;
+  const uint32_t bgrp = a.blkgrp[tile];
   // wall-velocity cotangents of this thread's links, in its own column of
   // LDS (FP64; no barrier: a thread touches only its column) rather than in
   // twelve registers held through the whole node update
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) v
       v[s * NWALL + 2] = pu[(3 * s + 2) * NTHREADS];
       v[s * NWALL + 3] = 0.0;
     }
-    tile_sum_store<MAXBG * NWALL, true>(v, a.part + (uint64_t)NBAL * gridDim.x + blockIdx.x, gridDim.x);
+    tile_sum_store<MAXBG * NWALL, true>(v, a.part + (uint64_t)NBAL * gridDim.x + tile, gridDim.x);
   }
 }
 

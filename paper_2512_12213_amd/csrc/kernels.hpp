@@ -87,6 +87,7 @@ struct AdjArgs {
   double ga_scale;         // factor from the node's force cotangent to grad_a
   int grad_f64;
   int seed_group, seed_axis;  // objective (last forward step only)
+  const uint32_t* tperm;   // [ntiles] tile of each workgroup (tiles with boundary rows first), or null
   Geom geo;
   Phys p;
 };

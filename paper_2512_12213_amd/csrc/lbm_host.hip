@@ -1506,6 +1506,7 @@ int lbm_adjoint_backward(lbm_ctx* h, double gJ, void* grad_a_dev, int grad_f64, 
   aa.ga_scale = gJ * fscale * h->dt / h->c;
   aa.seed_group = h->tape_group;
   aa.seed_axis = h->tape_axis;
+  aa.tperm = h->use_tperm ? (const uint32_t*)h->tperm.p : nullptr;  // the even steps' order
   aa.geo = sa.geo;
   aa.p = sa.p;
   ib.geo = ia.geo = sa.geo;
