@@ -1559,7 +1559,15 @@ static hipError_t launch_step_mac_t(const StepArgs& a, int parity, bool diag, hi
   const uint32_t nb = (a.geo.N + NTHREADS - 1) / NTHREADS;
   const bool ru = a.geo.nx % 64 == 0;
 #define LBM_MAC(PAR, DG, RU) k_step<L, P, 0, PAR, DG, RU, true><<<nb, NTHREADS, 0, st>>>(a)
-  if (ru) {
+  if (buffer_form<L, P, 0>(a.geo)) {
+    // buffer addressing of rows without boundary links, as the plain steps
+    // (the same arithmetic: bit-identical states)
+    if (parity == 0) {
+      if (diag) LBM_MAC(0, 2, 2); else LBM_MAC(0, 0, 2);
+    } else {
+      if (diag) LBM_MAC(1, 2, 2); else LBM_MAC(1, 0, 2);
+    }
+  } else if (ru) {
     if (parity == 0) {
       if (diag) LBM_MAC(0, 2, 1); else LBM_MAC(0, 0, 1);
     } else {
