@@ -106,8 +106,8 @@ int lbm_add_solid_mask(lbm_ctx* ctx, const unsigned char* mask_host, int group);
  * half a link from the fluid node), each wall link keeps its Maxwell-stress
  * correction, and the pass runs after every step.  A run recorded by
  * lbm_adjoint_forward also runs the pass after every step, and its adjoint
- * reverses it.  Not with the per-step wall-force record (LBM_EINVAL).
- * Set-up only. */
+ * reverses it; so does a call with the per-step wall-force record, whose
+ * every step then includes the interpolated links' changes.  Set-up only. */
 int lbm_set_link_fractions(lbm_ctx* ctx, const double* q_host);
 
 /* Wall velocity of a group (moving-wall bounce-back adds
@@ -296,10 +296,13 @@ int lbm_wall_force(lbm_ctx* ctx, double* out);
  * of the most recent such call in order, the four variants of lbm_wall_force:
  * out[n][G][4][3], G = lbm_num_groups, n = min(steps of that call,
  * max_steps), written to *nsteps.  The last entry equals lbm_wall_force.
- * Halfway walls only (LBM_EINVAL with lbm_set_link_fractions); not recorded by
+ * With walls that are not halfway (lbm_set_link_fractions) the interpolation
+ * runs as a pass after every step of such a call, and each step's record
+ * includes its interpolated links' changes.  Not recorded by
  * lbm_step_noalloc (LBM_EINVAL while on) or lbm_adjoint_forward.  Device
- * buffers of about 64 bytes per such tile and recorded step are allocated on
- * the first call.  LBM_ESTATE when no call has recorded it since the state
+ * buffers of about 64 bytes per such tile and recorded step (and 128 bytes
+ * per recorded step with interpolated links) are allocated on the first
+ * call.  LBM_ESTATE when no call has recorded it since the state
  * was set. */
 int lbm_set_wall_force_history(lbm_ctx* ctx, int on);
 int lbm_wall_force_history(lbm_ctx* ctx, double* out, int max_steps, int* nsteps);

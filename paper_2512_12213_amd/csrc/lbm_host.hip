@@ -150,6 +150,7 @@ struct lbm_ctx {
   std::vector<double> qlink;
   DevBuf ibb_node, ibb_rec, ibb_q, ibb_grp, ibb_delta, ibb_part, ibb_red;
   DevBuf ibb_half;  // [nibb][Q] halfway values of the last step (half-step distribution)
+  DevBuf ibb_hist;  // [steps - 1][MAXG][4] interpolated links' force changes of each step (per-step record)
   uint32_t nibb = 0;
   double* hred = nullptr;  // pinned [NBAL + MAXG * NWALL]
   void* scratch = nullptr;  // this device's fixed scratch array (lbm_step_noalloc), or null
@@ -980,6 +981,7 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
   if (hist) {
     HIPCHK(h->hist_ring.ensure((size_t)ring * slot * sizeof(double)));
     HIPCHK(h->hist_out.ensure((size_t)std::max(n - 1, 1) * MAXG * NWALL * sizeof(double)));
+    if (h->nibb) HIPCHK(h->ibb_hist.ensure((size_t)std::max(n - 1, 1) * MAXG * 4 * sizeof(double)));
   }
   int chunk0 = 0;  // first step of the ring's current chunk
   const size_t mbytes = (size_t)4 * h->N * elem_bytes(h->prec);
@@ -1043,9 +1045,13 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
     }
     if (h->nibb && (diag || !in_step)) {
       ib.parity = h->parity ^ 1;
-      ib.delta = diag ? sc.ibb_delta : nullptr;
+      ib.delta = (diag || hist) ? sc.ibb_delta : nullptr;
       ib.half = diag ? (double*)h->ibb_half.p : nullptr;
       HIPCHK(launch_ibb(h->lattice, h->prec, ib, h->stream));
+      if (hist && !diag)
+        // this step's changes of the returning values, for its record
+        HIPCHK(launch_ibb_reduce(h->lattice, sc.ibb_delta, (const uint8_t*)h->ibb_grp.p, h->nibb, h->G, sc.ibb_part,
+                                 (double*)h->ibb_hist.p + (size_t)i * MAXG * 4, h->stream));
     }
     if (timing) HIPCHK(hipEventRecord(h->ev[i + 1], h->stream));
     h->parity ^= 1;
@@ -1097,6 +1103,15 @@ static int step_loop(lbm_ctx* h, int n, int ckpt_every, void* tape = nullptr, co
     if (n > 1)
       HIPCHK(hipMemcpy(h->hist.data(), h->hist_out.p, (size_t)(n - 1) * MAXG * NWALL * sizeof(double),
                        hipMemcpyDeviceToHost));
+    if (n > 1 && h->nibb) {
+      // interpolated links: each step's changes of the returning values
+      std::vector<double> ih((size_t)(n - 1) * MAXG * 4);
+      HIPCHK(hipMemcpy(ih.data(), h->ibb_hist.p, ih.size() * sizeof(double), hipMemcpyDeviceToHost));
+      for (int st = 0; st < n - 1; ++st)
+        for (int gr = 0; gr < h->G; ++gr)
+          for (int k = 0; k < NWALL; ++k)
+            h->hist[((size_t)st * MAXG + gr) * NWALL + k] += ih[((size_t)st * MAXG + gr) * 4 + k];
+    }
     std::memcpy(h->hist.data() + (size_t)(n - 1) * MAXG * NWALL, h->last + NBAL, MAXG * NWALL * sizeof(double));
     h->hist_steps = n;
   } else {
@@ -1313,7 +1328,6 @@ int lbm_set_wall_force_history(lbm_ctx* h, int on) {
     int rc = build_geometry(h);
     if (rc) return rc;
   }
-  if (on && h->nibb) return fail(LBM_EINVAL, "the per-step wall-force history covers halfway walls only");
   h->hist_on = on != 0;
   return LBM_OK;
 }

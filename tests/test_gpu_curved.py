@@ -304,7 +304,5 @@ def test_link_fraction_errors(lbm):
     g.init_equilibrium()
     g.step(2)
     with pytest.raises(lbm.LBMError):
-        g.set_wall_force_history(True)
-    with pytest.raises(lbm.LBMError):
         g.set_link_fractions(q)  # set-up only
 

@@ -309,14 +309,46 @@ def test_wall_force_history_of_a_long_call_equals_one_step_calls(env):
     a.step_noalloc(1)
 
 
-def test_wall_force_history_refuses_walls_that_are_not_halfway(env):
+@pytest.mark.parametrize("storage", [W.F64, W.F32])
+def test_wall_force_history_with_walls_that_are_not_halfway(env, storage):
+    """Duct with a moving curved sphere (links at their wall distance), a
+    moving plane wall: a 6-step call with the history on (the interpolation
+    runs as a pass after every step), every step's record against the
+    oracle's wall force after that step (2-norm per group and variant;
+    FP64 1e-12, FP32 1e-4); the last entry equals lbm_wall_force."""
     L, torch = env
-    w = W.duct_sphere(nx=32, ny=16, nz=16, r=3.0, steps=0)
+    w = W.duct_sphere(nx=64, ny=20, nz=18, r=4.3, uw=0.01, a=1e-4, steps=0)
     w.curved = True
-    g = L.from_workload(w)
-    with pytest.raises(L.LBMError) as ei:
-        g.set_wall_force_history(True)
-    assert ei.value.code == L.LBM_EINVAL
+    w.wall_velocity = ((1, 0.01, 0.0, 0.0), (4, 0.004, -0.003, 0.002))
+    say("case wall-force history with interpolated walls", storage)
+    g = L.from_workload(w, storage=storage)
     with pytest.raises(L.LBMError) as ei:
         g.wall_force_history()
     assert ei.value.code == L.LBM_ESTATE
+    g.set_wall_force_history(True)
+    g.step(6)
+    hist = g.wall_force_history()
+    assert hist.shape[0] == 6
+    assert np.array_equal(hist[-1], g.wall_force())
+    o = make_oracle(w)
+    tol = 1e-12 if storage == W.F64 else 1e-4
+    worst = 0.0
+    G = hist.shape[1]
+    for s in range(6):
+        o.step(1)
+        fo = o.wall_force(G)
+        for k in range(G):
+            for var in range(4):
+                ref = np.linalg.norm(fo[k, var])
+                if ref > 0:
+                    worst = max(worst, np.linalg.norm(hist[s, k, var] - fo[k, var]) / ref)
+    say("  worst relative error over 6 steps: %.2e" % worst)
+    assert worst <= tol
+    # the interpolated links' share is in every step's record: the sphere's
+    # force differs from that of the same call without the record only by rounding
+    g2 = L.from_workload(w, storage=storage)
+    g2.step(3)
+    f3 = g2.wall_force()[4, 0]
+    assert np.linalg.norm(hist[2, 4, 0] - f3) <= (1e-12 if storage == W.F64 else 1e-5) * np.linalg.norm(f3)
+    g.close()
+    g2.close()
